@@ -1,0 +1,75 @@
+"""Pins of the MLP reference: gradients against central finite differences,
+the forward pass against a scalar network written with math.tanh, Adam's first
+step against its closed form, and loss reduction on a smooth target."""
+import math
+
+import numpy as np
+
+from oracle import mlp_ref
+
+
+def _data(n, d, seed=0):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, d))
+    t = np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2 % d] - 0.3 * X[:, -1]
+    return X, t
+
+
+def test_gradients_match_finite_differences():
+    d, H, n = 6, 9, 13
+    P = mlp_ref.init(d, H, seed=1)
+    for k in P:
+        P[k] = P[k] + 0.1 * np.random.default_rng(2).standard_normal(P[k].shape)
+    X, t = _data(n, d, 3)
+    y, c = mlp_ref.forward(P, X)
+    L, dy = mlp_ref.mse(y, t)
+    g = mlp_ref.backward(P, c, dy)
+    h = 1e-6
+    for k in mlp_ref.PARAM_NAMES:
+        flat = P[k].reshape(-1)
+        for idx in range(flat.size):
+            old = flat[idx]
+            flat[idx] = old + h
+            Lp = mlp_ref.mse(mlp_ref.forward(P, X)[0], t)[0]
+            flat[idx] = old - h
+            Lm = mlp_ref.mse(mlp_ref.forward(P, X)[0], t)[0]
+            flat[idx] = old
+            fd = (Lp - Lm) / (2 * h)
+            an = g[k].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (k, idx, fd, an)
+
+
+def test_forward_against_scalar_network():
+    P = {"W1": np.array([[0.7]]), "b1": np.array([-0.2]), "W2": np.array([[1.3]]), "b2": np.array([0.1]),
+         "W3": np.array([[-0.8]]), "b3": np.array([0.05])}
+    X = np.array([[0.3], [-1.1], [2.0]])
+    y, _ = mlp_ref.forward(P, X)
+    for x, yy in zip(X[:, 0], y):
+        want = -0.8 * math.tanh(1.3 * math.tanh(0.7 * x - 0.2) + 0.1) + 0.05
+        assert abs(yy - want) < 1e-15
+    # zero weights give the output bias
+    Z = {k: np.zeros_like(v) for k, v in mlp_ref.init(4, 5).items()}
+    Z["b3"] = np.array([1.25])
+    assert np.all(mlp_ref.forward(Z, np.ones((3, 4)))[0] == 1.25)
+
+
+def test_mse_definition():
+    L, dy = mlp_ref.mse(np.array([1.0, 2.0]), np.array([0.0, 4.0]))
+    assert L == 2.5 and np.array_equal(dy, np.array([1.0, -2.0]))
+
+
+def test_adam_first_step_closed_form():
+    P = {k: np.ones(3) for k in mlp_ref.PARAM_NAMES}
+    g = {k: np.array([0.5, -2.0, 1e-3]) for k in mlp_ref.PARAM_NAMES}
+    st = mlp_ref.adam_init(P)
+    mlp_ref.adam_step(P, g, st, lr=0.01, eps=1e-8)
+    want = 1.0 - 0.01 * g["W1"] / (np.abs(g["W1"]) + 1e-8)
+    for k in P:
+        assert np.allclose(P[k], want, rtol=0, atol=1e-15)
+
+
+def test_training_reduces_loss():
+    X, t = _data(256, 5, 4)
+    P = mlp_ref.init(5, 32, seed=5)
+    hist = mlp_ref.train(P, X, t, epochs=300, lr=3e-3)
+    assert hist[-1] < 0.2 * hist[0]
