@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Benchmark of the out-of-core FP64 product on one MI355X.
+
+One step is one complete out-of-core product C = alpha*A*B + beta*C: the
+partitioned pipeline of host-to-device tile copies, FP64 MFMA tile kernels and
+device-to-host C copies (every stage of the method), with A, B and C in
+page-locked host memory and device memory capped by the workload's budget.
+The reported value is end-to-end TFLOP/s, 2*M*N*K / t with t including all
+transfers (the paper's measure, Section VI).
+
+Prints ONE JSON line.  Default workload: M = N = K = 32768 (8 GiB per matrix),
+alpha = 1.5, beta = 0.5, entries uniform[-1, 1], device budget 4 GiB.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "OOC DGEMM end-to-end TFLOP/s, FP64 vs split-BF16 at equal error; link GB/s"
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="square-32768-budget-4GiB")
+    ap.add_argument("--planner", default="model", choices=["model", "paper", "mlp"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split"])
+    ap.add_argument("--slices", type=int, default=6)
+    ap.add_argument("--cpu-rows", type=int, default=128, help="rows of C the CPU reference computes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", type=int, default=1, help="time every op with HIP events in the timed steps")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the out-of-core product is "
+              f"measured per GPU, see the design notes for how it would shard", file=sys.stderr)
+        sys.exit(2)
+
+    import synth
+    from synth import workloads as W
+    import paper_1808_05056_amd as ooc
+
+    if not os.path.exists(ooc.LIB_PATH):
+        raise SystemExit("libooc.so is not built")
+    w = W.BY_NAME[args.workload]
+    planner = {"model": ooc.PLAN_MODEL, "paper": ooc.PLAN_PAPER, "mlp": ooc.PLAN_MLP}[args.planner]
+    prec = ooc.SPLIT_BF16 if args.precision == "split" else ooc.FP64
+    opts = ooc.make_opts(planner=planner, precision=prec, slices=args.slices if prec else 0)
+    popts = ooc.make_opts(planner=planner, precision=prec, slices=args.slices if prec else 0,
+                          profile=bool(args.profile))
+
+    log(f"[bench] workload {w.name}: M={w.M} N={w.N} K={w.K} budget={w.budget / 2**30:.2f} GiB; "
+        f"allocating {w.host_bytes() / 2**30:.1f} GiB page-locked host memory")
+    t0 = time.time()
+    Am = ooc.PinnedMatrix(w.M, w.K)
+    Bm = ooc.PinnedMatrix(w.K, w.N)
+    Cm = ooc.PinnedMatrix(w.M, w.N)
+    A, B, C = Am.array, Bm.array, Cm.array
+    synth.fill(A, w.spec_a())
+    synth.fill(B, w.spec_b())
+    synth.fill(C, w.spec_c())
+    log(f"[bench] inputs ready in {time.time() - t0:.1f}s")
+
+    # first call: checked against the CPU reference on sampled rows
+    st, s1 = ooc.ooc_gemm(w.alpha, A, B, w.beta, C, w.budget, opts)
+    plan = s1.plan
+    log(f"[bench] plan {plan}; first call {s1.t_total_s:.3f}s")
+    cpu = None
+    err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(0)
+        rows = np.unique(np.concatenate([[0, w.M - 1], rng.integers(0, w.M, args.cpu_rows)]))[: args.cpu_rows]
+        Cin = None
+        if w.beta != 0.0:
+            Cin = np.empty((len(rows), w.N))
+            synth.fill_rows(Cin, rows, w.spec_c())
+        tc = time.time()
+        ref, D = oracle.gemm_rows(w.alpha, A, B, w.beta, Cin, rows=rows)
+        tcpu = time.time() - tc
+        err = oracle.normalized_error(C[rows], ref, D)
+        flops = 2.0 * len(rows) * w.N * w.K
+        cpu = {"value": flops / tcpu / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"{len(rows)} of {w.M} rows of C ({flops:.3e} flop) in {tcpu:.1f}s; "
+                         f"the same plain triple loop extrapolates to {tcpu * w.M / len(rows):.0f}s for the whole product"}
+        log(f"[bench] CPU reference: {len(rows)} rows in {tcpu:.1f}s, max normalised error {err:.3e}")
+
+    for i in range(args.warmup):
+        ooc.ooc_gemm_planned(w.alpha, A, B, w.beta, C, w.budget, plan, opts)
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    times, kbusy, hbusy, dbusy = [], 0.0, 0.0, 0.0
+    nkern = 0
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        _, s = ooc.ooc_gemm_planned(w.alpha, A, B, w.beta, C, w.budget, plan, popts)
+        times.append(s.t_total_s)
+        kbusy += s.t_kernel_busy_s
+        hbusy += s.t_h2d_busy_s
+        dbusy += s.t_d2h_busy_s
+        nkern += s.kernels
+        log(f"[bench] step {i + 1}/{args.steps}: {s.t_total_s:.3f}s {w.flops / s.t_total_s / 1e12:.2f} TFLOP/s")
+    elapsed = time.perf_counter() - t_start
+    ms = elapsed / args.steps * 1e3
+    value = w.flops * args.steps / elapsed / 1e12
+
+    roof = None
+    if args.profile and kbusy > 0:
+        achieved = w.flops * args.steps / kbusy / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "kernel": "dgemm_f64_mfma", "launches_per_step": nkern // args.steps,
+                "avg_launch_ms": round(kbusy / nkern * 1e3, 4)}
+    link = None
+    if args.profile and hbusy > 0:
+        link = {"h2d_GBps": round(s1.bytes_h2d * args.steps / hbusy / 1e9, 2),
+                "d2h_GBps": round(s1.bytes_d2h * args.steps / dbusy / 1e9, 2) if dbusy > 0 else None,
+                "h2d_bytes_per_step": int(s1.bytes_h2d), "d2h_bytes_per_step": int(s1.bytes_d2h),
+                "h2d_busy_frac": round(hbusy / elapsed, 3), "kernel_busy_frac": round(kbusy / elapsed, 3)}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == ooc.FP64 else f"split-bf16x{args.slices}",
+        "data": "synthetic (seeded counter-based generator)",
+        "config": {"workload": w.name, "M": w.M, "N": w.N, "K": w.K, "alpha": w.alpha, "beta": w.beta,
+                   "budget_bytes": w.budget, "planner": args.planner, "plan": plan.as_dict(),
+                   "arena_bytes": int(s1.arena_bytes), "parallelism": "single GPU"},
+        "roofline": roof, "cpu_baseline": cpu, "link": link,
+        "max_normalized_error": err, "predicted_s": round(s1.t_predicted_s, 4),
+    }
+    print(json.dumps(out), flush=True)
+    for m in (Am, Bm, Cm):
+        m.free()
+    ooc.ooc_release(-1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * ooc.h -- C ABI of the MI355X out-of-core FP64 matrix product.
+ *
+ * The operation (the MMOOC kernel of Hanlon, Khalighzadeh, Manumachu and
+ * Lastovetsky, "libhclooc", Section V, text after Fig. 2):
+ *     C = alpha * A * B + beta * C
+ * with A (M x K), B (K x N) and C (M x N) row-major in host memory, leading
+ * dimensions lda >= K, ldb >= N, ldc >= N (elements), and a device-memory
+ * budget smaller than the operands.  The library partitions the operands into
+ * tiles that fit the budget, moves tiles host-to-device, runs a tile product
+ * on each, and moves C tiles back, overlapping the three on HIP streams
+ * (Section V, Figs. 3 and 4: stages S(b), S(a), S(c), DGEMM, R(c)).
+ *
+ * Conventions for every entry point
+ *   - Sizes are element counts unless the name ends in _bytes.
+ *   - Host pointers are borrowed: the caller owns A, B, C and any arena it
+ *     passes; the library never frees them.  A, B and C must be page-locked
+ *     host memory (ooc_host_alloc, or hipHostMalloc).
+ *   - Calls are synchronous: they return after C is complete in host memory
+ *     (the paper's final stream synchronisation, Fig. 2).
+ *   - Errors are reported by the return code only (no exception crosses the
+ *     ABI); ooc_last_error() gives a message for the calling thread.  On an
+ *     error C is unspecified except for the blocks counted in
+ *     ooc_stats.blocks_done, which were written back completely.
+ *   - Quick returns follow the reference BLAS: M == 0 or N == 0 does nothing;
+ *     alpha == 0 or K == 0 gives C = beta*C without reading A or B; beta == 0
+ *     does not read C (NaN in C does not propagate).
+ *   - One call at a time per device; calls on one device from several host
+ *     threads are serialised by the library.
+ */
+#ifndef OOC_H
+#define OOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OOC_OK = 0,
+  OOC_ERR_ARG = 1,        /* invalid size, leading dimension, pointer, plan or option */
+  OOC_ERR_BUDGET = 2,     /* no plan fits in budget_bytes (or the plan's footprint exceeds it) */
+  OOC_ERR_DEVICE_MEM = 3, /* budget above the device's free memory, or device allocation failed */
+  OOC_ERR_NOT_PINNED = 4, /* A, B or C is not page-locked host memory */
+  OOC_ERR_HIP = 5,        /* a HIP runtime call failed (message in ooc_last_error) */
+  OOC_ERR_NO_DEVICE = 6,  /* no usable gfx950 device with that ordinal */
+  OOC_ERR_INJECTED = 7,   /* failure injected by OOC_FAIL_AT (tests of error paths) */
+  OOC_ERR_CAPACITY = 8    /* an output array is too small (ooc_schedule, ooc_plan_candidates) */
+} ooc_status;
+
+typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1 } ooc_precision;
+
+/* How a plan is chosen.  PAPER: the paper's partitioner (Section V: fewest
+ * vertical B slices, then fewest horizontal A slices, such that two C blocks of
+ * a column, their A slices and the column's B slice fit), two streams used
+ * round robin, A and C double-buffered, B single-buffered.  MODEL: the
+ * candidate with the smallest simulated pipeline time under the analytic
+ * cost model.  MLP: the candidate with the smallest time predicted by the
+ * loaded MLP (falls back to MODEL when none is loaded).  AUTO = MODEL. */
+typedef enum { OOC_PLAN_AUTO = 0, OOC_PLAN_PAPER = 1, OOC_PLAN_MODEL = 2, OOC_PLAN_MLP = 3 } ooc_planner;
+
+/* Task orders over the grid of C blocks (i: block row, j: block column) and
+ * K panels p.  COLS is the paper's order (column by column, Fig. 2).
+ * COLS_P keeps a whole block column of C resident and walks K panels outside
+ * the block rows, so each B panel is loaded once; ROWS_P is its transpose. */
+typedef enum {
+  OOC_ORDER_COLS = 0,   /* for j, for i, for p */
+  OOC_ORDER_ROWS = 1,   /* for i, for j, for p */
+  OOC_ORDER_COLS_P = 2, /* for j, for p, for i */
+  OOC_ORDER_ROWS_P = 3  /* for i, for p, for j */
+} ooc_order;
+
+/* A tiling and pipeline plan. */
+typedef struct {
+  int64_t mb, nb, kb;   /* C block rows and columns; K panel length (kb == K: no K split) */
+  int32_t order;        /* ooc_order */
+  int32_t nbuf_a;       /* device buffers for A panels (mb x kb) */
+  int32_t nbuf_b;       /* device buffers for B panels (kb x nb) */
+  int32_t nbuf_c;       /* device buffers for C blocks (mb x nb) */
+  int32_t nstreams;     /* 1: one stream; 2: the paper's two streams used round robin by
+                           block parity; 3: one stream each for H2D, kernels and D2H */
+  int32_t precision;    /* ooc_precision */
+  int32_t slices;       /* split-BF16 slice count s (1..8); ignored for FP64 */
+  int32_t reserved;
+} ooc_plan_t;
+
+/* Options; a NULL pointer means all defaults (zero-initialised struct). */
+typedef struct {
+  int32_t device;       /* HIP device ordinal (default 0) */
+  int32_t planner;      /* ooc_planner (default AUTO) */
+  int32_t precision;    /* ooc_precision (default FP64) */
+  int32_t slices;       /* split-BF16 slices (0: 6) */
+  int32_t nstreams;     /* restrict candidate plans to this stream count (0: any) */
+  int32_t profile;      /* 1: time every operation with HIP events (fills the busy times) */
+  void* arena;          /* optional caller-owned device memory used instead of allocating */
+  size_t arena_bytes;   /* its size; must be >= the plan's footprint */
+} ooc_opts;
+
+/* Outcome of a call. */
+typedef struct {
+  ooc_plan_t plan;
+  double t_total_s;      /* host wall time from entry to return */
+  double t_pipeline_s;   /* first operation issued to last one complete */
+  double t_h2d_busy_s;   /* sum of H2D copy durations (profile == 1) */
+  double t_d2h_busy_s;   /* sum of D2H copy durations (profile == 1) */
+  double t_kernel_busy_s;/* sum of kernel durations (profile == 1) */
+  double t_predicted_s;  /* the cost model's prediction for the plan */
+  double flops;          /* 2*M*N*K */
+  uint64_t bytes_h2d, bytes_d2h;
+  uint64_t arena_bytes;  /* device bytes used by the call (<= budget) */
+  int64_t ops, tasks, kernels;
+  int64_t blocks_done;   /* C blocks completely written back to the host */
+} ooc_stats;
+
+/* ---- the out-of-core product ---------------------------------------------------- */
+
+/* C = alpha*A*B + beta*C through a device budget of budget_bytes.
+ * All device memory the call uses (tile buffers and split workspace) is at most
+ * budget_bytes; it is allocated for the call (or taken from opts->arena) and
+ * cached for the next call on the device until ooc_release().
+ * Errors: OOC_ERR_ARG (negative sizes, ld too small, NULL operand with a
+ * nonzero extent), OOC_ERR_BUDGET (nothing fits), OOC_ERR_DEVICE_MEM,
+ * OOC_ERR_NOT_PINNED, OOC_ERR_NO_DEVICE, OOC_ERR_HIP. */
+ooc_status ooc_gemm(int64_t M, int64_t N, int64_t K, double alpha,
+                    const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double beta, double* C, int64_t ldc, size_t budget_bytes,
+                    const ooc_opts* opts, ooc_stats* stats);
+
+/* Choose a plan for the problem and budget (host only, no device access). */
+ooc_status ooc_plan(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes,
+                    const ooc_opts* opts, ooc_plan_t* out);
+
+/* The product with a caller-given plan; fails with OOC_ERR_BUDGET if its
+ * footprint exceeds budget_bytes and OOC_ERR_ARG if the plan is malformed. */
+ooc_status ooc_gemm_planned(int64_t M, int64_t N, int64_t K, double alpha,
+                            const double* A, int64_t lda, const double* B, int64_t ldb,
+                            double beta, double* C, int64_t ldc, size_t budget_bytes,
+                            const ooc_plan_t* plan, const ooc_opts* opts, ooc_stats* stats);
+
+/* Device bytes a plan needs (tile buffers, alignment, split workspace). */
+ooc_status ooc_plan_footprint(int64_t M, int64_t N, int64_t K, double beta,
+                              const ooc_plan_t* plan, uint64_t* bytes);
+
+/* The paper's partitioner alone: h horizontal A slices and w vertical B slices
+ * (Section V; fewest w, then fewest h, with footprint 2*mb*K + K*nb + 2*mb*nb
+ * elements, or M*K + K*N + M*N for a single block). OOC_ERR_BUDGET if none fits. */
+ooc_status ooc_partition(int64_t M, int64_t N, int64_t K, size_t budget_bytes,
+                         int64_t* h, int64_t* w);
+
+/* All candidate plans the MODEL/MLP planners consider (host only).  Writes up
+ * to cap plans and their modelled times; *n receives the total count
+ * (OOC_ERR_CAPACITY if it exceeds cap). */
+ooc_status ooc_plan_candidates(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes,
+                               const ooc_opts* opts, ooc_plan_t* plans, double* model_s,
+                               int64_t cap, int64_t* n);
+
+/* The analytic cost model's simulated time of a plan (host only). */
+ooc_status ooc_plan_predict(int64_t M, int64_t N, int64_t K, double beta, const ooc_plan_t* plan,
+                            double* seconds);
+
+/* ---- the operation list (what the HIP backend issues), for inspection ---------- */
+
+typedef enum {
+  OOC_OP_H2D = 0,        /* host submatrix -> device buffer (2-D pitched copy) */
+  OOC_OP_D2H = 1,        /* device buffer -> host submatrix */
+  OOC_OP_GEMM = 2,       /* FP64 tile product c = alpha*a*b + beta*c on device buffers */
+  OOC_OP_SPLIT_A = 3,    /* split-BF16: exponents and slices of an A panel into the workspace */
+  OOC_OP_SPLIT_B = 4,    /* split-BF16: exponents and slices of a B panel into the workspace */
+  OOC_OP_SPLIT_GEMM = 5  /* split-BF16 tile product from the slices in the workspace */
+} ooc_op_kind;
+
+#define OOC_MAX_WAITS 4
+
+typedef struct {
+  int32_t kind;               /* ooc_op_kind */
+  int32_t stream;             /* stream index, 0 .. nstreams-1 */
+  int32_t task;               /* index of the tile task this op serves */
+  int32_t nwait;              /* entries used in wait[] */
+  int32_t wait[OOC_MAX_WAITS];/* earlier ops (other streams) that must complete first */
+  int32_t mat;                /* copies: 0 = A, 1 = B, 2 = C */
+  int32_t slot;               /* device buffer index within its operand's pool */
+  int64_t row0, col0;         /* copies: host submatrix origin; GEMM: C block origin (i0, j0) */
+  int64_t rows, cols;         /* copies: submatrix extent; GEMM: m, n */
+  int64_t k0, k;              /* GEMM: K panel origin and length */
+  int64_t off_a, ld_a;        /* GEMM: arena element offset / leading dim of the A panel */
+  int64_t off_b, ld_b;        /* GEMM: same for the B panel */
+  int64_t off_c, ld_c;        /* GEMM: C block; copies: the device side of the copy */
+  int64_t off_w, len_w;       /* split ops: workspace element offset and length */
+  double alpha, beta;         /* GEMM: effective scalars of this panel step */
+} ooc_op;
+
+/* The operation list a plan produces (host only).  Writes up to cap ops;
+ * *nops receives the count and *arena_bytes the arena size the offsets assume. */
+ooc_status ooc_schedule(int64_t M, int64_t N, int64_t K, double alpha, double beta,
+                        const ooc_plan_t* plan, ooc_op* ops, int64_t cap, int64_t* nops,
+                        uint64_t* arena_bytes);
+
+/* ---- memory helpers ----------------------------------------------------------- */
+
+ooc_status ooc_host_alloc(void** ptr, size_t bytes);  /* page-locked host memory */
+ooc_status ooc_host_free(void* ptr);
+ooc_status ooc_device_alloc(int32_t device, void** ptr, size_t bytes);
+ooc_status ooc_device_free(int32_t device, void* ptr);
+/* Synchronous copies between host and device memory (for tests and tools). */
+ooc_status ooc_copy_to_device(int32_t device, void* dst, const void* src, size_t bytes);
+ooc_status ooc_copy_to_host(int32_t device, void* dst, const void* src, size_t bytes);
+
+/* Free the device buffers, streams and events cached for a device (-1: all). */
+ooc_status ooc_release(int32_t device);
+
+/* ---- in-core tile kernels on device memory (building blocks, for tests) ------- */
+
+/* C = alpha*A*B + beta*C on device pointers with the FP64 MFMA tile kernel (the
+ * paper's DGEMM stage, Section V).  Row-major, lda >= k, ldb >= n, ldc >= n.
+ * If ms_out is not NULL the kernel is timed with HIP events (milliseconds). */
+ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, double alpha,
+                            const double* A, int64_t lda, const double* B, int64_t ldb,
+                            double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
+
+/* ---- messages and version ----------------------------------------------------- */
+
+const char* ooc_last_error(void);   /* message of the calling thread's last error */
+const char* ooc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OOC_H */

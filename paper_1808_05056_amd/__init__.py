@@ -1,0 +1,322 @@
+"""Python binding of libooc.so, the MI355X out-of-core FP64 matrix product.
+
+Argument marshalling only: every step of the product (planning, scheduling,
+copies, tile kernels) runs in the native library.  Importing this package
+loads the built library and raises if it is missing; build it with
+``python -m paper_1808_05056_amd.build``.
+
+Names follow the C ABI in include/ooc.h:
+    ooc_gemm, ooc_gemm_planned, ooc_plan, ooc_plan_footprint, ooc_partition,
+    ooc_plan_candidates, ooc_plan_predict, ooc_schedule, ooc_host_alloc,
+    ooc_host_free, ooc_release, ooc_dgemm_device, ooc_last_error
+plus numpy helpers for page-locked host matrices and device buffers.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libooc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1808_05056_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- ABI types (mirror include/ooc.h) ------------------------------------------------
+
+OOC_OK, OOC_ERR_ARG, OOC_ERR_BUDGET, OOC_ERR_DEVICE_MEM, OOC_ERR_NOT_PINNED, OOC_ERR_HIP, \
+    OOC_ERR_NO_DEVICE, OOC_ERR_INJECTED, OOC_ERR_CAPACITY = range(9)
+STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_BUDGET", 3: "ERR_DEVICE_MEM", 4: "ERR_NOT_PINNED", 5: "ERR_HIP",
+                6: "ERR_NO_DEVICE", 7: "ERR_INJECTED", 8: "ERR_CAPACITY"}
+FP64, SPLIT_BF16 = 0, 1
+PLAN_AUTO, PLAN_PAPER, PLAN_MODEL, PLAN_MLP = 0, 1, 2, 3
+ORDER_COLS, ORDER_ROWS, ORDER_COLS_P, ORDER_ROWS_P = 0, 1, 2, 3
+OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_A, OP_SPLIT_B, OP_SPLIT_GEMM = range(6)
+OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_a", 4: "split_b", 5: "split_gemm"}
+MAX_WAITS = 4
+
+i32, i64, u64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class ooc_plan_t(ctypes.Structure):
+    _fields_ = [("mb", i64), ("nb", i64), ("kb", i64), ("order", i32), ("nbuf_a", i32), ("nbuf_b", i32),
+                ("nbuf_c", i32), ("nstreams", i32), ("precision", i32), ("slices", i32), ("reserved", i32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+    def __repr__(self):
+        return "ooc_plan_t(" + ", ".join(f"{k}={v}" for k, v in self.as_dict().items()) + ")"
+
+
+class ooc_opts(ctypes.Structure):
+    _fields_ = [("device", i32), ("planner", i32), ("precision", i32), ("slices", i32), ("nstreams", i32),
+                ("profile", i32), ("arena", vp), ("arena_bytes", sz)]
+
+
+class ooc_stats(ctypes.Structure):
+    _fields_ = [("plan", ooc_plan_t), ("t_total_s", dbl), ("t_pipeline_s", dbl), ("t_h2d_busy_s", dbl),
+                ("t_d2h_busy_s", dbl), ("t_kernel_busy_s", dbl), ("t_predicted_s", dbl), ("flops", dbl),
+                ("bytes_h2d", u64), ("bytes_d2h", u64), ("arena_bytes", u64), ("ops", i64), ("tasks", i64),
+                ("kernels", i64), ("blocks_done", i64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "plan"}
+        d["plan"] = self.plan.as_dict()
+        return d
+
+
+class ooc_op(ctypes.Structure):
+    _fields_ = [("kind", i32), ("stream", i32), ("task", i32), ("nwait", i32), ("wait", i32 * MAX_WAITS),
+                ("mat", i32), ("slot", i32), ("row0", i64), ("col0", i64), ("rows", i64), ("cols", i64),
+                ("k0", i64), ("k", i64), ("off_a", i64), ("ld_a", i64), ("off_b", i64), ("ld_b", i64),
+                ("off_c", i64), ("ld_c", i64), ("off_w", i64), ("len_w", i64), ("alpha", dbl), ("beta", dbl)]
+
+
+P = ctypes.POINTER
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("ooc_gemm", i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
+_sig("ooc_gemm_planned", i32, [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, sz, P(ooc_plan_t), P(ooc_opts),
+                               P(ooc_stats)])
+_sig("ooc_plan", i32, [i64, i64, i64, dbl, sz, P(ooc_opts), P(ooc_plan_t)])
+_sig("ooc_plan_footprint", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(u64)])
+_sig("ooc_partition", i32, [i64, i64, i64, sz, P(i64), P(i64)])
+_sig("ooc_plan_candidates", i32, [i64, i64, i64, dbl, sz, P(ooc_opts), P(ooc_plan_t), P(dbl), i64, P(i64)])
+_sig("ooc_plan_predict", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(dbl)])
+_sig("ooc_schedule", i32, [i64, i64, i64, dbl, dbl, P(ooc_plan_t), P(ooc_op), i64, P(i64), P(u64)])
+_sig("ooc_host_alloc", i32, [P(vp), sz])
+_sig("ooc_host_free", i32, [vp])
+_sig("ooc_device_alloc", i32, [i32, P(vp), sz])
+_sig("ooc_device_free", i32, [i32, vp])
+_sig("ooc_copy_to_device", i32, [i32, vp, vp, sz])
+_sig("ooc_copy_to_host", i32, [i32, vp, vp, sz])
+_sig("ooc_release", i32, [i32])
+_sig("ooc_dgemm_device", i32, [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
+_sig("ooc_last_error", ctypes.c_char_p, [])
+_sig("ooc_version", ctypes.c_char_p, [])
+
+EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
+           "ooc_plan_predict", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
+           "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_dgemm_device",
+           "ooc_last_error", "ooc_version"]
+
+
+class OOCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def ooc_last_error():
+    return _lib.ooc_last_error().decode()
+
+
+def ooc_version():
+    return _lib.ooc_version().decode()
+
+
+def _check(st):
+    if st != OOC_OK:
+        raise OOCError(st, ooc_last_error())
+    return st
+
+
+def _mat_arg(X, name):
+    """(pointer, leading dimension) of a 2-D row-major float64 view, or (None, 0)."""
+    if X is None:
+        return None, 0
+    if not isinstance(X, np.ndarray) or X.dtype != np.float64 or X.ndim != 2 or X.strides[1] != 8 or X.strides[0] % 8:
+        raise TypeError(f"{name} must be a 2-D row-major float64 numpy view")
+    return X.ctypes.data, max(X.strides[0] // 8, X.shape[1])
+
+
+def make_opts(device=0, planner=PLAN_AUTO, precision=FP64, slices=0, nstreams=0, profile=False, arena=None,
+              arena_bytes=0):
+    return ooc_opts(device, planner, precision, slices, nstreams, 1 if profile else 0, arena, arena_bytes)
+
+
+def make_plan(mb, nb, kb, order=ORDER_COLS, nbuf_a=2, nbuf_b=1, nbuf_c=2, nstreams=3, precision=FP64, slices=0):
+    return ooc_plan_t(mb, nb, kb, order, nbuf_a, nbuf_b, nbuf_c, nstreams, precision, slices, 0)
+
+
+# ---- entry points ---------------------------------------------------------------------
+
+def ooc_gemm(alpha, A, B, beta, C, budget_bytes, opts=None, raise_on_error=True):
+    """C = alpha*A@B + beta*C in place (A, B, C page-locked float64 views).
+    Returns (status, ooc_stats)."""
+    M, N = C.shape
+    K = A.shape[1] if A is not None else 0
+    pa, lda = _mat_arg(A, "A")
+    pb, ldb = _mat_arg(B, "B")
+    pc, ldc = _mat_arg(C, "C")
+    st = ooc_stats()
+    s = _lib.ooc_gemm(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, budget_bytes,
+                      ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
+
+
+def ooc_gemm_raw(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, budget_bytes, opts=None):
+    """The ABI call with raw pointers and sizes (for argument-check tests). Returns (status, stats)."""
+    st = ooc_stats()
+    s = _lib.ooc_gemm(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, budget_bytes,
+                      ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    return s, st
+
+
+def ooc_gemm_planned(alpha, A, B, beta, C, budget_bytes, plan, opts=None, raise_on_error=True):
+    M, N = C.shape
+    K = A.shape[1] if A is not None else 0
+    pa, lda = _mat_arg(A, "A")
+    pb, ldb = _mat_arg(B, "B")
+    pc, ldc = _mat_arg(C, "C")
+    st = ooc_stats()
+    s = _lib.ooc_gemm_planned(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, budget_bytes, ctypes.byref(plan),
+                              ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
+
+
+def ooc_plan(M, N, K, beta, budget_bytes, opts=None):
+    p = ooc_plan_t()
+    _check(_lib.ooc_plan(M, N, K, beta, budget_bytes, ctypes.byref(opts) if opts is not None else None,
+                         ctypes.byref(p)))
+    return p
+
+
+def ooc_plan_footprint(M, N, K, beta, plan):
+    b = u64()
+    _check(_lib.ooc_plan_footprint(M, N, K, beta, ctypes.byref(plan), ctypes.byref(b)))
+    return b.value
+
+
+def ooc_partition(M, N, K, budget_bytes):
+    h, w = i64(), i64()
+    st = _lib.ooc_partition(M, N, K, budget_bytes, ctypes.byref(h), ctypes.byref(w))
+    if st == OOC_ERR_BUDGET:
+        return None
+    _check(st)
+    return h.value, w.value
+
+
+def ooc_plan_candidates(M, N, K, beta, budget_bytes, opts=None, cap=4096):
+    plans = (ooc_plan_t * cap)()
+    times = (dbl * cap)()
+    n = i64()
+    _check(_lib.ooc_plan_candidates(M, N, K, beta, budget_bytes, ctypes.byref(opts) if opts is not None else None,
+                                    plans, times, cap, ctypes.byref(n)))
+    return [plans[x] for x in range(n.value)], [times[x] for x in range(n.value)]
+
+
+def ooc_plan_predict(M, N, K, beta, plan):
+    t = dbl()
+    _check(_lib.ooc_plan_predict(M, N, K, beta, ctypes.byref(plan), ctypes.byref(t)))
+    return t.value
+
+
+def ooc_schedule(M, N, K, alpha, beta, plan):
+    """The operation list as dicts (keys as in the CPU schedule checker) and the arena size in elements."""
+    n = i64()
+    ab = u64()
+    st = _lib.ooc_schedule(M, N, K, alpha, beta, ctypes.byref(plan), None, 0, ctypes.byref(n), ctypes.byref(ab))
+    if st not in (OOC_OK, OOC_ERR_CAPACITY):
+        _check(st)
+    cap = max(n.value, 1)
+    arr = (ooc_op * cap)()
+    _check(_lib.ooc_schedule(M, N, K, alpha, beta, ctypes.byref(plan), arr, cap, ctypes.byref(n), ctypes.byref(ab)))
+    ops = []
+    for x in range(n.value):
+        o = arr[x]
+        kind = OP_NAMES[o.kind]
+        d = dict(kind=kind, stream=o.stream, task=o.task, waits=[o.wait[k] for k in range(o.nwait)], slot=o.slot)
+        if kind in ("h2d", "d2h"):
+            d.update(mat="ABC"[o.mat], row0=o.row0, col0=o.col0, rows=o.rows, cols=o.cols, dev_off=o.off_c,
+                     dev_ld=o.ld_c)
+        else:
+            d.update(m=o.rows, n=o.cols, k=o.k, i0=o.row0, j0=o.col0, k0=o.k0, off_a=o.off_a, lda=o.ld_a,
+                     off_b=o.off_b, ldb=o.ld_b, off_c=o.off_c, ldc=o.ld_c, off_w=o.off_w, len_w=o.len_w,
+                     alpha=o.alpha, beta=o.beta)
+        ops.append(d)
+    return ops, ab.value // 8
+
+
+def ooc_release(device=-1):
+    _check(_lib.ooc_release(device))
+
+
+def ooc_dgemm_device(m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps=1, timed=False, device=0):
+    ms = dbl()
+    _check(_lib.ooc_dgemm_device(device, m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps,
+                                 ctypes.byref(ms) if timed else None))
+    return ms.value if timed else None
+
+
+# ---- memory helpers ---------------------------------------------------------------------
+
+class PinnedMatrix:
+    """A page-locked host matrix (rows x cols, row pitch ld) exposed as a numpy view."""
+
+    def __init__(self, rows, cols, ld=None):
+        self.ld = cols if ld is None else ld
+        nbytes = max(1, rows * self.ld * 8)
+        p = vp()
+        _check(_lib.ooc_host_alloc(ctypes.byref(p), nbytes))
+        self.ptr = p.value
+        buf = (ctypes.c_double * max(1, rows * self.ld)).from_address(self.ptr)
+        full = np.ctypeslib.as_array(buf)[: rows * self.ld].reshape(rows, self.ld) if rows * self.ld else np.empty((rows, self.ld))
+        self.array = full[:, :cols]
+
+    def free(self):
+        if self.ptr:
+            _lib.ooc_host_free(self.ptr)
+            self.ptr = None
+            self.array = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class DeviceBuffer:
+    """Device memory for the tile-kernel entry points."""
+
+    def __init__(self, nbytes, device=0):
+        p = vp()
+        _check(_lib.ooc_device_alloc(device, ctypes.byref(p), nbytes))
+        self.ptr, self.nbytes, self.device = p.value, nbytes, device
+
+    def upload(self, X):
+        X = np.ascontiguousarray(X)
+        assert X.nbytes <= self.nbytes
+        _check(_lib.ooc_copy_to_device(self.device, self.ptr, X.ctypes.data, X.nbytes))
+
+    def download(self, shape, dtype=np.float64):
+        out = np.empty(shape, dtype=dtype)
+        assert out.nbytes <= self.nbytes
+        _check(_lib.ooc_copy_to_host(self.device, out.ctypes.data, self.ptr, out.nbytes))
+        return out
+
+    def free(self):
+        if self.ptr:
+            _lib.ooc_device_free(self.device, self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,559 @@
+// C ABI entry points and the HIP backend that runs an operation list.
+//
+// The paper's MMOOC (Section V, Fig. 2) issues, per C block, asynchronous
+// copies and a DGEMM on two streams, tied together with events, and
+// synchronises both streams before returning.  Here the operation list from
+// the scheduler is issued in order: each op first makes its stream wait for
+// the events of the ops listed in its wait set, then enqueues a pitched copy
+// (hipMemcpy2DAsync between page-locked host memory and the device arena) or
+// a tile kernel, and records an event if a later op on another stream waits
+// for it.  The call returns after every stream has drained.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace ooc {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+ooc_status fail(ooc_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+struct DevCtx {
+  std::mutex mu;
+  bool init = false;
+  hipStream_t st[3] = {nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> ev;   // dependency events (no timing)
+  std::vector<hipEvent_t> tev;  // timing events (profile mode)
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+};
+
+DevCtx g_dev[kMaxDevices];
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+ooc_status hip_fail(hipError_t e, const char* what) {
+  return fail(OOC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                       \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+// Select the device and create its streams once.
+ooc_status ensure_device(int dev) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return fail(OOC_ERR_NO_DEVICE, "no HIP device available");
+  }
+  if (dev < 0 || dev >= count || dev >= kMaxDevices) return fail(OOC_ERR_NO_DEVICE, "device ordinal out of range");
+  HIPCHK(hipSetDevice(dev), "hipSetDevice");
+  DevCtx& c = g_dev[dev];
+  if (!c.init) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(OOC_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    for (int s = 0; s < 3; ++s) HIPCHK(hipStreamCreateWithFlags(&c.st[s], hipStreamNonBlocking), "hipStreamCreate");
+    c.init = true;
+  }
+  return OOC_OK;
+}
+
+ooc_status ensure_events(std::vector<hipEvent_t>& pool, size_t n, unsigned flags) {
+  while (pool.size() < n) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, flags), "hipEventCreate");
+    pool.push_back(e);
+  }
+  return OOC_OK;
+}
+
+bool is_pinned(const void* p) {
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeHost;
+}
+
+bool range_pinned(const double* base, int64_t rows, int64_t cols, int64_t ld) {
+  if (rows == 0 || cols == 0) return true;
+  return is_pinned(base) && is_pinned(base + (rows - 1) * ld + (cols - 1));
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : dflt;
+}
+
+struct HostMats {
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  double* C; int64_t ldc;
+};
+
+ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>& ops, double* arena,
+                   const HostMats& hm, bool profile, ooc_stats* st) {
+  const size_t n = ops.size();
+  std::vector<int> evidx(n, -1);
+  size_t nev = 0;
+  for (const ooc_op& o : ops)
+    for (int k = 0; k < o.nwait; ++k)
+      if (evidx[o.wait[k]] < 0) evidx[o.wait[k]] = (int)nev++;
+  ooc_status s0 = ensure_events(c.ev, nev, hipEventDisableTiming);
+  if (s0 != OOC_OK) return s0;
+  if (profile) {
+    s0 = ensure_events(c.tev, 2 * n, hipEventDefault);
+    if (s0 != OOC_OK) return s0;
+  }
+  const int fail_at = env_int("OOC_FAIL_AT", -1);
+  ooc_status status = OOC_OK;
+  std::string msg;
+  int64_t d2h_issued = 0;
+  size_t issued = 0;
+  const double t0 = now_s();
+  for (size_t x = 0; x < n; ++x) {
+    const ooc_op& o = ops[x];
+    if ((int)x == fail_at) {
+      status = OOC_ERR_INJECTED;
+      msg = "failure injected at op " + std::to_string(x);
+      break;
+    }
+    hipStream_t s = c.st[o.stream];
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < o.nwait && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, c.ev[evidx[o.wait[k]]], 0);
+    if (e == hipSuccess && profile) e = hipEventRecord(c.tev[2 * x], s);
+    if (e == hipSuccess) {
+      switch (o.kind) {
+        case OOC_OP_H2D:
+        case OOC_OP_D2H: {
+          const double* hbase = o.mat == 0 ? hm.A : (o.mat == 1 ? hm.B : hm.C);
+          const int64_t hld = o.mat == 0 ? hm.lda : (o.mat == 1 ? hm.ldb : hm.ldc);
+          double* host = const_cast<double*>(hbase) + o.row0 * hld + o.col0;
+          double* dev = arena + o.off_c;
+          const bool contiguous = (o.cols == hld || o.rows == 1) && (o.cols == o.ld_c || o.rows == 1);
+          if (o.kind == OOC_OP_H2D) {
+            if (contiguous)
+              e = hipMemcpyAsync(dev, host, (size_t)(o.rows * o.cols) * 8, hipMemcpyHostToDevice, s);
+            else
+              e = hipMemcpy2DAsync(dev, (size_t)o.ld_c * 8, host, (size_t)hld * 8, (size_t)o.cols * 8,
+                                   (size_t)o.rows, hipMemcpyHostToDevice, s);
+          } else {
+            if (contiguous)
+              e = hipMemcpyAsync(host, dev, (size_t)(o.rows * o.cols) * 8, hipMemcpyDeviceToHost, s);
+            else
+              e = hipMemcpy2DAsync(host, (size_t)hld * 8, dev, (size_t)o.ld_c * 8, (size_t)o.cols * 8,
+                                   (size_t)o.rows, hipMemcpyDeviceToHost, s);
+            ++d2h_issued;
+          }
+          break;
+        }
+        case OOC_OP_GEMM:
+          e = launch_dgemm_f64(o.rows, o.cols, o.k, o.alpha, arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b,
+                               o.beta, arena + o.off_c, o.ld_c, s);
+          break;
+        default:
+          status = OOC_ERR_ARG;
+          msg = "operation kind not supported by this build";
+          break;
+      }
+    }
+    if (status != OOC_OK) break;
+    if (e == hipSuccess && profile) e = hipEventRecord(c.tev[2 * x + 1], s);
+    if (e == hipSuccess && evidx[x] >= 0) e = hipEventRecord(c.ev[evidx[x]], s);
+    if (e != hipSuccess) {
+      status = OOC_ERR_HIP;
+      msg = std::string("issuing op ") + std::to_string(x) + ": " + hipGetErrorString(e);
+      break;
+    }
+    ++issued;
+  }
+  // drain every stream, also after a failure, so no work outlives the call
+  for (int k = 0; k < plan.nstreams; ++k) {
+    hipError_t e = hipStreamSynchronize(c.st[k]);
+    if (e != hipSuccess && status == OOC_OK) {
+      status = OOC_ERR_HIP;
+      msg = std::string("stream synchronise: ") + hipGetErrorString(e);
+    }
+  }
+  const double t1 = now_s();
+  if (st) {
+    st->t_pipeline_s = t1 - t0;
+    st->blocks_done = (status == OOC_OK || status == OOC_ERR_INJECTED) ? d2h_issued : 0;
+    if (profile && status == OOC_OK) {
+      double th = 0, td = 0, tk = 0;
+      for (size_t x = 0; x < issued; ++x) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c.tev[2 * x], c.tev[2 * x + 1]) != hipSuccess) continue;
+        if (ops[x].kind == OOC_OP_H2D) th += ms * 1e-3;
+        else if (ops[x].kind == OOC_OP_D2H) td += ms * 1e-3;
+        else tk += ms * 1e-3;
+      }
+      st->t_h2d_busy_s = th;
+      st->t_d2h_busy_s = td;
+      st->t_kernel_busy_s = tk;
+    }
+  }
+  if (status != OOC_OK) return fail(status, msg);
+  return OOC_OK;
+}
+
+ooc_status check_args(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                      int64_t ldb, double beta, double* C, int64_t ldc) {
+  (void)beta;
+  if (M < 0 || N < 0 || K < 0) return fail(OOC_ERR_ARG, "negative matrix size");
+  const bool need_ab = M > 0 && N > 0 && K > 0 && alpha != 0.0;
+  if (M > 0 && N > 0) {
+    if (!C) return fail(OOC_ERR_ARG, "C is NULL");
+    if (ldc < N) return fail(OOC_ERR_ARG, "ldc < N");
+  }
+  if (need_ab) {
+    if (!A || !B) return fail(OOC_ERR_ARG, "A or B is NULL");
+    if (lda < K) return fail(OOC_ERR_ARG, "lda < K");
+    if (ldb < N) return fail(OOC_ERR_ARG, "ldb < N");
+  }
+  return OOC_OK;
+}
+
+ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                     int64_t ldb, double beta, double* C, int64_t ldc, size_t budget_bytes, const ooc_plan_t* given,
+                     const ooc_opts* opts, ooc_stats* stats) {
+  const double t_enter = now_s();
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  ooc_status st = check_args(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  if (st != OOC_OK) return st;
+  if (M == 0 || N == 0) return OOC_OK;
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.alpha = alpha; pb.beta = beta;
+  ooc_plan_t plan;
+  double predicted = 0.0;
+  if (given) {
+    plan = *given;
+  } else {
+    st = choose_plan(pb, budget_bytes, opts, &plan, &predicted);
+    if (st != OOC_OK) return st;
+  }
+  Layout lay;
+  st = plan_layout(pb, plan, &lay);
+  if (st != OOC_OK) return st;
+  if (lay.bytes > budget_bytes)
+    return fail(OOC_ERR_BUDGET, "plan footprint " + std::to_string(lay.bytes) + " bytes exceeds the budget of " +
+                                    std::to_string(budget_bytes));
+  std::vector<ooc_op> ops;
+  st = build_schedule(pb, plan, lay, &ops);
+  if (st != OOC_OK) return st;
+  if (given) predicted = simulate(pb, plan, ops);
+
+  const int dev = opts ? opts->device : 0;
+  st = ensure_device(dev);
+  if (st != OOC_OK) return st;
+  const int64_t keff = pb.keff();
+  if (keff > 0 && (!range_pinned(A, M, K, lda) || !range_pinned(B, K, N, ldb)))
+    return fail(OOC_ERR_NOT_PINNED, "A or B is not page-locked host memory (use ooc_host_alloc)");
+  if (!range_pinned(C, M, N, ldc)) return fail(OOC_ERR_NOT_PINNED, "C is not page-locked host memory (use ooc_host_alloc)");
+
+  DevCtx& c = g_dev[dev];
+  std::lock_guard<std::mutex> lock(c.mu);
+  double* arena = nullptr;
+  if (opts && opts->arena) {
+    if (opts->arena_bytes < lay.bytes) return fail(OOC_ERR_ARG, "opts->arena is smaller than the plan's footprint");
+    arena = static_cast<double*>(opts->arena);
+  } else {
+    if (c.arena && (c.arena_bytes < lay.bytes || c.arena_bytes > budget_bytes)) {
+      HIPCHK(hipFree(c.arena), "hipFree");
+      c.arena = nullptr;
+      c.arena_bytes = 0;
+    }
+    if (!c.arena && lay.bytes > 0) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+      if (lay.bytes > fr)
+        return fail(OOC_ERR_DEVICE_MEM, "plan needs " + std::to_string(lay.bytes) + " bytes, device has " +
+                                            std::to_string(fr) + " free");
+      hipError_t e = hipMalloc(&c.arena, lay.bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c.arena = nullptr;
+        return fail(OOC_ERR_DEVICE_MEM, std::string("hipMalloc of the arena failed: ") + hipGetErrorString(e));
+      }
+      c.arena_bytes = lay.bytes;
+    }
+    arena = static_cast<double*>(c.arena);
+  }
+  HostMats hm{A, lda, B, ldb, C, ldc};
+  st = run_ops(c, plan, ops, arena, hm, opts && opts->profile, stats);
+  if (stats) {
+    stats->plan = plan;
+    stats->t_total_s = now_s() - t_enter;
+    stats->t_predicted_s = predicted;
+    stats->flops = 2.0 * (double)M * (double)N * (double)K;
+    stats->arena_bytes = lay.bytes;
+    stats->ops = (int64_t)ops.size();
+    int64_t tasks = 0, kern = 0;
+    uint64_t bh = 0, bd = 0;
+    for (const ooc_op& o : ops) {
+      if (o.kind == OOC_OP_H2D) bh += (uint64_t)(o.rows * o.cols) * 8;
+      else if (o.kind == OOC_OP_D2H) bd += (uint64_t)(o.rows * o.cols) * 8;
+      else ++kern;
+      if (o.kind == OOC_OP_GEMM || o.kind == OOC_OP_SPLIT_GEMM) ++tasks;
+    }
+    stats->tasks = tasks;
+    stats->kernels = kern;
+    stats->bytes_h2d = bh;
+    stats->bytes_d2h = bd;
+  }
+  return st;
+}
+
+}  // namespace
+
+bool mlp_predict(const Problem&, uint64_t, const std::vector<ooc_plan_t>&, std::vector<double>*) { return false; }
+
+}  // namespace ooc
+
+using namespace ooc;
+
+extern "C" {
+
+ooc_status ooc_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                    int64_t ldb, double beta, double* C, int64_t ldc, size_t budget_bytes, const ooc_opts* opts,
+                    ooc_stats* stats) {
+  return gemm_impl(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, budget_bytes, nullptr, opts, stats);
+}
+
+ooc_status ooc_gemm_planned(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                            const double* B, int64_t ldb, double beta, double* C, int64_t ldc, size_t budget_bytes,
+                            const ooc_plan_t* plan, const ooc_opts* opts, ooc_stats* stats) {
+  if (!plan) return fail(OOC_ERR_ARG, "plan is NULL");
+  return gemm_impl(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, budget_bytes, plan, opts, stats);
+}
+
+ooc_status ooc_plan(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes, const ooc_opts* opts,
+                    ooc_plan_t* out) {
+  if (!out) return fail(OOC_ERR_ARG, "out is NULL");
+  if (M <= 0 || N <= 0 || K < 0) return fail(OOC_ERR_ARG, "M and N must be positive, K non-negative");
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.alpha = 1.0; pb.beta = beta;
+  return choose_plan(pb, budget_bytes, opts, out, nullptr);
+}
+
+ooc_status ooc_plan_footprint(int64_t M, int64_t N, int64_t K, double beta, const ooc_plan_t* plan, uint64_t* bytes) {
+  if (!plan || !bytes) return fail(OOC_ERR_ARG, "NULL argument");
+  if (M <= 0 || N <= 0 || K < 0) return fail(OOC_ERR_ARG, "M and N must be positive, K non-negative");
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.beta = beta;
+  Layout lay;
+  ooc_status st = plan_layout(pb, *plan, &lay);
+  if (st != OOC_OK) return st;
+  *bytes = lay.bytes;
+  return OOC_OK;
+}
+
+ooc_status ooc_partition(int64_t M, int64_t N, int64_t K, size_t budget_bytes, int64_t* h, int64_t* w) {
+  if (!h || !w) return fail(OOC_ERR_ARG, "NULL argument");
+  if (M <= 0 || N <= 0 || K < 0) return fail(OOC_ERR_ARG, "M and N must be positive, K non-negative");
+  if (!paper_partition(M, N, K, budget_bytes / 8, h, w)) return fail(OOC_ERR_BUDGET, "no split fits the budget");
+  return OOC_OK;
+}
+
+ooc_status ooc_plan_candidates(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes,
+                               const ooc_opts* opts, ooc_plan_t* plans, double* model_s, int64_t cap, int64_t* n) {
+  if (!n) return fail(OOC_ERR_ARG, "n is NULL");
+  if (M <= 0 || N <= 0 || K < 0) return fail(OOC_ERR_ARG, "M and N must be positive, K non-negative");
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.beta = beta;
+  std::vector<ooc_plan_t> ps;
+  std::vector<double> ts;
+  ooc_status st = plan_candidates(pb, budget_bytes, opts, &ps, &ts);
+  if (st != OOC_OK) return st;
+  *n = (int64_t)ps.size();
+  for (int64_t x = 0; x < (int64_t)ps.size() && x < cap; ++x) {
+    if (plans) plans[x] = ps[x];
+    if (model_s) model_s[x] = ts[x];
+  }
+  if ((int64_t)ps.size() > cap) return fail(OOC_ERR_CAPACITY, "more candidates than cap");
+  return OOC_OK;
+}
+
+ooc_status ooc_plan_predict(int64_t M, int64_t N, int64_t K, double beta, const ooc_plan_t* plan, double* seconds) {
+  if (!plan || !seconds) return fail(OOC_ERR_ARG, "NULL argument");
+  if (M <= 0 || N <= 0 || K < 0) return fail(OOC_ERR_ARG, "M and N must be positive, K non-negative");
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.beta = beta;
+  Layout lay;
+  ooc_status st = plan_layout(pb, *plan, &lay);
+  if (st != OOC_OK) return st;
+  std::vector<ooc_op> ops;
+  st = build_schedule(pb, *plan, lay, &ops);
+  if (st != OOC_OK) return st;
+  *seconds = simulate(pb, *plan, ops);
+  return OOC_OK;
+}
+
+ooc_status ooc_schedule(int64_t M, int64_t N, int64_t K, double alpha, double beta, const ooc_plan_t* plan,
+                        ooc_op* ops, int64_t cap, int64_t* nops, uint64_t* arena_bytes) {
+  if (!plan || !nops) return fail(OOC_ERR_ARG, "NULL argument");
+  if (M < 0 || N < 0 || K < 0) return fail(OOC_ERR_ARG, "negative size");
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.alpha = alpha; pb.beta = beta;
+  Layout lay;
+  ooc_status st = OOC_OK;
+  if (M > 0 && N > 0) {
+    st = plan_layout(pb, *plan, &lay);
+    if (st != OOC_OK) return st;
+  }
+  std::vector<ooc_op> v;
+  st = build_schedule(pb, *plan, lay, &v);
+  if (st != OOC_OK) return st;
+  *nops = (int64_t)v.size();
+  if (arena_bytes) *arena_bytes = lay.bytes;
+  for (int64_t x = 0; x < (int64_t)v.size() && x < cap; ++x)
+    if (ops) ops[x] = v[x];
+  if ((int64_t)v.size() > cap) return fail(OOC_ERR_CAPACITY, "more ops than cap");
+  return OOC_OK;
+}
+
+ooc_status ooc_host_alloc(void** ptr, size_t bytes) {
+  if (!ptr) return fail(OOC_ERR_ARG, "ptr is NULL");
+  *ptr = nullptr;
+  if (bytes == 0) return OOC_OK;
+  hipError_t e = hipHostMalloc(ptr, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  return OOC_OK;
+}
+
+ooc_status ooc_host_free(void* ptr) {
+  if (!ptr) return OOC_OK;
+  HIPCHK(hipHostFree(ptr), "hipHostFree");
+  return OOC_OK;
+}
+
+ooc_status ooc_device_alloc(int32_t device, void** ptr, size_t bytes) {
+  if (!ptr) return fail(OOC_ERR_ARG, "ptr is NULL");
+  ooc_status st = ensure_device(device);
+  if (st != OOC_OK) return st;
+  *ptr = nullptr;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return fail(OOC_ERR_DEVICE_MEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return OOC_OK;
+}
+
+ooc_status ooc_device_free(int32_t device, void* ptr) {
+  if (!ptr) return OOC_OK;
+  ooc_status st = ensure_device(device);
+  if (st != OOC_OK) return st;
+  HIPCHK(hipFree(ptr), "hipFree");
+  return OOC_OK;
+}
+
+ooc_status ooc_copy_to_device(int32_t device, void* dst, const void* src, size_t bytes) {
+  ooc_status st = ensure_device(device);
+  if (st != OOC_OK) return st;
+  HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy H2D");
+  return OOC_OK;
+}
+
+ooc_status ooc_copy_to_host(int32_t device, void* dst, const void* src, size_t bytes) {
+  ooc_status st = ensure_device(device);
+  if (st != OOC_OK) return st;
+  HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "hipMemcpy D2H");
+  return OOC_OK;
+}
+
+ooc_status ooc_release(int32_t device) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    (void)hipGetLastError();
+    return OOC_OK;
+  }
+  for (int d = 0; d < count && d < kMaxDevices; ++d) {
+    if (device >= 0 && d != device) continue;
+    DevCtx& c = g_dev[d];
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (!c.init) continue;
+    HIPCHK(hipSetDevice(d), "hipSetDevice");
+    for (int s = 0; s < 3; ++s) HIPCHK(hipStreamSynchronize(c.st[s]), "hipStreamSynchronize");
+    if (c.arena) HIPCHK(hipFree(c.arena), "hipFree");
+    c.arena = nullptr;
+    c.arena_bytes = 0;
+    for (hipEvent_t e : c.ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c.tev) (void)hipEventDestroy(e);
+    c.ev.clear();
+    c.tev.clear();
+    for (int s = 0; s < 3; ++s) (void)hipStreamDestroy(c.st[s]);
+    c.init = false;
+  }
+  return OOC_OK;
+}
+
+ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                            int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                            int32_t reps, double* ms_out) {
+  if (m < 0 || n < 0 || k < 0) return fail(OOC_ERR_ARG, "negative size");
+  if (m == 0 || n == 0) return OOC_OK;
+  if (!C || ldc < n) return fail(OOC_ERR_ARG, "bad C or ldc");
+  if (k > 0 && (!A || !B || lda < k || ldb < n)) return fail(OOC_ERR_ARG, "bad A, B, lda or ldb");
+  ooc_status st = ensure_device(device);
+  if (st != OOC_OK) return st;
+  DevCtx& c = g_dev[device];
+  std::lock_guard<std::mutex> lock(c.mu);
+  hipStream_t s = c.st[1];
+  const int r = reps > 0 ? reps : 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ms_out) {
+    HIPCHK(hipEventCreate(&e0), "hipEventCreate");
+    HIPCHK(hipEventCreate(&e1), "hipEventCreate");
+    HIPCHK(hipEventRecord(e0, s), "hipEventRecord");
+  }
+  for (int x = 0; x < r; ++x) HIPCHK(launch_dgemm_f64(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s), "dgemm launch");
+  if (ms_out) HIPCHK(hipEventRecord(e1, s), "hipEventRecord");
+  HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (ms_out) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    *ms_out = ms / r;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return OOC_OK;
+}
+
+const char* ooc_last_error(void) { return g_err.c_str(); }
+
+const char* ooc_version(void) { return "ooc-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

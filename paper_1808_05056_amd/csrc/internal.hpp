@@ -1,0 +1,78 @@
+// Internal declarations of the out-of-core product library (host side).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ooc.h"
+
+namespace ooc {
+
+// Thread-local error message behind ooc_last_error().
+void set_error(const std::string& msg);
+ooc_status fail(ooc_status st, const std::string& msg);
+
+struct Problem {
+  int64_t M = 0, N = 0, K = 0;
+  double alpha = 1.0, beta = 0.0;
+  // K as the pipeline sees it: 0 when alpha == 0 or K == 0 (A and B are not read).
+  int64_t keff() const { return (alpha == 0.0 || K == 0) ? 0 : K; }
+};
+
+// Where the tile buffers live in the device arena (element offsets).
+struct Layout {
+  int64_t offA = 0, offB = 0, offC = 0, offW = 0;
+  int64_t slotA = 0, slotB = 0, slotC = 0;  // elements per buffer
+  int64_t lenW = 0;                         // split workspace elements
+  uint64_t bytes = 0;                       // whole arena
+};
+
+int64_t ceil_div(int64_t a, int64_t b);
+
+// Checks a plan's shape and fills the arena layout. Returns OOC_OK or OOC_ERR_ARG.
+ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay);
+
+// Split-BF16 workspace elements a plan needs (0 for FP64 plans).
+int64_t split_workspace_elems(const Problem& pb, const ooc_plan_t& plan);
+
+// The operation list of a plan (see ooc_op). Returns OOC_OK or OOC_ERR_ARG
+// (e.g. too few C buffers for the task order).
+ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layout& lay,
+                          std::vector<ooc_op>* ops);
+
+// The paper's partitioner (Section V); false if nothing fits.
+bool paper_partition(int64_t M, int64_t N, int64_t K, uint64_t budget_elems, int64_t* h, int64_t* w);
+
+// The plan the paper's MMOOC runs for a problem (two streams, A and C double-buffered).
+bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan);
+
+// Hardware figures the cost model uses.
+struct Machine {
+  double h2d_gbs = 57.6;      // pinned host -> device, one direction active (GB/s)
+  double d2h_gbs = 57.1;      // device -> pinned host
+  double duplex_gbs = 48.7;   // each direction when both are active
+  double copy_latency_s = 12e-6;
+  double kernel_tflops = 60.0;  // sustained FP64 tile-kernel rate on large tiles
+  double kernel_launch_s = 6e-6;
+  double split_tflops_per_product = 1500.0; // BF16 slice-product rate (TFLOP/s of BF16 work)
+  int cus = 256;
+};
+const Machine& machine();
+
+// Simulated time of an operation list under the cost model.
+double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc_op>& ops);
+
+// Candidate plans (feasible within the budget) with modelled times, best first.
+ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
+                           std::vector<ooc_plan_t>* plans, std::vector<double>* times);
+
+// Choose a plan according to opts->planner.
+ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
+                       ooc_plan_t* plan, double* predicted);
+
+// MLP planner hook: predicted times for candidate plans, or false if no model is loaded.
+bool mlp_predict(const Problem& pb, uint64_t budget_bytes, const std::vector<ooc_plan_t>& plans,
+                 std::vector<double>* seconds);
+
+}  // namespace ooc

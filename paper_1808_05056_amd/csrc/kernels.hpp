@@ -1,0 +1,16 @@
+// Launchers of the device kernels (all enqueue on the given stream and return
+// the launch status; none synchronises).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ooc {
+
+// C = alpha*A*B + beta*C, FP64 on matrix cores (row-major; k == 0 gives beta*C).
+hipError_t launch_dgemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
+                            const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                            hipStream_t stream);
+
+}  // namespace ooc

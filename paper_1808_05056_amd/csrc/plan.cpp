@@ -1,0 +1,371 @@
+// Planning: arena layout, the paper's partitioner, candidate plans and the
+// analytic cost model (a discrete-event simulation of the operation list).
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <set>
+#include <tuple>
+
+#include "internal.hpp"
+
+namespace ooc {
+
+const Machine& machine() {
+  static Machine m;
+  return m;
+}
+
+int64_t split_workspace_elems(const Problem& pb, const ooc_plan_t& plan) {
+  if (plan.precision != OOC_SPLIT_BF16 || pb.keff() == 0) return 0;
+  // BF16 slices of one A panel and one B panel (2 bytes each, s planes), the
+  // per-row and per-column exponents (int32), counted in 8-byte elements.
+  const int64_t s = plan.slices;
+  const int64_t kpad = ceil_div(plan.kb, 64) * 64;
+  const int64_t mpad = ceil_div(plan.mb, 256) * 256, npad = ceil_div(plan.nb, 256) * 256;
+  const int64_t slice_bytes = 2 * s * (mpad * kpad + kpad * npad);
+  const int64_t exp_bytes = 4 * (mpad + npad);
+  return ceil_div(slice_bytes + exp_bytes, 8) + 64;
+}
+
+ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
+  const int64_t K = pb.keff();
+  if (plan.mb <= 0 || plan.nb <= 0) return fail(OOC_ERR_ARG, "plan: mb and nb must be positive");
+  if (K > 0 && plan.kb <= 0) return fail(OOC_ERR_ARG, "plan: kb must be positive");
+  if (plan.nstreams < 1 || plan.nstreams > 3) return fail(OOC_ERR_ARG, "plan: nstreams must be 1, 2 or 3");
+  if (plan.order < 0 || plan.order > 3) return fail(OOC_ERR_ARG, "plan: unknown order");
+  if (plan.nbuf_c < 1 || (K > 0 && (plan.nbuf_a < 1 || plan.nbuf_b < 1)))
+    return fail(OOC_ERR_ARG, "plan: every operand needs at least one buffer");
+  if (plan.precision != OOC_FP64 && plan.precision != OOC_SPLIT_BF16)
+    return fail(OOC_ERR_ARG, "plan: unknown precision");
+  if (plan.precision == OOC_SPLIT_BF16 && (plan.slices < 1 || plan.slices > 8))
+    return fail(OOC_ERR_ARG, "plan: slices must be 1..8");
+  // clamp to the problem (a block larger than the matrix is the matrix)
+  const int64_t mb = std::min(plan.mb, std::max<int64_t>(pb.M, 1));
+  const int64_t nb = std::min(plan.nb, std::max<int64_t>(pb.N, 1));
+  const int64_t kb = K > 0 ? std::min(plan.kb, K) : 0;
+  const int64_t h = ceil_div(pb.M, mb), w = ceil_div(pb.N, nb);
+  Layout L;
+  const bool single = (h * w == 1) && (K == 0 || kb >= K);
+  if (single) {
+    // one block: each operand needs exactly one buffer (the in-core case)
+    L.slotA = mb * kb;
+    L.slotB = kb * nb;
+    L.slotC = mb * nb;
+    L.offA = 0;
+    L.offB = L.offA + (K > 0 ? L.slotA : 0);
+    L.offC = L.offB + (K > 0 ? L.slotB : 0);
+    L.offW = L.offC + L.slotC;
+  } else {
+    L.slotA = mb * kb;
+    L.slotB = kb * nb;
+    L.slotC = mb * nb;
+    L.offA = 0;
+    L.offB = L.offA + (K > 0 ? plan.nbuf_a * L.slotA : 0);
+    L.offC = L.offB + (K > 0 ? plan.nbuf_b * L.slotB : 0);
+    L.offW = L.offC + plan.nbuf_c * L.slotC;
+  }
+  ooc_plan_t p2 = plan;
+  p2.mb = mb; p2.nb = nb; p2.kb = kb;
+  L.lenW = split_workspace_elems(pb, p2);
+  if (L.lenW > 0) L.offW = ceil_div(L.offW, 32) * 32;  // 256-byte aligned workspace
+  L.bytes = (uint64_t)(L.offW + L.lenW) * 8u;
+  *lay = L;
+  return OOC_OK;
+}
+
+// ---- the paper's partitioner -----------------------------------------------------
+
+static inline uint64_t paper_footprint(int64_t M, int64_t N, int64_t K, int64_t h, int64_t w) {
+  const int64_t mb = ceil_div(M, h), nb = ceil_div(N, w);
+  if (h * w == 1) return (uint64_t)(M * K + K * N + M * N);
+  return (uint64_t)(2 * mb * K + K * nb + 2 * mb * nb);
+}
+
+static inline bool proper_split(int64_t n, int64_t parts) { return ceil_div(n, ceil_div(n, parts)) == parts; }
+
+bool paper_partition(int64_t M, int64_t N, int64_t K, uint64_t budget_elems, int64_t* h_out, int64_t* w_out) {
+  // Fewest vertical B slices w, then fewest horizontal A slices h, such that
+  // two C blocks of one column, their two A slices and the column's B slice fit.
+  for (int64_t w = 1; w <= N; ++w) {
+    if (!proper_split(N, w)) continue;
+    if (paper_footprint(M, N, K, 1, w) <= budget_elems) {
+      *h_out = 1; *w_out = w;
+      return true;
+    }
+    if (M == 1 || paper_footprint(M, N, K, M, w) > budget_elems) continue;
+    int64_t lo = 1, hi = M;  // footprint(lo) > budget >= footprint(hi)
+    while (hi - lo > 1) {
+      int64_t mid = lo + (hi - lo) / 2;
+      if (paper_footprint(M, N, K, mid, w) <= budget_elems) hi = mid; else lo = mid;
+    }
+    *h_out = hi; *w_out = w;
+    return true;
+  }
+  return false;
+}
+
+bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan) {
+  int64_t h = 1, w = 1;
+  const int64_t K = pb.keff();
+  if (!paper_partition(pb.M, pb.N, K, budget_bytes / 8, &h, &w)) return false;
+  ooc_plan_t p{};
+  p.mb = ceil_div(pb.M, h);
+  p.nb = ceil_div(pb.N, w);
+  p.kb = K;
+  p.order = OOC_ORDER_COLS;
+  p.nbuf_a = 2;
+  p.nbuf_b = 1;
+  p.nbuf_c = 2;
+  p.nstreams = 2;
+  p.precision = OOC_FP64;
+  p.slices = 0;
+  *plan = p;
+  return true;
+}
+
+// ---- cost model --------------------------------------------------------------------
+
+static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k, bool split, int slices) {
+  if (m <= 0 || n <= 0) return mc.kernel_launch_s;
+  const double tiles = (double)ceil_div(m, 128) * (double)ceil_div(n, 128);
+  const double slots = 2.0 * mc.cus;
+  const double waves = std::ceil(tiles / slots);
+  const double fill = tiles / (waves * slots);
+  const double keff = (double)k / ((double)k + 64.0);
+  if (k <= 0) return mc.kernel_launch_s + (double)m * n * 16.0 / 4e12;
+  double flops = 2.0 * m * n * k;
+  double rate;
+  if (split) {
+    const double products = slices * (slices + 1) / 2.0;
+    rate = mc.split_tflops_per_product * 1e12 / products;
+    // slicing passes over A and B (HBM bound)
+    const double slice_s = (double)(m + n) * k * (8.0 + 2.0 * slices) / 4e12;
+    return mc.kernel_launch_s * 3 + slice_s + flops / (rate * fill * keff);
+  }
+  rate = mc.kernel_tflops * 1e12;
+  return mc.kernel_launch_s + flops / (rate * fill * keff);
+}
+
+double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc_op>& ops) {
+  // Event-driven fluid simulation: copies in one direction share that
+  // direction's bandwidth, which drops to the duplex figure while the other
+  // direction is busy; kernels share the device equally.
+  const Machine& mc = machine();
+  const size_t n = ops.size();
+  if (n == 0) return 0.0;
+  std::vector<double> work(n), done_at(n, -1.0);
+  std::vector<int> cls(n);  // 0 H2D, 1 D2H, 2 kernel
+  for (size_t x = 0; x < n; ++x) {
+    const ooc_op& o = ops[x];
+    if (o.kind == OOC_OP_H2D) { cls[x] = 0; work[x] = (double)o.rows * o.cols * 8.0; }
+    else if (o.kind == OOC_OP_D2H) { cls[x] = 1; work[x] = (double)o.rows * o.cols * 8.0; }
+    else {
+      cls[x] = 2;
+      work[x] = kernel_seconds(mc, o.rows, o.cols, o.k, o.kind == OOC_OP_SPLIT_GEMM, plan.slices);
+    }
+  }
+  const int ns = plan.nstreams;
+  std::vector<std::vector<int>> q(ns);
+  for (size_t x = 0; x < n; ++x) q[ops[x].stream].push_back((int)x);
+  std::vector<size_t> head(ns, 0);
+  std::vector<double> remaining(work);
+  std::vector<double> lat(n, 0.0);  // latency left before a copy streams
+  for (size_t x = 0; x < n; ++x) lat[x] = cls[x] < 2 ? mc.copy_latency_s : 0.0;
+  std::vector<int> running;
+  double now = 0.0;
+  size_t completed = 0;
+  auto ready = [&](int x) {
+    const ooc_op& o = ops[x];
+    for (int k = 0; k < o.nwait; ++k)
+      if (done_at[o.wait[k]] < 0) return false;
+    return true;
+  };
+  std::vector<char> active(ns, 0);
+  while (completed < n) {
+    for (int s = 0; s < ns; ++s) {
+      if (active[s] || head[s] >= q[s].size()) continue;
+      int x = q[s][head[s]];
+      if (ready(x)) { running.push_back(x); active[s] = 1; }
+    }
+    if (running.empty()) return std::numeric_limits<double>::infinity();  // deadlock
+    int nh = 0, nd = 0, nk = 0;
+    for (int x : running) { if (lat[x] > 0) continue; if (cls[x] == 0) ++nh; else if (cls[x] == 1) ++nd; else ++nk; }
+    const double bw_h = (nd ? mc.duplex_gbs : mc.h2d_gbs) * 1e9;
+    const double bw_d = (nh ? mc.duplex_gbs : mc.d2h_gbs) * 1e9;
+    double dt = std::numeric_limits<double>::infinity();
+    std::vector<double> rate(running.size());
+    for (size_t r = 0; r < running.size(); ++r) {
+      int x = running[r];
+      if (lat[x] > 0) { rate[r] = 0; dt = std::min(dt, lat[x]); continue; }
+      if (cls[x] == 0) rate[r] = bw_h / nh;
+      else if (cls[x] == 1) rate[r] = bw_d / nd;
+      else rate[r] = 1.0 / nk;
+      dt = std::min(dt, remaining[x] / rate[r]);
+    }
+    now += dt;
+    std::vector<int> still;
+    for (size_t r = 0; r < running.size(); ++r) {
+      int x = running[r];
+      if (lat[x] > 0) { lat[x] -= dt; if (lat[x] < 1e-15) lat[x] = 0; still.push_back(x); continue; }
+      remaining[x] -= rate[r] * dt;
+      if (remaining[x] <= remaining[x] * 0 + 1e-12 * std::max(1.0, work[x])) {
+        done_at[x] = now;
+        ++completed;
+        active[ops[x].stream] = 0;
+        ++head[ops[x].stream];
+      } else {
+        still.push_back(x);
+      }
+    }
+    running.swap(still);
+  }
+  return now;
+}
+
+// ---- candidates ---------------------------------------------------------------------
+
+static std::vector<int64_t> split_sizes(int64_t n, int64_t align, int max_parts) {
+  std::set<int64_t> out;
+  for (int parts = 1; parts <= max_parts; ++parts) {
+    int64_t s = ceil_div(n, parts);
+    if (align > 1 && s > align) s = ceil_div(s, align) * align;
+    if (s >= 1) out.insert(std::min(s, n));
+  }
+  return std::vector<int64_t>(out.begin(), out.end());
+}
+
+static std::vector<int64_t> panel_sizes(int64_t K) {
+  std::set<int64_t> out;
+  out.insert(K);
+  for (int64_t d = 2; d <= 64; d *= 2) {
+    int64_t s = ceil_div(ceil_div(K, d), 64) * 64;
+    if (s >= 256 && s < K) out.insert(s);
+  }
+  return std::vector<int64_t>(out.begin(), out.end());
+}
+
+ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
+                           std::vector<ooc_plan_t>* plans, std::vector<double>* times) {
+  plans->clear();
+  times->clear();
+  const int64_t M = pb.M, N = pb.N, K = pb.keff();
+  const int prec = opts ? opts->precision : OOC_FP64;
+  const int slices = (opts && opts->slices > 0) ? opts->slices : 6;
+  const int want_streams = opts ? opts->nstreams : 0;
+  const Machine& mc = machine();
+  struct Cand { ooc_plan_t p; double lb; };
+  std::vector<Cand> cands;
+  auto consider = [&](ooc_plan_t p) {
+    Layout lay;
+    p.precision = prec;
+    p.slices = prec == OOC_SPLIT_BF16 ? slices : 0;
+    if (plan_layout(pb, p, &lay) != OOC_OK) return;
+    if (lay.bytes > budget_bytes) return;
+    // analytic lower bound: operand traffic vs link, flops vs kernel rate
+    const int64_t h = ceil_div(M, p.mb), w = ceil_div(N, p.nb);
+    const int64_t P = K > 0 ? ceil_div(K, p.kb) : 1;
+    double a_loads = 1, b_loads = 1;
+    switch (p.order) {
+      case OOC_ORDER_COLS: a_loads = (p.nbuf_a >= h * P) ? 1 : (double)w; b_loads = (P == 1 || p.nbuf_b >= P) ? 1 : (double)h; break;
+      case OOC_ORDER_ROWS: b_loads = (p.nbuf_b >= w * P) ? 1 : (double)h; a_loads = (P == 1 || p.nbuf_a >= P) ? 1 : (double)w; break;
+      case OOC_ORDER_COLS_P: a_loads = (double)w; b_loads = 1; break;
+      case OOC_ORDER_ROWS_P: a_loads = 1; b_loads = (double)h; break;
+    }
+    const double h2d = 8.0 * ((double)M * K * a_loads + (double)K * N * b_loads + (pb.beta != 0 ? (double)M * N : 0));
+    const double d2h = 8.0 * (double)M * N;
+    const double t_link = std::max(h2d / (mc.h2d_gbs * 1e9), d2h / (mc.d2h_gbs * 1e9));
+    const double t_comp = 2.0 * M * N * K / (mc.kernel_tflops * 1e12);
+    cands.push_back({p, std::max(t_link, t_comp) + (double)h * w * P * mc.kernel_launch_s});
+  };
+  const int max_parts = 64;
+  std::vector<int64_t> mbs = split_sizes(M, 128, max_parts), nbs = split_sizes(N, 128, max_parts);
+  std::vector<int64_t> kbs = K > 0 ? panel_sizes(K) : std::vector<int64_t>{0};
+  std::vector<int> stream_opts = {1, 2, 3};
+  if (want_streams >= 1 && want_streams <= 3) stream_opts = {want_streams};
+  for (int ns : stream_opts) {
+    for (int64_t mb : mbs) {
+      for (int64_t nb : nbs) {
+        const int64_t h = ceil_div(M, mb), w = ceil_div(N, nb);
+        for (int64_t kb : kbs) {
+          ooc_plan_t p{};
+          p.mb = mb; p.nb = nb; p.kb = kb; p.nstreams = ns;
+          const bool fullk = (K == 0 || kb >= K);
+          // the paper's structure and its transpose (K whole)
+          if (fullk) {
+            for (int nbr : {1, 2}) {
+              p.order = OOC_ORDER_COLS; p.nbuf_a = 2; p.nbuf_b = nbr; p.nbuf_c = 2; consider(p);
+              p.order = OOC_ORDER_ROWS; p.nbuf_a = nbr; p.nbuf_b = 2; p.nbuf_c = 2; consider(p);
+            }
+            if (h > 1 && h <= 8) { p.order = OOC_ORDER_COLS; p.nbuf_a = (int)h; p.nbuf_b = 2; p.nbuf_c = 2; consider(p); }
+            if (w > 1 && w <= 8) { p.order = OOC_ORDER_ROWS; p.nbuf_a = 2; p.nbuf_b = (int)w; p.nbuf_c = 2; consider(p); }
+          } else {
+            // C-stationary blocks with K panels streamed
+            p.nbuf_a = 2; p.nbuf_b = 2; p.nbuf_c = 2;
+            p.order = OOC_ORDER_COLS; consider(p);
+            p.order = OOC_ORDER_ROWS; consider(p);
+            // a resident column (row) of C blocks, K panels outside
+            if (h <= 64) { p.order = OOC_ORDER_COLS_P; p.nbuf_c = (int)h + 1; consider(p); }
+            if (w <= 64) { p.order = OOC_ORDER_ROWS_P; p.nbuf_c = (int)w + 1; consider(p); }
+          }
+        }
+      }
+    }
+  }
+  if (cands.empty()) return fail(OOC_ERR_BUDGET, "no plan fits in the device budget");
+  std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.lb < b.lb; });
+  const size_t keep = std::min<size_t>(cands.size(), 48);
+  std::vector<std::pair<double, ooc_plan_t>> sim;
+  for (size_t c = 0; c < keep; ++c) {
+    Layout lay;
+    plan_layout(pb, cands[c].p, &lay);
+    std::vector<ooc_op> ops;
+    if (build_schedule(pb, cands[c].p, lay, &ops) != OOC_OK) continue;
+    sim.push_back({simulate(pb, cands[c].p, ops), cands[c].p});
+  }
+  if (sim.empty()) return fail(OOC_ERR_BUDGET, "no schedulable plan fits in the device budget");
+  std::stable_sort(sim.begin(), sim.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  for (auto& s : sim) {
+    plans->push_back(s.second);
+    times->push_back(s.first);
+  }
+  return OOC_OK;
+}
+
+ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts, ooc_plan_t* plan,
+                       double* predicted) {
+  const int planner = opts ? opts->planner : OOC_PLAN_AUTO;
+  if (planner == OOC_PLAN_PAPER) {
+    if (!paper_plan(pb, budget_bytes, plan)) return fail(OOC_ERR_BUDGET, "the paper's partitioner finds no split that fits the budget");
+    if (opts && opts->precision == OOC_SPLIT_BF16) {
+      plan->precision = OOC_SPLIT_BF16;
+      plan->slices = opts->slices > 0 ? opts->slices : 6;
+    }
+    Layout lay;
+    ooc_status st = plan_layout(pb, *plan, &lay);
+    if (st != OOC_OK) return st;
+    if (lay.bytes > budget_bytes) return fail(OOC_ERR_BUDGET, "the paper's plan does not fit the budget with the split workspace");
+    if (predicted) {
+      std::vector<ooc_op> ops;
+      build_schedule(pb, *plan, lay, &ops);
+      *predicted = simulate(pb, *plan, ops);
+    }
+    return OOC_OK;
+  }
+  std::vector<ooc_plan_t> plans;
+  std::vector<double> times;
+  ooc_status st = plan_candidates(pb, budget_bytes, opts, &plans, &times);
+  if (st != OOC_OK) return st;
+  size_t best = 0;
+  if (planner == OOC_PLAN_MLP) {
+    std::vector<double> pred;
+    if (mlp_predict(pb, budget_bytes, plans, &pred)) {
+      for (size_t c = 1; c < pred.size(); ++c)
+        if (pred[c] < pred[best]) best = c;
+    }
+  }
+  *plan = plans[best];
+  if (predicted) *predicted = times[best];
+  return OOC_OK;
+}
+
+}  // namespace ooc

@@ -1,0 +1,283 @@
+// Plan -> operation list.
+//
+// The pipeline of the paper (Section V, Figs. 2-4) moves A slices, B slices
+// and C blocks into device buffers, multiplies, and moves C blocks back, with
+// events that keep a buffer from being overwritten while an operation still
+// reads it.  This builder generalises it: the C blocks (mb x nb) and K panels
+// (kb) form a grid of tile tasks walked in a chosen order; each operand has a
+// pool of device buffers; a panel stays resident until its buffer is needed
+// again (a buffer whose content has no later use goes first, then the least
+// recently used), and every reuse of a buffer waits for the last operation
+// that read its old content.  A C block occupies a buffer from its first K
+// panel until it is back on the host.  With the paper's configuration (order
+// by columns, K not split, A and C double-buffered, B single-buffered, two
+// streams by block parity) this reproduces the paper's ordering.
+#include <algorithm>
+#include <climits>
+#include <map>
+#include <string>
+
+#include "internal.hpp"
+
+namespace ooc {
+
+int64_t ceil_div(int64_t a, int64_t b) { return b <= 0 ? 0 : (a + b - 1) / b; }
+
+namespace {
+
+struct Task {
+  int64_t i, j, p;
+};
+
+struct Pool {
+  int n = 0;
+  std::vector<int64_t> key;       // content key per buffer (-1: empty)
+  std::vector<int64_t> last_use;  // task index of the last use
+  std::vector<int> last_reader;   // op index of the last kernel that read the buffer
+  std::vector<int> load_op;       // op index that loaded the current content
+  std::vector<int64_t> next_use;  // task index of the content's next use (INT64_MAX: none)
+  void init(int nb) {
+    n = nb;
+    key.assign(nb, -1);
+    last_use.assign(nb, -1);
+    last_reader.assign(nb, -1);
+    load_op.assign(nb, -1);
+    next_use.assign(nb, INT64_MAX);
+  }
+  int find(int64_t k) const {
+    for (int s = 0; s < n; ++s)
+      if (key[s] == k) return s;
+    return -1;
+  }
+  // Buffer to overwrite: an empty one, else one whose content is dead (least
+  // recently used first), else the least recently used.
+  int victim() const {
+    int best = -1;
+    for (int s = 0; s < n; ++s)
+      if (key[s] < 0) return s;
+    for (int s = 0; s < n; ++s)
+      if (next_use[s] == INT64_MAX && (best < 0 || last_use[s] < last_use[best])) best = s;
+    if (best >= 0) return best;
+    for (int s = 0; s < n; ++s)
+      if (best < 0 || last_use[s] < last_use[best]) best = s;
+    return best;
+  }
+};
+
+std::vector<Task> make_tasks(int order, int64_t h, int64_t w, int64_t P) {
+  std::vector<Task> t;
+  t.reserve((size_t)(h * w * P));
+  switch (order) {
+    case OOC_ORDER_COLS:
+      for (int64_t j = 0; j < w; ++j)
+        for (int64_t i = 0; i < h; ++i)
+          for (int64_t p = 0; p < P; ++p) t.push_back({i, j, p});
+      break;
+    case OOC_ORDER_ROWS:
+      for (int64_t i = 0; i < h; ++i)
+        for (int64_t j = 0; j < w; ++j)
+          for (int64_t p = 0; p < P; ++p) t.push_back({i, j, p});
+      break;
+    case OOC_ORDER_COLS_P:
+      for (int64_t j = 0; j < w; ++j)
+        for (int64_t p = 0; p < P; ++p)
+          for (int64_t i = 0; i < h; ++i) t.push_back({i, j, p});
+      break;
+    case OOC_ORDER_ROWS_P:
+      for (int64_t i = 0; i < h; ++i)
+        for (int64_t p = 0; p < P; ++p)
+          for (int64_t j = 0; j < w; ++j) t.push_back({i, j, p});
+      break;
+  }
+  return t;
+}
+
+// next_use[t] = index of the next task after t with the same key (INT64_MAX if none)
+std::vector<int64_t> next_uses(const std::vector<int64_t>& keys) {
+  std::vector<int64_t> nxt(keys.size(), INT64_MAX);
+  std::map<int64_t, int64_t> seen;
+  for (int64_t t = (int64_t)keys.size() - 1; t >= 0; --t) {
+    auto it = seen.find(keys[t]);
+    if (it != seen.end()) nxt[t] = it->second;
+    seen[keys[t]] = t;
+  }
+  return nxt;
+}
+
+}  // namespace
+
+ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layout& lay,
+                          std::vector<ooc_op>* ops_out) {
+  std::vector<ooc_op>& ops = *ops_out;
+  ops.clear();
+  const int64_t M = pb.M, N = pb.N, K = pb.keff();
+  if (M == 0 || N == 0) return OOC_OK;
+  const int64_t mb = plan.mb, nb = plan.nb;
+  const int64_t kb = K > 0 ? plan.kb : 0;
+  const int64_t h = ceil_div(M, mb), w = ceil_div(N, nb);
+  const int64_t P = K > 0 ? ceil_div(K, kb) : 1;
+  const bool split = plan.precision == OOC_SPLIT_BF16 && K > 0;
+  const int ns = plan.nstreams;
+
+  std::vector<Task> tasks = make_tasks(plan.order, h, w, P);
+  const int64_t T = (int64_t)tasks.size();
+  std::vector<int64_t> ka(T), kbk(T);
+  for (int64_t t = 0; t < T; ++t) {
+    ka[t] = tasks[t].i * P + tasks[t].p;
+    kbk[t] = tasks[t].p * w + tasks[t].j;
+  }
+  std::vector<int64_t> nxa = next_uses(ka), nxb = next_uses(kbk);
+
+  Pool pa, pbf, pc;
+  pa.init(K > 0 ? plan.nbuf_a : 0);
+  pbf.init(K > 0 ? plan.nbuf_b : 0);
+  pc.init(plan.nbuf_c);
+  // C bookkeeping: block key -> buffer, the op that last wrote it
+  std::vector<int> c_close(plan.nbuf_c, -1);    // D2H op that emptied the buffer
+  std::vector<int64_t> c_block(plan.nbuf_c, -1);  // open block key, -1 if free
+  std::vector<int> c_last_writer(plan.nbuf_c, -1);
+  std::vector<int64_t> c_closed_at(plan.nbuf_c, -1);
+
+  auto stream_of = [&](int kind, int64_t task) -> int {
+    if (ns == 3) return kind == OOC_OP_H2D ? 0 : (kind == OOC_OP_D2H ? 2 : 1);
+    if (ns == 2) return (int)(task % 2);
+    return 0;
+  };
+  // index of the last op on each stream (to drop waits already implied by stream order)
+  auto push = [&](ooc_op op, std::vector<int> waits) -> int {
+    op.stream = stream_of(op.kind, op.task);
+    std::sort(waits.begin(), waits.end());
+    waits.erase(std::unique(waits.begin(), waits.end()), waits.end());
+    op.nwait = 0;
+    for (int wv : waits) {
+      if (wv < 0) continue;
+      if (ops[wv].stream == op.stream) continue;  // earlier op on the same stream
+      if (op.nwait >= OOC_MAX_WAITS) return -1;
+      op.wait[op.nwait++] = wv;
+    }
+    ops.push_back(op);
+    return (int)ops.size() - 1;
+  };
+  auto blank = [&](int kind, int64_t task) {
+    ooc_op op{};
+    op.kind = kind;
+    op.task = (int32_t)task;
+    return op;
+  };
+
+  int64_t split_ws_a = lay.offW;  // slices of the current A and B panels (split path)
+  (void)split_ws_a;
+  for (int64_t t = 0; t < T; ++t) {
+    const Task& tk = tasks[t];
+    const int64_t i0 = tk.i * mb, m = std::min(mb, M - i0);
+    const int64_t j0 = tk.j * nb, n = std::min(nb, N - j0);
+    const int64_t k0 = tk.p * kb, k = K > 0 ? std::min(kb, K - k0) : 0;
+    int sa = -1, sb = -1;
+    if (K > 0) {
+      // A panel (i, p)
+      sa = pa.find(ka[t]);
+      if (sa < 0) {
+        sa = pa.victim();
+        ooc_op op = blank(OOC_OP_H2D, t);
+        op.mat = 0;
+        op.slot = sa;
+        op.row0 = i0; op.col0 = k0; op.rows = m; op.cols = k;
+        op.off_c = lay.offA + sa * lay.slotA; op.ld_c = k;
+        int x = push(op, {pa.last_reader[sa]});
+        if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+        pa.key[sa] = ka[t];
+        pa.load_op[sa] = x;
+      }
+      pa.last_use[sa] = t;
+      pa.next_use[sa] = nxa[t];
+      // B panel (p, j)
+      sb = pbf.find(kbk[t]);
+      if (sb < 0) {
+        sb = pbf.victim();
+        ooc_op op = blank(OOC_OP_H2D, t);
+        op.mat = 1;
+        op.slot = sb;
+        op.row0 = k0; op.col0 = j0; op.rows = k; op.cols = n;
+        op.off_c = lay.offB + sb * lay.slotB; op.ld_c = n;
+        int x = push(op, {pbf.last_reader[sb]});
+        if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+        pbf.key[sb] = kbk[t];
+        pbf.load_op[sb] = x;
+      }
+      pbf.last_use[sb] = t;
+      pbf.next_use[sb] = nxb[t];
+    }
+    // C block (i, j)
+    const int64_t ckey = tk.i * w + tk.j;
+    int sc = -1;
+    for (int s = 0; s < plan.nbuf_c; ++s)
+      if (c_block[s] == ckey) sc = s;
+    int c_dep = -1;
+    if (tk.p == 0) {
+      if (sc >= 0) return fail(OOC_ERR_ARG, "schedule: C block opened twice");
+      for (int s = 0; s < plan.nbuf_c; ++s) {
+        if (c_block[s] >= 0) continue;
+        if (sc < 0 || c_closed_at[s] < c_closed_at[sc]) sc = s;
+      }
+      if (sc < 0)
+        return fail(OOC_ERR_ARG, "plan has too few C buffers for its task order (nbuf_c=" +
+                                     std::to_string(plan.nbuf_c) + ")");
+      c_block[sc] = ckey;
+      c_dep = c_close[sc];  // previous content must be home before it is overwritten
+      if (pb.beta != 0.0) {
+        ooc_op op = blank(OOC_OP_H2D, t);
+        op.mat = 2;
+        op.slot = sc;
+        op.row0 = i0; op.col0 = j0; op.rows = m; op.cols = n;
+        op.off_c = lay.offC + sc * lay.slotC; op.ld_c = n;
+        int x = push(op, {c_close[sc]});
+        if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+        c_dep = x;
+      }
+    } else {
+      if (sc < 0) return fail(OOC_ERR_ARG, "schedule: C block not open");
+      c_dep = c_last_writer[sc];
+    }
+    // the tile product
+    ooc_op g = blank(split ? OOC_OP_SPLIT_GEMM : OOC_OP_GEMM, t);
+    g.slot = sc;
+    g.row0 = i0; g.col0 = j0; g.rows = m; g.cols = n;
+    g.k0 = k0; g.k = k;
+    if (K > 0) {
+      g.off_a = lay.offA + sa * lay.slotA; g.ld_a = k;
+      g.off_b = lay.offB + sb * lay.slotB; g.ld_b = n;
+    }
+    g.off_c = lay.offC + sc * lay.slotC; g.ld_c = n;
+    g.off_w = lay.offW; g.len_w = lay.lenW;
+    g.alpha = pb.alpha;
+    g.beta = tk.p == 0 ? pb.beta : 1.0;
+    std::vector<int> gw = {c_dep};
+    if (K > 0) {
+      gw.push_back(pa.load_op[sa]);
+      gw.push_back(pbf.load_op[sb]);
+    }
+    int gx = push(g, gw);
+    if (gx < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+    if (K > 0) {
+      pa.last_reader[sa] = gx;
+      pbf.last_reader[sb] = gx;
+    }
+    c_last_writer[sc] = gx;
+    // C block home after its last panel
+    if (tk.p == P - 1) {
+      ooc_op op = blank(OOC_OP_D2H, t);
+      op.mat = 2;
+      op.slot = sc;
+      op.row0 = i0; op.col0 = j0; op.rows = m; op.cols = n;
+      op.off_c = lay.offC + sc * lay.slotC; op.ld_c = n;
+      int x = push(op, {gx});
+      if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+      c_close[sc] = x;
+      c_block[sc] = -1;
+      c_closed_at[sc] = t;
+    }
+  }
+  return OOC_OK;
+}
+
+}  // namespace ooc

@@ -8,18 +8,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def pytest_configure(config):
-    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: long-running")
-
-
-@pytest.fixture(scope="session", autouse=True)
-def _built_helpers():
-    """Build the C helpers (generator, CPU reference) if they are not built yet."""
+def _ensure_built():
+    """Build what is not built yet: the generator, the CPU reference, the HIP library."""
     import synth
     import oracle
     if not os.path.exists(os.path.join(ROOT, "synth", "libsynth.so")):
         synth.build()
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build()
-    yield
+    if not os.path.exists(os.path.join(ROOT, "paper_1808_05056_amd", "libooc.so")):
+        from paper_1808_05056_amd import build as b
+        b.build()
+
+
+_ensure_built()
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: long-running")

@@ -1,0 +1,161 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads and exports
+every declared entry point, its partitioner agrees with the reference, its
+operation lists are race free and compute the reference product when run on
+the CPU in random legal orders, and it rejects bad arguments before touching
+a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import plan_ref, sched_ref
+import paper_1808_05056_amd as ooc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MiB, GiB = 1 << 20, 1 << 30
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "ooc.h")).read()
+    names = sorted(set(re.findall(r"^(?:ooc_status|const char\*)\s+(ooc_\w+)\s*\(", hdr, re.M)))
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(ooc._lib, n), n
+    assert set(names) == set(ooc.EXPORTS)
+
+
+def test_partition_matches_reference():
+    rng = np.random.default_rng(0)
+    cases = [(4, 4, 8, 44 * 8), (1024, 1024, 1024, 8 * MiB), (32768, 32768, 32768, 4 * GiB),
+             (65536, 16384, 32768, 8 * GiB), (262144, 8192, 8192, 2 * GiB)]
+    for _ in range(300):
+        M, N, K = (int(x) for x in rng.integers(1, 300, 3))
+        cases.append((M, N, K, int(rng.integers(8, 8 * (M * K + K * N + M * N) + 64))))
+    for M, N, K, b in cases:
+        assert ooc.ooc_partition(M, N, K, b) == plan_ref.partition(M, N, K, b // 8), (M, N, K, b)
+
+
+def test_paper_plan_footprint_is_the_papers():
+    for M, N, K, b in [(4, 4, 8, 44 * 8), (1024, 1024, 1024, 8 * MiB), (32768, 32768, 32768, 4 * GiB),
+                       (300, 200, 100, 200000)]:
+        p = ooc.ooc_plan(M, N, K, 0.5, b, ooc.make_opts(planner=ooc.PLAN_PAPER))
+        h, w = plan_ref.partition(M, N, K, b // 8)
+        assert (p.mb, p.nb, p.kb) == (-(-M // h), -(-N // w), K)
+        assert (p.order, p.nbuf_a, p.nbuf_b, p.nbuf_c, p.nstreams) == (ooc.ORDER_COLS, 2, 1, 2, 2)
+        assert ooc.ooc_plan_footprint(M, N, K, 0.5, p) == 8 * plan_ref.footprint(M, N, K, h, w) <= b
+
+
+def _problem(M, N, K, seed):
+    A = synth.matrix(M, K, synth.spec(seed, 0, synth.INT))
+    B = synth.matrix(K, N, synth.spec(seed, 1, synth.INT))
+    C = synth.matrix(M, N, synth.spec(seed, 2, synth.INT))
+    return A, B, C
+
+
+PLANS = [
+    # (M, N, K, plan)
+    (40, 36, 24, ooc.make_plan(10, 18, 24, ooc.ORDER_COLS, 2, 1, 2, 2)),   # the paper's configuration
+    (40, 36, 24, ooc.make_plan(10, 18, 24, ooc.ORDER_COLS, 2, 1, 2, 3)),
+    (40, 36, 24, ooc.make_plan(10, 18, 24, ooc.ORDER_COLS, 2, 2, 2, 3)),
+    (40, 36, 24, ooc.make_plan(10, 18, 24, ooc.ORDER_ROWS, 1, 2, 2, 3)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS, 2, 2, 2, 3)),     # ragged everywhere, K split
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS, 2, 2, 2, 2)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 6, 3)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 3, 2, 5, 3)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 5, 1)),
+    (41, 37, 29, ooc.make_plan(41, 37, 29, ooc.ORDER_COLS, 1, 1, 1, 3)),   # one block (in-core)
+    (41, 37, 29, ooc.make_plan(9, 37, 29, ooc.ORDER_COLS, 5, 1, 2, 3)),    # all A slices resident
+]
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.5])
+@pytest.mark.parametrize("case", range(len(PLANS)))
+def test_schedule_is_race_free_and_correct(case, beta):
+    M, N, K, plan = PLANS[case]
+    ops, arena = ooc.ooc_schedule(M, N, K, 1.5, beta, plan)
+    assert arena * 8 == ooc.ooc_plan_footprint(M, N, K, beta, plan)
+    assert sched_ref.check_hazards(ops) == []
+    assert sched_ref.check_cover(ops, M, N, K) == []
+    assert all(op["stream"] < plan.nstreams for op in ops)
+    A, B, C = _problem(M, N, K, 7 + case)
+    want, _ = oracle.gemm_rows(1.5, A, B, beta, C)
+    for seed in range(8):
+        Cw = C.copy() if beta != 0 else np.full_like(C, np.nan)
+        sched_ref.execute(ops, A, B, Cw, arena, seed=seed)
+        assert np.array_equal(Cw, want), seed
+
+
+def test_paper_configuration_implies_the_papers_event_order():
+    for (M, K, N, budget) in [(4, 8, 4, 44 * 8), (64, 30, 50, 3000 * 8)]:
+        h, w = plan_ref.partition(M, N, K, budget // 8)
+        p = ooc.ooc_plan(M, N, K, 0.5, budget, ooc.make_opts(planner=ooc.PLAN_PAPER))
+        for beta in (0.0, 0.5):
+            ops, arena = ooc.ooc_schedule(M, N, K, 1.0, beta, p)
+            assert arena <= budget // 8
+            reach = sched_ref.happens_before(ops)
+            names = sched_ref.logical_names(ops, h)
+            # a slice still resident in its buffer is not sent again: its
+            # arrival is the earlier copy of the same rows
+            for x, op in enumerate(ops):
+                if op["kind"] == "gemm" and (sched_ref.H2D_A, op["task"]) not in names:
+                    src = max(y for y in range(x) if ops[y]["kind"] == "h2d" and ops[y]["mat"] == "A"
+                              and ops[y]["row0"] == op["i0"])
+                    names[(sched_ref.H2D_A, op["task"])] = src
+                    names[("resident", op["task"])] = True
+            checked = 0
+            for later, earlier in sched_ref.paper_rules(h, w, beta != 0):
+                if later[0] == sched_ref.H2D_A and ("resident", later[1]) in names:
+                    continue  # no copy, so nothing to order
+                assert (reach[names[later]] >> names[earlier]) & 1, (later, earlier)
+                checked += 1
+            assert checked > 0
+
+
+def test_alpha_zero_and_k_zero_schedules_read_no_ab():
+    plan = ooc.make_plan(10, 9, 8, ooc.ORDER_COLS, 2, 1, 2, 3)
+    for (alpha, K) in [(0.0, 16), (1.0, 0)]:
+        ops, arena = ooc.ooc_schedule(30, 27, K, alpha, 0.5, plan)
+        assert not any(op["kind"] == "h2d" and op["mat"] in "AB" for op in ops)
+        C = synth.matrix(30, 27, synth.spec(3, 2, synth.INT))
+        Cw = C.copy()
+        sched_ref.execute(ops, np.full((30, max(K, 1)), np.nan), np.full((max(K, 1), 27), np.nan), Cw, arena)
+        assert np.array_equal(Cw, 0.5 * C)
+
+
+def test_candidates_fit_budget_and_are_sorted():
+    for (M, N, K, b) in [(32768, 32768, 32768, 4 * GiB), (8000, 9000, 7000, 512 * MiB), (1024, 1024, 1024, 8 * MiB)]:
+        plans, times = ooc.ooc_plan_candidates(M, N, K, 0.5, b)
+        assert plans and times == sorted(times)
+        for p in plans:
+            assert ooc.ooc_plan_footprint(M, N, K, 0.5, p) <= b
+        best = ooc.ooc_plan(M, N, K, 0.5, b)
+        assert ooc.ooc_plan_footprint(M, N, K, 0.5, best) <= b
+
+
+def test_argument_errors_before_device_access():
+    s, _ = ooc.ooc_gemm_raw(-1, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 1 << 20)
+    assert s == ooc.OOC_ERR_ARG
+    A = np.zeros((4, 4)); B = np.zeros((4, 4)); C = np.zeros((4, 4))
+    s, _ = ooc.ooc_gemm_raw(4, 4, 4, 1.0, A.ctypes.data, 3, B.ctypes.data, 4, 0.0, C.ctypes.data, 4, 1 << 20)
+    assert s == ooc.OOC_ERR_ARG and "lda" in ooc.ooc_last_error()
+    s, _ = ooc.ooc_gemm_raw(4, 4, 4, 1.0, A.ctypes.data, 4, B.ctypes.data, 4, 0.0, None, 4, 1 << 20)
+    assert s == ooc.OOC_ERR_ARG
+    s, _ = ooc.ooc_gemm_raw(4, 4, 4, 1.0, None, 4, B.ctypes.data, 4, 0.0, C.ctypes.data, 4, 1 << 20)
+    assert s == ooc.OOC_ERR_ARG
+    # nothing fits in 100 bytes
+    s, _ = ooc.ooc_gemm_raw(4, 4, 8, 1.0, A.ctypes.data, 8, B.ctypes.data, 4, 0.0, C.ctypes.data, 4, 100)
+    assert s == ooc.OOC_ERR_BUDGET
+    # empty problems return at once
+    s, _ = ooc.ooc_gemm_raw(0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, 0)
+    assert s == ooc.OOC_OK
+    # a plan larger than the budget is refused
+    plan = ooc.make_plan(4, 4, 8, ooc.ORDER_COLS, 1, 1, 1, 3)
+    st = ooc._lib.ooc_gemm_planned(4, 4, 8, 1.0, A.ctypes.data, 8, B.ctypes.data, 4, 0.0, C.ctypes.data, 4, 64,
+                                   ooc.ctypes.byref(plan), None, None)
+    assert st == ooc.OOC_ERR_BUDGET
+    bad = ooc.make_plan(0, 4, 8)
+    with pytest.raises(ooc.OOCError):
+        ooc.ooc_plan_footprint(4, 4, 8, 0.0, bad)
