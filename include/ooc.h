@@ -83,7 +83,10 @@ typedef struct {
                            block parity; 3: one stream each for H2D, kernels and D2H */
   int32_t precision;    /* ooc_precision */
   int32_t slices;       /* split-BF16 slice count s (1..8); ignored for FP64 */
-  int32_t reserved;
+  int32_t nbuf_d;       /* 0: each C block is loaded into its own buffer before its first K panel.
+                           >0 (beta != 0 only): C blocks start from zero and the initial C of a block
+                           is staged in one of nbuf_d extra buffers (mb x nb) and added, scaled by
+                           beta, at one K-panel step chosen to spread these copies over time */
 } ooc_plan_t;
 
 /* Options; a NULL pointer means all defaults (zero-initialised struct). */
@@ -96,6 +99,9 @@ typedef struct {
   int32_t profile;      /* 1: time every operation with HIP events (fills the busy times) */
   void* arena;          /* optional caller-owned device memory used instead of allocating */
   size_t arena_bytes;   /* its size; must be >= the plan's footprint */
+  double* timeline;     /* optional (profile == 1): receives start and end of op x, in seconds
+                           from the first op's start, at timeline[2x] and timeline[2x+1] */
+  int64_t timeline_cap; /* number of ops timeline can hold */
 } ooc_opts;
 
 /* Outcome of a call. */
@@ -160,12 +166,18 @@ ooc_status ooc_plan_candidates(int64_t M, int64_t N, int64_t K, double beta, siz
 ooc_status ooc_plan_predict(int64_t M, int64_t N, int64_t K, double beta, const ooc_plan_t* plan,
                             double* seconds);
 
+/* The cost model's timeline of the plan's operation list (host only): start and
+ * end of op x at times[2x], times[2x+1] (seconds).  *nops receives the op
+ * count; OOC_ERR_CAPACITY if it exceeds cap. */
+ooc_status ooc_plan_simulate(int64_t M, int64_t N, int64_t K, double beta, const ooc_plan_t* plan,
+                             double* times, int64_t cap, int64_t* nops);
+
 /* ---- the operation list (what the HIP backend issues), for inspection ---------- */
 
 typedef enum {
   OOC_OP_H2D = 0,        /* host submatrix -> device buffer (2-D pitched copy) */
   OOC_OP_D2H = 1,        /* device buffer -> host submatrix */
-  OOC_OP_GEMM = 2,       /* FP64 tile product c = alpha*a*b + beta*c on device buffers */
+  OOC_OP_GEMM = 2,       /* FP64 tile product c = alpha*a*b + beta*c + gamma*d on device buffers */
   OOC_OP_SPLIT_A = 3,    /* split-BF16: exponents and slices of an A panel into the workspace */
   OOC_OP_SPLIT_B = 4,    /* split-BF16: exponents and slices of a B panel into the workspace */
   OOC_OP_SPLIT_GEMM = 5  /* split-BF16 tile product from the slices in the workspace */
@@ -187,8 +199,10 @@ typedef struct {
   int64_t off_a, ld_a;        /* GEMM: arena element offset / leading dim of the A panel */
   int64_t off_b, ld_b;        /* GEMM: same for the B panel */
   int64_t off_c, ld_c;        /* GEMM: C block; copies: the device side of the copy */
+  int64_t off_d, ld_d;        /* GEMM: staged initial C block added with weight gamma */
   int64_t off_w, len_w;       /* split ops: workspace element offset and length */
-  double alpha, beta;         /* GEMM: effective scalars of this panel step */
+  double alpha, beta, gamma;  /* GEMM: effective scalars of this panel step (beta == 0: c not
+                                 read; gamma == 0: d not read) */
 } ooc_op;
 
 /* The operation list a plan produces (host only).  Writes up to cap ops;

@@ -25,6 +25,7 @@ An operation is a dict with keys
   stream, waits (list of earlier op indices), task
   copies: mat ('A'|'B'|'C'), row0, col0, rows, cols, dev_off, dev_ld (elements)
   gemm:   m, n, k, i0, j0, k0, off_a, lda, off_b, ldb, off_c, ldc, alpha, beta
+          and optionally off_d, ldd, gamma: c = alpha*a@b + beta*c + gamma*d
   other kernels: reads / writes, lists of (offset, rows, cols, ld) device regions.
 """
 import random
@@ -129,6 +130,8 @@ def _regions(op):
         reads = [(op["off_a"], op["m"], op["k"], op["lda"]), (op["off_b"], op["k"], op["n"], op["ldb"])]
         if op["beta"] != 0.0:
             reads.append((op["off_c"], op["m"], op["n"], op["ldc"]))
+        if op.get("gamma", 0.0) != 0.0:
+            reads.append((op["off_d"], op["m"], op["n"], op["ldd"]))
         return reads, [(op["off_c"], op["m"], op["n"], op["ldc"])]
     return list(op.get("reads", [])), list(op.get("writes", []))
 
@@ -241,6 +244,8 @@ def execute(ops, A, B, C, arena_elems, seed=0, poison=np.nan, kernels=None):
             res = op["alpha"] * prod
             if op["beta"] != 0.0:
                 res = res + op["beta"] * c
+            if op.get("gamma", 0.0) != 0.0:
+                res = res + op["gamma"] * view(op["off_d"], op["m"], op["n"], op["ldd"])
             c[...] = res
         else:
             if kernels is None or k not in kernels:

@@ -3,7 +3,7 @@
 Argument marshalling only: every step of the product (planning, scheduling,
 copies, tile kernels) runs in the native library.  Importing this package
 loads the built library and raises if it is missing; build it with
-``python -m paper_1808_05056_amd.build``.
+``python paper_1808_05056_amd/build.py``.
 
 Names follow the C ABI in include/ooc.h:
     ooc_gemm, ooc_gemm_planned, ooc_plan, ooc_plan_footprint, ooc_partition,
@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libooc.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1808_05056_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_1808_05056_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -42,18 +42,21 @@ i32, i64, u64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ct
 
 class ooc_plan_t(ctypes.Structure):
     _fields_ = [("mb", i64), ("nb", i64), ("kb", i64), ("order", i32), ("nbuf_a", i32), ("nbuf_b", i32),
-                ("nbuf_c", i32), ("nstreams", i32), ("precision", i32), ("slices", i32), ("reserved", i32)]
+                ("nbuf_c", i32), ("nstreams", i32), ("precision", i32), ("slices", i32), ("nbuf_d", i32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
     def __repr__(self):
         return "ooc_plan_t(" + ", ".join(f"{k}={v}" for k, v in self.as_dict().items()) + ")"
 
 
+P_dbl = ctypes.POINTER(ctypes.c_double)
+
+
 class ooc_opts(ctypes.Structure):
     _fields_ = [("device", i32), ("planner", i32), ("precision", i32), ("slices", i32), ("nstreams", i32),
-                ("profile", i32), ("arena", vp), ("arena_bytes", sz)]
+                ("profile", i32), ("arena", vp), ("arena_bytes", sz), ("timeline", P_dbl), ("timeline_cap", i64)]
 
 
 class ooc_stats(ctypes.Structure):
@@ -72,7 +75,8 @@ class ooc_op(ctypes.Structure):
     _fields_ = [("kind", i32), ("stream", i32), ("task", i32), ("nwait", i32), ("wait", i32 * MAX_WAITS),
                 ("mat", i32), ("slot", i32), ("row0", i64), ("col0", i64), ("rows", i64), ("cols", i64),
                 ("k0", i64), ("k", i64), ("off_a", i64), ("ld_a", i64), ("off_b", i64), ("ld_b", i64),
-                ("off_c", i64), ("ld_c", i64), ("off_w", i64), ("len_w", i64), ("alpha", dbl), ("beta", dbl)]
+                ("off_c", i64), ("ld_c", i64), ("off_d", i64), ("ld_d", i64), ("off_w", i64), ("len_w", i64),
+                ("alpha", dbl), ("beta", dbl), ("gamma", dbl)]
 
 
 P = ctypes.POINTER
@@ -93,6 +97,7 @@ _sig("ooc_plan_footprint", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(u64)])
 _sig("ooc_partition", i32, [i64, i64, i64, sz, P(i64), P(i64)])
 _sig("ooc_plan_candidates", i32, [i64, i64, i64, dbl, sz, P(ooc_opts), P(ooc_plan_t), P(dbl), i64, P(i64)])
 _sig("ooc_plan_predict", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(dbl)])
+_sig("ooc_plan_simulate", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(dbl), i64, P(i64)])
 _sig("ooc_schedule", i32, [i64, i64, i64, dbl, dbl, P(ooc_plan_t), P(ooc_op), i64, P(i64), P(u64)])
 _sig("ooc_host_alloc", i32, [P(vp), sz])
 _sig("ooc_host_free", i32, [vp])
@@ -106,7 +111,7 @@ _sig("ooc_last_error", ctypes.c_char_p, [])
 _sig("ooc_version", ctypes.c_char_p, [])
 
 EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
-           "ooc_plan_predict", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
+           "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_dgemm_device",
            "ooc_last_error", "ooc_version"]
 
@@ -141,12 +146,20 @@ def _mat_arg(X, name):
 
 
 def make_opts(device=0, planner=PLAN_AUTO, precision=FP64, slices=0, nstreams=0, profile=False, arena=None,
-              arena_bytes=0):
-    return ooc_opts(device, planner, precision, slices, nstreams, 1 if profile else 0, arena, arena_bytes)
+              arena_bytes=0, timeline=None):
+    """timeline: a float64 numpy array of 2*nops entries to receive per-op start/end (profile mode)."""
+    o = ooc_opts(device, planner, precision, slices, nstreams, 1 if profile else 0, arena, arena_bytes, None, 0)
+    if timeline is not None:
+        assert timeline.dtype == np.float64 and timeline.flags.c_contiguous
+        o.timeline = timeline.ctypes.data_as(P_dbl)
+        o.timeline_cap = timeline.size // 2
+        o._keep = timeline
+    return o
 
 
-def make_plan(mb, nb, kb, order=ORDER_COLS, nbuf_a=2, nbuf_b=1, nbuf_c=2, nstreams=3, precision=FP64, slices=0):
-    return ooc_plan_t(mb, nb, kb, order, nbuf_a, nbuf_b, nbuf_c, nstreams, precision, slices, 0)
+def make_plan(mb, nb, kb, order=ORDER_COLS, nbuf_a=2, nbuf_b=1, nbuf_c=2, nstreams=3, precision=FP64, slices=0,
+              nbuf_d=0):
+    return ooc_plan_t(mb, nb, kb, order, nbuf_a, nbuf_b, nbuf_c, nstreams, precision, slices, nbuf_d)
 
 
 # ---- entry points ---------------------------------------------------------------------
@@ -226,6 +239,18 @@ def ooc_plan_predict(M, N, K, beta, plan):
     return t.value
 
 
+def ooc_plan_simulate(M, N, K, beta, plan):
+    """The cost model's per-op (start, end) times, shape (nops, 2)."""
+    n = i64()
+    st = _lib.ooc_plan_simulate(M, N, K, beta, ctypes.byref(plan), None, 0, ctypes.byref(n))
+    if st not in (OOC_OK, OOC_ERR_CAPACITY):
+        _check(st)
+    t = np.zeros(2 * max(n.value, 1))
+    _check(_lib.ooc_plan_simulate(M, N, K, beta, ctypes.byref(plan), t.ctypes.data_as(P_dbl), n.value,
+                                  ctypes.byref(n)))
+    return t[: 2 * n.value].reshape(-1, 2)
+
+
 def ooc_schedule(M, N, K, alpha, beta, plan):
     """The operation list as dicts (keys as in the CPU schedule checker) and the arena size in elements."""
     n = i64()
@@ -246,8 +271,8 @@ def ooc_schedule(M, N, K, alpha, beta, plan):
                      dev_ld=o.ld_c)
         else:
             d.update(m=o.rows, n=o.cols, k=o.k, i0=o.row0, j0=o.col0, k0=o.k0, off_a=o.off_a, lda=o.ld_a,
-                     off_b=o.off_b, ldb=o.ld_b, off_c=o.off_c, ldc=o.ld_c, off_w=o.off_w, len_w=o.len_w,
-                     alpha=o.alpha, beta=o.beta)
+                     off_b=o.off_b, ldb=o.ld_b, off_c=o.off_c, ldc=o.ld_c, off_d=o.off_d, ldd=o.ld_d,
+                     off_w=o.off_w, len_w=o.len_w, alpha=o.alpha, beta=o.beta, gamma=o.gamma)
         ops.append(d)
     return ops, ab.value // 8
 

@@ -1,6 +1,6 @@
 """Build libooc.so (HIP for gfx950) in-tree with hipcc.
 
-python -m paper_1808_05056_amd.build      (or build() from Python)
+python paper_1808_05056_amd/build.py   (standalone: it does not import the package)
 """
 import concurrent.futures as cf
 import os

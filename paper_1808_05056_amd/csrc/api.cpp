@@ -119,7 +119,7 @@ struct HostMats {
 };
 
 ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>& ops, double* arena,
-                   const HostMats& hm, bool profile, ooc_stats* st) {
+                   const HostMats& hm, bool profile, double* timeline, int64_t timeline_cap, ooc_stats* st) {
   const size_t n = ops.size();
   std::vector<int> evidx(n, -1);
   size_t nev = 0;
@@ -176,7 +176,7 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
         }
         case OOC_OP_GEMM:
           e = launch_dgemm_f64(o.rows, o.cols, o.k, o.alpha, arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b,
-                               o.beta, arena + o.off_c, o.ld_c, s);
+                               o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d, s);
           break;
         default:
           status = OOC_ERR_ARG;
@@ -218,6 +218,15 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
       st->t_h2d_busy_s = th;
       st->t_d2h_busy_s = td;
       st->t_kernel_busy_s = tk;
+      if (timeline) {
+        for (size_t x = 0; x < issued && (int64_t)x < timeline_cap; ++x) {
+          float a = 0.f, b = 0.f;
+          if (hipEventElapsedTime(&a, c.tev[0], c.tev[2 * x]) != hipSuccess) a = -1.f;
+          if (hipEventElapsedTime(&b, c.tev[0], c.tev[2 * x + 1]) != hipSuccess) b = -1.f;
+          timeline[2 * x] = a * 1e-3;
+          timeline[2 * x + 1] = b * 1e-3;
+        }
+      }
     }
   }
   if (status != OOC_OK) return fail(status, msg);
@@ -307,7 +316,8 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
     arena = static_cast<double*>(c.arena);
   }
   HostMats hm{A, lda, B, ldb, C, ldc};
-  st = run_ops(c, plan, ops, arena, hm, opts && opts->profile, stats);
+  st = run_ops(c, plan, ops, arena, hm, opts && opts->profile, opts ? opts->timeline : nullptr,
+               opts ? opts->timeline_cap : 0, stats);
   if (stats) {
     stats->plan = plan;
     stats->t_total_s = now_s() - t_enter;
@@ -413,6 +423,27 @@ ooc_status ooc_plan_predict(int64_t M, int64_t N, int64_t K, double beta, const 
   st = build_schedule(pb, *plan, lay, &ops);
   if (st != OOC_OK) return st;
   *seconds = simulate(pb, *plan, ops);
+  return OOC_OK;
+}
+
+ooc_status ooc_plan_simulate(int64_t M, int64_t N, int64_t K, double beta, const ooc_plan_t* plan, double* times,
+                             int64_t cap, int64_t* nops) {
+  if (!plan || !nops) return fail(OOC_ERR_ARG, "NULL argument");
+  if (M <= 0 || N <= 0 || K < 0) return fail(OOC_ERR_ARG, "M and N must be positive, K non-negative");
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.beta = beta;
+  Layout lay;
+  ooc_status st = plan_layout(pb, *plan, &lay);
+  if (st != OOC_OK) return st;
+  std::vector<ooc_op> ops;
+  st = build_schedule(pb, *plan, lay, &ops);
+  if (st != OOC_OK) return st;
+  std::vector<double> tv;
+  simulate(pb, *plan, ops, &tv);
+  *nops = (int64_t)ops.size();
+  if (times)
+    for (int64_t x = 0; x < 2 * (int64_t)ops.size() && x < 2 * cap; ++x) times[x] = tv[x];
+  if ((int64_t)ops.size() > cap) return fail(OOC_ERR_CAPACITY, "more ops than cap");
   return OOC_OK;
 }
 
@@ -539,7 +570,8 @@ ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, dou
     HIPCHK(hipEventCreate(&e1), "hipEventCreate");
     HIPCHK(hipEventRecord(e0, s), "hipEventRecord");
   }
-  for (int x = 0; x < r; ++x) HIPCHK(launch_dgemm_f64(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, s), "dgemm launch");
+  for (int x = 0; x < r; ++x)
+    HIPCHK(launch_dgemm_f64(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 0.0, nullptr, 0, s), "dgemm launch");
   if (ms_out) HIPCHK(hipEventRecord(e1, s), "hipEventRecord");
   HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (ms_out) {

@@ -38,7 +38,7 @@ template <bool VEC>
 __global__ __launch_bounds__(NTHREADS, 2) void dgemm_f64_mfma(
     int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
-    int tiles_m, int tiles_n) {
+    double gamma, const double* __restrict__ D, int64_t ldd, int tiles_m, int tiles_n) {
   __shared__ __attribute__((aligned(16))) double As[2][BK][BM + PADA];
   __shared__ __attribute__((aligned(16))) double Bs[2][BK][BN + PADB];
 
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void dgemm_f64_mfma(
     __syncthreads();
   }
 
-  // ---- epilogue: C = alpha*acc + beta*C (C not read when beta == 0) --------------
+  // ---- epilogue: C = alpha*acc + beta*C + gamma*D (C, D not read when their weight is 0)
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void dgemm_f64_mfma(
           double* pc = C + row * ldc + col;
           double val = alpha * acc[i][j][v];
           if (beta != 0.0) val += beta * *pc;
+          if (gamma != 0.0) val += gamma * D[row * ldd + col];
           *pc = val;
         }
       }
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(NTHREADS, 2) void dgemm_f64_mfma(
 
 hipError_t launch_dgemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-                            hipStream_t stream) {
+                            double gamma, const double* D, int64_t ldd, hipStream_t stream) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const int tiles_m = (int)((m + BM - 1) / BM), tiles_n = (int)((n + BN - 1) / BN);
   const int64_t nt = (int64_t)tiles_m * tiles_n;
@@ -168,13 +169,14 @@ hipError_t launch_dgemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const
   const bool vec = ((lda & 1) == 0) && ((ldb & 1) == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0) &&
                    ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
   if (k <= 0) { A = nullptr; B = nullptr; }
+  if (gamma == 0.0) D = nullptr;
   dim3 grid((unsigned)nt), block(NTHREADS);
   if (vec)
     hipLaunchKernelGGL(dgemm_f64_mfma<true>, grid, block, 0, stream, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
-                       tiles_m, tiles_n);
+                       gamma, D, ldd, tiles_m, tiles_n);
   else
     hipLaunchKernelGGL(dgemm_f64_mfma<false>, grid, block, 0, stream, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
-                       tiles_m, tiles_n);
+                       gamma, D, ldd, tiles_m, tiles_n);
   return hipGetLastError();
 }
 

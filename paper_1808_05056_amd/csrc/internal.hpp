@@ -22,8 +22,9 @@ struct Problem {
 
 // Where the tile buffers live in the device arena (element offsets).
 struct Layout {
-  int64_t offA = 0, offB = 0, offC = 0, offW = 0;
-  int64_t slotA = 0, slotB = 0, slotC = 0;  // elements per buffer
+  int64_t offA = 0, offB = 0, offC = 0, offD = 0, offW = 0;
+  int64_t slotA = 0, slotB = 0, slotC = 0, slotD = 0;  // elements per buffer
+  int nbufD = 0;                                        // staging buffers for initial C in use
   int64_t lenW = 0;                         // split workspace elements
   uint64_t bytes = 0;                       // whole arena
 };
@@ -48,12 +49,16 @@ bool paper_partition(int64_t M, int64_t N, int64_t K, uint64_t budget_elems, int
 bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan);
 
 // Hardware figures the cost model uses.
+// Measured on an MI355X (PCIe Gen5 x16 host link, pinned host memory).
 struct Machine {
   double h2d_gbs = 57.6;      // pinned host -> device, one direction active (GB/s)
   double d2h_gbs = 57.1;      // device -> pinned host
   double duplex_gbs = 48.7;   // each direction when both are active
   double copy_latency_s = 12e-6;
-  double kernel_tflops = 60.0;  // sustained FP64 tile-kernel rate on large tiles
+  double kernel_tflops = 66.9;     // FP64 tile kernel, two workgroups per CU, large k
+  double kernel_tflops_1wg = 55.8; // same with one workgroup per CU
+  double kernel_k0 = 64.0;         // per-tile fixed cost in units of k
+  double kernel_scalar_factor = 1.15;  // odd leading dimensions (8-byte loads)
   double kernel_launch_s = 6e-6;
   double split_tflops_per_product = 1500.0; // BF16 slice-product rate (TFLOP/s of BF16 work)
   int cus = 256;
@@ -61,7 +66,9 @@ struct Machine {
 const Machine& machine();
 
 // Simulated time of an operation list under the cost model.
-double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc_op>& ops);
+// If times is not null it receives the start and end of every op.
+double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc_op>& ops,
+                std::vector<double>* times = nullptr);
 
 // Candidate plans (feasible within the budget) with modelled times, best first.
 ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,

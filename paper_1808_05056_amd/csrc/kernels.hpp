@@ -8,9 +8,10 @@
 
 namespace ooc {
 
-// C = alpha*A*B + beta*C, FP64 on matrix cores (row-major; k == 0 gives beta*C).
+// C = alpha*A*B + beta*C + gamma*D, FP64 on matrix cores (row-major; k == 0
+// gives beta*C + gamma*D; C is not read when beta == 0, D not when gamma == 0).
 hipError_t launch_dgemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
-                            hipStream_t stream);
+                            double gamma, const double* D, int64_t ldd, hipStream_t stream);
 
 }  // namespace ooc

@@ -39,6 +39,7 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
     return fail(OOC_ERR_ARG, "plan: unknown precision");
   if (plan.precision == OOC_SPLIT_BF16 && (plan.slices < 1 || plan.slices > 8))
     return fail(OOC_ERR_ARG, "plan: slices must be 1..8");
+  if (plan.nbuf_d < 0) return fail(OOC_ERR_ARG, "plan: nbuf_d must be >= 0");
   // clamp to the problem (a block larger than the matrix is the matrix)
   const int64_t mb = std::min(plan.mb, std::max<int64_t>(pb.M, 1));
   const int64_t nb = std::min(plan.nb, std::max<int64_t>(pb.N, 1));
@@ -54,7 +55,8 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
     L.offA = 0;
     L.offB = L.offA + (K > 0 ? L.slotA : 0);
     L.offC = L.offB + (K > 0 ? L.slotB : 0);
-    L.offW = L.offC + L.slotC;
+    L.offD = L.offC + L.slotC;
+    L.offW = L.offD;
   } else {
     L.slotA = mb * kb;
     L.slotB = kb * nb;
@@ -62,7 +64,13 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
     L.offA = 0;
     L.offB = L.offA + (K > 0 ? plan.nbuf_a * L.slotA : 0);
     L.offC = L.offB + (K > 0 ? plan.nbuf_b * L.slotB : 0);
-    L.offW = L.offC + plan.nbuf_c * L.slotC;
+    L.offD = L.offC + plan.nbuf_c * L.slotC;
+    // staging buffers for the initial C (only when C is read at all)
+    if (plan.nbuf_d > 0 && pb.beta != 0.0) {
+      L.nbufD = plan.nbuf_d;
+      L.slotD = mb * nb;
+    }
+    L.offW = L.offD + (int64_t)L.nbufD * L.slotD;
   }
   ooc_plan_t p2 = plan;
   p2.mb = mb; p2.nb = nb; p2.kb = kb;
@@ -128,25 +136,36 @@ bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan) {
 static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k, bool split, int slices) {
   if (m <= 0 || n <= 0) return mc.kernel_launch_s;
   const double tiles = (double)ceil_div(m, 128) * (double)ceil_div(n, 128);
-  const double slots = 2.0 * mc.cus;
-  const double waves = std::ceil(tiles / slots);
-  const double fill = tiles / (waves * slots);
-  const double keff = (double)k / ((double)k + 64.0);
   if (k <= 0) return mc.kernel_launch_s + (double)m * n * 16.0 / 4e12;
-  double flops = 2.0 * m * n * k;
-  double rate;
+  // every 128 x 128 tile costs the same; a CU runs two at a time (one if
+  // there are fewer tiles than CUs); a partial last wave of at most one tile
+  // per CU runs at the one-workgroup rate
+  const double tile_flops = 2.0 * 128.0 * 128.0 * (double)k * (1.0 + mc.kernel_k0 / (double)k);
+  const double r2 = mc.kernel_tflops * 1e12 / mc.cus;      // per CU, two tiles in flight
+  const double r1 = mc.kernel_tflops_1wg * 1e12 / mc.cus;  // per CU, one tile
+  double t;
+  if (tiles <= mc.cus) {
+    t = tile_flops / r1;
+  } else {
+    const double per_wave = 2.0 * mc.cus;
+    const double full = std::floor(tiles / per_wave);
+    const double rest = tiles - full * per_wave;
+    t = full * 2.0 * tile_flops / r2;
+    if (rest > mc.cus) t += 2.0 * tile_flops / r2;
+    else if (rest > 0) t += tile_flops / r1;
+  }
+  if ((k & 1) || (n & 1)) t *= mc.kernel_scalar_factor;
   if (split) {
     const double products = slices * (slices + 1) / 2.0;
-    rate = mc.split_tflops_per_product * 1e12 / products;
-    // slicing passes over A and B (HBM bound)
+    const double rate = mc.split_tflops_per_product * 1e12 / products;
     const double slice_s = (double)(m + n) * k * (8.0 + 2.0 * slices) / 4e12;
-    return mc.kernel_launch_s * 3 + slice_s + flops / (rate * fill * keff);
+    return mc.kernel_launch_s * 3 + slice_s + 2.0 * m * n * k / rate;
   }
-  rate = mc.kernel_tflops * 1e12;
-  return mc.kernel_launch_s + flops / (rate * fill * keff);
+  return mc.kernel_launch_s + t;
 }
 
-double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc_op>& ops) {
+double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc_op>& ops,
+                std::vector<double>* times) {
   // Event-driven fluid simulation: copies in one direction share that
   // direction's bandwidth, which drops to the duplex figure while the other
   // direction is busy; kernels share the device equally.
@@ -181,11 +200,16 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
     return true;
   };
   std::vector<char> active(ns, 0);
+  if (times) times->assign(2 * n, 0.0);
   while (completed < n) {
     for (int s = 0; s < ns; ++s) {
       if (active[s] || head[s] >= q[s].size()) continue;
       int x = q[s][head[s]];
-      if (ready(x)) { running.push_back(x); active[s] = 1; }
+      if (ready(x)) {
+        running.push_back(x);
+        active[s] = 1;
+        if (times) (*times)[2 * x] = now;
+      }
     }
     if (running.empty()) return std::numeric_limits<double>::infinity();  // deadlock
     int nh = 0, nd = 0, nk = 0;
@@ -208,8 +232,9 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
       int x = running[r];
       if (lat[x] > 0) { lat[x] -= dt; if (lat[x] < 1e-15) lat[x] = 0; still.push_back(x); continue; }
       remaining[x] -= rate[r] * dt;
-      if (remaining[x] <= remaining[x] * 0 + 1e-12 * std::max(1.0, work[x])) {
+      if (remaining[x] <= 1e-9 * std::max(1.0, work[x])) {
         done_at[x] = now;
+        if (times) (*times)[2 * x + 1] = now;
         ++completed;
         active[ops[x].stream] = 0;
         ++head[ops[x].stream];
@@ -274,8 +299,16 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
     const double h2d = 8.0 * ((double)M * K * a_loads + (double)K * N * b_loads + (pb.beta != 0 ? (double)M * N : 0));
     const double d2h = 8.0 * (double)M * N;
     const double t_link = std::max(h2d / (mc.h2d_gbs * 1e9), d2h / (mc.d2h_gbs * 1e9));
-    const double t_comp = 2.0 * M * N * K / (mc.kernel_tflops * 1e12);
-    cands.push_back({p, std::max(t_link, t_comp) + (double)h * w * P * mc.kernel_launch_s});
+    // kernel time from the tile model: full blocks plus the ragged edge blocks
+    const int64_t mr = M - (h - 1) * p.mb, nr = N - (w - 1) * p.nb;
+    const int64_t kr = K > 0 ? K - (P - 1) * p.kb : 0;
+    auto kt = [&](int64_t m, int64_t n) {
+      double t = (double)(P - 1) * kernel_seconds(mc, m, n, p.kb, prec == OOC_SPLIT_BF16, p.slices);
+      return t + kernel_seconds(mc, m, n, kr, prec == OOC_SPLIT_BF16, p.slices);
+    };
+    const double t_comp = (double)(h - 1) * (w - 1) * kt(p.mb, p.nb) + (double)(h - 1) * kt(p.mb, nr) +
+                          (double)(w - 1) * kt(mr, p.nb) + kt(mr, nr);
+    cands.push_back({p, std::max(t_link, t_comp)});
   };
   const int max_parts = 64;
   std::vector<int64_t> mbs = split_sizes(M, 128, max_parts), nbs = split_sizes(N, 128, max_parts);
@@ -300,12 +333,18 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
             if (w > 1 && w <= 8) { p.order = OOC_ORDER_ROWS; p.nbuf_a = 2; p.nbuf_b = (int)w; p.nbuf_c = 2; consider(p); }
           } else {
             // C-stationary blocks with K panels streamed
-            p.nbuf_a = 2; p.nbuf_b = 2; p.nbuf_c = 2;
-            p.order = OOC_ORDER_COLS; consider(p);
-            p.order = OOC_ORDER_ROWS; consider(p);
-            // a resident column (row) of C blocks, K panels outside
-            if (h <= 64) { p.order = OOC_ORDER_COLS_P; p.nbuf_c = (int)h + 1; consider(p); }
-            if (w <= 64) { p.order = OOC_ORDER_ROWS_P; p.nbuf_c = (int)w + 1; consider(p); }
+            for (int nd : {0, 1}) {
+              if (nd && pb.beta == 0.0) continue;
+              p.nbuf_d = nd;
+              p.nbuf_a = 2; p.nbuf_b = 2; p.nbuf_c = 2;
+              p.order = OOC_ORDER_COLS; consider(p);
+              p.order = OOC_ORDER_ROWS; consider(p);
+              // a resident column (row) of C blocks, K panels outside; with the
+              // initial C staged, no spare C buffer is needed at a column change
+              if (h <= 64) { p.order = OOC_ORDER_COLS_P; p.nbuf_c = (int)h + (nd ? 0 : 1); consider(p); }
+              if (w <= 64) { p.order = OOC_ORDER_ROWS_P; p.nbuf_c = (int)w + (nd ? 0 : 1); consider(p); }
+            }
+            p.nbuf_d = 0;
           }
         }
       }
@@ -313,7 +352,7 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
   }
   if (cands.empty()) return fail(OOC_ERR_BUDGET, "no plan fits in the device budget");
   std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.lb < b.lb; });
-  const size_t keep = std::min<size_t>(cands.size(), 48);
+  const size_t keep = std::min<size_t>(cands.size(), 96);
   std::vector<std::pair<double, ooc_plan_t>> sim;
   for (size_t c = 0; c < keep; ++c) {
     Layout lay;

@@ -49,17 +49,23 @@ struct Pool {
       if (key[s] == k) return s;
     return -1;
   }
-  // Buffer to overwrite: an empty one, else one whose content is dead (least
-  // recently used first), else the least recently used.
-  int victim() const {
-    int best = -1;
+  // Buffer to overwrite for task t: an empty one; else, leaving out the buffer
+  // the previous task read (its kernel is likely still running) unless it is
+  // the only one, a buffer whose content is dead (least recently used first),
+  // else the least recently used.
+  int victim(int64_t t) const {
     for (int s = 0; s < n; ++s)
       if (key[s] < 0) return s;
+    bool others = false;
     for (int s = 0; s < n; ++s)
-      if (next_use[s] == INT64_MAX && (best < 0 || last_use[s] < last_use[best])) best = s;
+      if (last_use[s] < t - 1) others = true;
+    auto eligible = [&](int s) { return !others || last_use[s] < t - 1; };
+    int best = -1;
+    for (int s = 0; s < n; ++s)
+      if (eligible(s) && next_use[s] == INT64_MAX && (best < 0 || last_use[s] < last_use[best])) best = s;
     if (best >= 0) return best;
     for (int s = 0; s < n; ++s)
-      if (best < 0 || last_use[s] < last_use[best]) best = s;
+      if (eligible(s) && (best < 0 || last_use[s] < last_use[best])) best = s;
     return best;
   }
 };
@@ -128,10 +134,19 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
   }
   std::vector<int64_t> nxa = next_uses(ka), nxb = next_uses(kbk);
 
-  Pool pa, pbf, pc;
+  Pool pa, pbf, pd;
   pa.init(K > 0 ? plan.nbuf_a : 0);
   pbf.init(K > 0 ? plan.nbuf_b : 0);
-  pc.init(plan.nbuf_c);
+  // staged initial C: the block starts from zero and beta*C_in is added at one
+  // K-panel step, spread over the panels so the copies do not bunch up
+  const bool staged = lay.nbufD > 0 && pb.beta != 0.0;
+  pd.init(staged ? lay.nbufD : 0);
+  auto fold_panel = [&](const Task& tk) -> int64_t {
+    if (!staged || P == 1) return 0;
+    if (plan.order == OOC_ORDER_COLS_P) return (tk.i * P) / h;
+    if (plan.order == OOC_ORDER_ROWS_P) return (tk.j * P) / w;
+    return P - 1;
+  };
   // C bookkeeping: block key -> buffer, the op that last wrote it
   std::vector<int> c_close(plan.nbuf_c, -1);    // D2H op that emptied the buffer
   std::vector<int64_t> c_block(plan.nbuf_c, -1);  // open block key, -1 if free
@@ -173,36 +188,36 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     const int64_t j0 = tk.j * nb, n = std::min(nb, N - j0);
     const int64_t k0 = tk.p * kb, k = K > 0 ? std::min(kb, K - k0) : 0;
     int sa = -1, sb = -1;
+    // loads this task needs, issued in the order their buffers become free
+    struct Load { ooc_op op; int war; int* load_op_slot; };
+    std::vector<Load> loads;
+    int c_load_placeholder = -1;
     if (K > 0) {
       // A panel (i, p)
       sa = pa.find(ka[t]);
       if (sa < 0) {
-        sa = pa.victim();
+        sa = pa.victim(t);
         ooc_op op = blank(OOC_OP_H2D, t);
         op.mat = 0;
         op.slot = sa;
         op.row0 = i0; op.col0 = k0; op.rows = m; op.cols = k;
         op.off_c = lay.offA + sa * lay.slotA; op.ld_c = k;
-        int x = push(op, {pa.last_reader[sa]});
-        if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+        loads.push_back({op, pa.last_reader[sa], &pa.load_op[sa]});
         pa.key[sa] = ka[t];
-        pa.load_op[sa] = x;
       }
       pa.last_use[sa] = t;
       pa.next_use[sa] = nxa[t];
       // B panel (p, j)
       sb = pbf.find(kbk[t]);
       if (sb < 0) {
-        sb = pbf.victim();
+        sb = pbf.victim(t);
         ooc_op op = blank(OOC_OP_H2D, t);
         op.mat = 1;
         op.slot = sb;
         op.row0 = k0; op.col0 = j0; op.rows = k; op.cols = n;
         op.off_c = lay.offB + sb * lay.slotB; op.ld_c = n;
-        int x = push(op, {pbf.last_reader[sb]});
-        if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+        loads.push_back({op, pbf.last_reader[sb], &pbf.load_op[sb]});
         pbf.key[sb] = kbk[t];
-        pbf.load_op[sb] = x;
       }
       pbf.last_use[sb] = t;
       pbf.next_use[sb] = nxb[t];
@@ -224,20 +239,39 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
                                      std::to_string(plan.nbuf_c) + ")");
       c_block[sc] = ckey;
       c_dep = c_close[sc];  // previous content must be home before it is overwritten
-      if (pb.beta != 0.0) {
+      if (pb.beta != 0.0 && !staged) {
         ooc_op op = blank(OOC_OP_H2D, t);
         op.mat = 2;
         op.slot = sc;
         op.row0 = i0; op.col0 = j0; op.rows = m; op.cols = n;
         op.off_c = lay.offC + sc * lay.slotC; op.ld_c = n;
-        int x = push(op, {c_close[sc]});
-        if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
-        c_dep = x;
+        loads.push_back({op, c_close[sc], &c_load_placeholder});
       }
     } else {
       if (sc < 0) return fail(OOC_ERR_ARG, "schedule: C block not open");
       c_dep = c_last_writer[sc];
     }
+    // staged initial C for this block, added at its fold panel
+    int sd = -1;
+    const bool fold_here = staged && tk.p == fold_panel(tk);
+    if (fold_here) {
+      sd = pd.victim(t);
+      ooc_op op = blank(OOC_OP_H2D, t);
+      op.mat = 2;
+      op.slot = -1 - sd;
+      op.row0 = i0; op.col0 = j0; op.rows = m; op.cols = n;
+      op.off_c = lay.offD + sd * lay.slotD; op.ld_c = n;
+      loads.push_back({op, pd.last_reader[sd], &pd.load_op[sd]});
+      pd.key[sd] = ckey;
+      pd.last_use[sd] = t;
+    }
+    std::stable_sort(loads.begin(), loads.end(), [](const Load& a, const Load& b) { return a.war < b.war; });
+    for (Load& L : loads) {
+      int x = push(L.op, {L.war});
+      if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
+      *L.load_op_slot = x;
+    }
+    if (c_load_placeholder >= 0) c_dep = c_load_placeholder;
     // the tile product
     ooc_op g = blank(split ? OOC_OP_SPLIT_GEMM : OOC_OP_GEMM, t);
     g.slot = sc;
@@ -250,18 +284,26 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     g.off_c = lay.offC + sc * lay.slotC; g.ld_c = n;
     g.off_w = lay.offW; g.len_w = lay.lenW;
     g.alpha = pb.alpha;
-    g.beta = tk.p == 0 ? pb.beta : 1.0;
+    g.beta = tk.p == 0 ? (staged ? 0.0 : pb.beta) : 1.0;
+    g.gamma = 0.0;
+    if (fold_here) {
+      g.off_d = lay.offD + sd * lay.slotD;
+      g.ld_d = n;
+      g.gamma = pb.beta;
+    }
     std::vector<int> gw = {c_dep};
     if (K > 0) {
       gw.push_back(pa.load_op[sa]);
       gw.push_back(pbf.load_op[sb]);
     }
+    if (fold_here) gw.push_back(pd.load_op[sd]);
     int gx = push(g, gw);
     if (gx < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
     if (K > 0) {
       pa.last_reader[sa] = gx;
       pbf.last_reader[sb] = gx;
     }
+    if (fold_here) pd.last_reader[sd] = gx;
     c_last_writer[sc] = gx;
     // C block home after its last panel
     if (tk.p == P - 1) {

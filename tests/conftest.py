@@ -17,8 +17,11 @@ def _ensure_built():
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build()
     if not os.path.exists(os.path.join(ROOT, "paper_1808_05056_amd", "libooc.so")):
-        from paper_1808_05056_amd import build as b
-        b.build()
+        import importlib.util
+        spec = importlib.util.spec_from_file_location("ooc_build", os.path.join(ROOT, "paper_1808_05056_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
 
 
 _ensure_built()
