@@ -68,6 +68,13 @@ PLANS = [
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 5, 1)),
     (41, 37, 29, ooc.make_plan(41, 37, 29, ooc.ORDER_COLS, 1, 1, 1, 3)),   # one block (in-core)
     (41, 37, 29, ooc.make_plan(9, 37, 29, ooc.ORDER_COLS, 5, 1, 2, 3)),    # all A slices resident
+    # initial C staged and folded at a spread K panel
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 5, 3, nbuf_d=1)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 2, 2, 4, 3, nbuf_d=2)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS, 2, 2, 2, 3, nbuf_d=1)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS, 2, 2, 2, 2, nbuf_d=1)),
+    (41, 37, 29, ooc.make_plan(9, 10, 29, ooc.ORDER_COLS, 2, 1, 2, 3, nbuf_d=1)),  # one panel: fold at once
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 5, 1, nbuf_d=1)),
 ]
 
 

@@ -83,6 +83,8 @@ SMALL_PLANS = [
     ("colsp", ooc.make_plan(256, 256, 256, ooc.ORDER_COLS_P, 2, 2, 5, 3), None),
     ("rowsp-2s", ooc.make_plan(200, 300, 192, ooc.ORDER_ROWS_P, 2, 2, 5, 2), None),
     ("one-stream", ooc.make_plan(128, 512, 1024, ooc.ORDER_COLS, 2, 1, 2, 1), None),
+    ("colsp-staged", ooc.make_plan(256, 256, 256, ooc.ORDER_COLS_P, 2, 2, 4, 3, nbuf_d=1), None),
+    ("rows-ksplit-staged", ooc.make_plan(384, 256, 320, ooc.ORDER_ROWS, 2, 2, 2, 3, nbuf_d=1), None),
 ]
 
 
