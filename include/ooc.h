@@ -50,6 +50,12 @@ typedef enum {
   OOC_ERR_CAPACITY = 8    /* an output array is too small (ooc_schedule, ooc_plan_candidates) */
 } ooc_status;
 
+/* FP64: tile products in FP64 on matrix cores.  SPLIT_BF16: each tile product
+ * is formed from s BF16 slices per operand (error-free splitting, Ozaki et al.
+ * 2012): slice products are exact with FP32 accumulation over chunks of 64,
+ * chunk sums are added exactly in FP64, and the weighted slice sums are
+ * combined in FP64; only the slices beyond s are dropped (truncation error
+ * about (s+1) 2^(-8s) relative to (|A||B|)_ij times the row/column spread). */
 typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1 } ooc_precision;
 
 /* How a plan is chosen.  PAPER: the paper's partitioner (Section V: fewest
@@ -178,12 +184,11 @@ typedef enum {
   OOC_OP_H2D = 0,        /* host submatrix -> device buffer (2-D pitched copy) */
   OOC_OP_D2H = 1,        /* device buffer -> host submatrix */
   OOC_OP_GEMM = 2,       /* FP64 tile product c = alpha*a*b + beta*c + gamma*d on device buffers */
-  OOC_OP_SPLIT_A = 3,    /* split-BF16: exponents and slices of an A panel into the workspace */
-  OOC_OP_SPLIT_B = 4,    /* split-BF16: exponents and slices of a B panel into the workspace */
-  OOC_OP_SPLIT_GEMM = 5  /* split-BF16 tile product from the slices in the workspace */
+  OOC_OP_SPLIT_GEMM = 3  /* the same product from BF16 slices: slices and exponents of the A and B
+                            panels are written to the workspace (off_w, len_w), then multiplied */
 } ooc_op_kind;
 
-#define OOC_MAX_WAITS 4
+#define OOC_MAX_WAITS 6
 
 typedef struct {
   int32_t kind;               /* ooc_op_kind */
@@ -232,6 +237,15 @@ ooc_status ooc_release(int32_t device);
 ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, double alpha,
                             const double* A, int64_t lda, const double* B, int64_t ldb,
                             double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
+
+/* The split-BF16 tile product on device pointers (s = slices, 1..8): the
+ * error-free slicing of Ozaki et al. (2012) on BF16 matrix cores with exact
+ * FP32 chunk sums (see ooc_precision).  Row-major; C = alpha*A*B + beta*C
+ * rounded as alpha*S + beta*C with separate roundings.  The call allocates
+ * and frees its own workspace.  ms_out as for ooc_dgemm_device. */
+ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
+                                 const double* A, int64_t lda, const double* B, int64_t ldb,
+                                 double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
 
 /* ---- messages and version ----------------------------------------------------- */
 

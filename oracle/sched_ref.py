@@ -126,8 +126,15 @@ def _regions(op):
         return [], [(op["dev_off"], op["rows"], op["cols"], op["dev_ld"])]
     if k == "d2h":
         return [(op["dev_off"], op["rows"], op["cols"], op["dev_ld"])], []
-    if k == "gemm":
+    if k in ("gemm", "split_gemm"):
         reads = [(op["off_a"], op["m"], op["k"], op["lda"]), (op["off_b"], op["k"], op["n"], op["ldb"])]
+        if k == "split_gemm" and op.get("len_w", 0) > 0:
+            ws = (op["off_w"], 1, op["len_w"], op["len_w"])
+            if op["beta"] != 0.0:
+                reads.append((op["off_c"], op["m"], op["n"], op["ldc"]))
+            if op.get("gamma", 0.0) != 0.0:
+                reads.append((op["off_d"], op["m"], op["n"], op["ldd"]))
+            return reads + [ws], [(op["off_c"], op["m"], op["n"], op["ldc"]), ws]
         if op["beta"] != 0.0:
             reads.append((op["off_c"], op["m"], op["n"], op["ldc"]))
         if op.get("gamma", 0.0) != 0.0:

@@ -33,9 +33,9 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_BUDGET", 3: "ERR_DEVICE_MEM", 4: 
 FP64, SPLIT_BF16 = 0, 1
 PLAN_AUTO, PLAN_PAPER, PLAN_MODEL, PLAN_MLP = 0, 1, 2, 3
 ORDER_COLS, ORDER_ROWS, ORDER_COLS_P, ORDER_ROWS_P = 0, 1, 2, 3
-OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_A, OP_SPLIT_B, OP_SPLIT_GEMM = range(6)
-OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_a", 4: "split_b", 5: "split_gemm"}
-MAX_WAITS = 4
+OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM = range(4)
+OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_gemm"}
+MAX_WAITS = 6
 
 i32, i64, u64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -107,13 +107,14 @@ _sig("ooc_copy_to_device", i32, [i32, vp, vp, sz])
 _sig("ooc_copy_to_host", i32, [i32, vp, vp, sz])
 _sig("ooc_release", i32, [i32])
 _sig("ooc_dgemm_device", i32, [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
+_sig("ooc_split_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 _sig("ooc_last_error", ctypes.c_char_p, [])
 _sig("ooc_version", ctypes.c_char_p, [])
 
 EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_dgemm_device",
-           "ooc_last_error", "ooc_version"]
+           "ooc_split_gemm_device", "ooc_last_error", "ooc_version"]
 
 
 class OOCError(RuntimeError):
@@ -279,6 +280,13 @@ def ooc_schedule(M, N, K, alpha, beta, plan):
 
 def ooc_release(device=-1):
     _check(_lib.ooc_release(device))
+
+
+def ooc_split_gemm_device(m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps=1, timed=False, device=0):
+    ms = dbl()
+    _check(_lib.ooc_split_gemm_device(device, m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps,
+                                      ctypes.byref(ms) if timed else None))
+    return ms.value if timed else None
 
 
 def ooc_dgemm_device(m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps=1, timed=False, device=0):

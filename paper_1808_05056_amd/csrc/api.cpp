@@ -178,6 +178,11 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
           e = launch_dgemm_f64(o.rows, o.cols, o.k, o.alpha, arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b,
                                o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d, s);
           break;
+        case OOC_OP_SPLIT_GEMM:
+          e = launch_split_gemm(o.rows, o.cols, o.k, plan.slices, o.alpha, arena + o.off_a, o.ld_a, arena + o.off_b,
+                                o.ld_b, o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d,
+                                arena + o.off_w, (size_t)o.len_w * 8, s);
+          break;
         default:
           status = OOC_ERR_ARG;
           msg = "operation kind not supported by this build";
@@ -581,6 +586,46 @@ ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, dou
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
+  return OOC_OK;
+}
+
+ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
+                                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                                 int64_t ldc, int32_t reps, double* ms_out) {
+  if (m < 0 || n < 0 || k < 0) return fail(OOC_ERR_ARG, "negative size");
+  if (s < 1 || s > 8) return fail(OOC_ERR_ARG, "slices must be 1..8");
+  if (m == 0 || n == 0) return OOC_OK;
+  if (!C || ldc < n) return fail(OOC_ERR_ARG, "bad C or ldc");
+  if (k > 0 && (!A || !B || lda < k || ldb < n)) return fail(OOC_ERR_ARG, "bad A, B, lda or ldb");
+  ooc_status st = ensure_device(device);
+  if (st != OOC_OK) return st;
+  DevCtx& c = g_dev[device];
+  std::lock_guard<std::mutex> lock(c.mu);
+  hipStream_t strm = c.st[1];
+  const size_t wsb = split_workspace_bytes(m, n, k, s);
+  void* ws = nullptr;
+  HIPCHK(hipMalloc(&ws, wsb), "hipMalloc workspace");
+  const int r = reps > 0 ? reps : 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  if (ms_out) {
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, strm);
+  }
+  for (int x = 0; x < r && e == hipSuccess; ++x)
+    e = launch_split_gemm(m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, 0.0, nullptr, 0, ws, wsb, strm);
+  if (e == hipSuccess && ms_out) e = hipEventRecord(e1, strm);
+  if (e == hipSuccess) e = hipStreamSynchronize(strm);
+  if (e == hipSuccess && ms_out) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, e0, e1);
+    *ms_out = ms / r;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(ws);
+  if (e != hipSuccess) return hip_fail(e, "split gemm");
   return OOC_OK;
 }
 

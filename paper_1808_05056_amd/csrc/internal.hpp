@@ -45,8 +45,9 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
 // The paper's partitioner (Section V); false if nothing fits.
 bool paper_partition(int64_t M, int64_t N, int64_t K, uint64_t budget_elems, int64_t* h, int64_t* w);
 
-// The plan the paper's MMOOC runs for a problem (two streams, A and C double-buffered).
-bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan);
+// The plan the paper's MMOOC runs for a problem (two streams, A and C
+// double-buffered, B single-buffered), with the given tile precision.
+bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan, int precision, int slices);
 
 // Hardware figures the cost model uses.
 // Measured on an MI355X (PCIe Gen5 x16 host link, pinned host memory).

@@ -14,4 +14,11 @@ hipError_t launch_dgemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const
                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                             double gamma, const double* D, int64_t ldd, hipStream_t stream);
 
+// Split-BF16 tile product (s slices): same result contract as launch_dgemm_f64
+// up to the split scheme's error; uses `workspace` (split_workspace_bytes).
+size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s);
+hipError_t launch_split_gemm(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
+                             const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream);
+
 }  // namespace ooc

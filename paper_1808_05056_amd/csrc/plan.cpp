@@ -7,6 +7,7 @@
 #include <tuple>
 
 #include "internal.hpp"
+#include "kernels.hpp"
 
 namespace ooc {
 
@@ -17,14 +18,8 @@ const Machine& machine() {
 
 int64_t split_workspace_elems(const Problem& pb, const ooc_plan_t& plan) {
   if (plan.precision != OOC_SPLIT_BF16 || pb.keff() == 0) return 0;
-  // BF16 slices of one A panel and one B panel (2 bytes each, s planes), the
-  // per-row and per-column exponents (int32), counted in 8-byte elements.
-  const int64_t s = plan.slices;
-  const int64_t kpad = ceil_div(plan.kb, 64) * 64;
-  const int64_t mpad = ceil_div(plan.mb, 256) * 256, npad = ceil_div(plan.nb, 256) * 256;
-  const int64_t slice_bytes = 2 * s * (mpad * kpad + kpad * npad);
-  const int64_t exp_bytes = 4 * (mpad + npad);
-  return ceil_div(slice_bytes + exp_bytes, 8) + 64;
+  // BF16 slice planes of one A panel and one B panel plus their exponents
+  return ceil_div((int64_t)split_workspace_bytes(plan.mb, plan.nb, plan.kb, plan.slices), 8);
 }
 
 ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
@@ -112,23 +107,50 @@ bool paper_partition(int64_t M, int64_t N, int64_t K, uint64_t budget_elems, int
   return false;
 }
 
-bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan) {
-  int64_t h = 1, w = 1;
+bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan, int precision, int slices) {
+  // The paper's rule (fewest w, then fewest h) over the plan's full device
+  // layout; for FP64 the layout is exactly the partitioner's footprint, for
+  // split-BF16 it adds the slice workspace, which also shrinks as h grows.
   const int64_t K = pb.keff();
-  if (!paper_partition(pb.M, pb.N, K, budget_bytes / 8, &h, &w)) return false;
-  ooc_plan_t p{};
-  p.mb = ceil_div(pb.M, h);
-  p.nb = ceil_div(pb.N, w);
-  p.kb = K;
-  p.order = OOC_ORDER_COLS;
-  p.nbuf_a = 2;
-  p.nbuf_b = 1;
-  p.nbuf_c = 2;
-  p.nstreams = 2;
-  p.precision = OOC_FP64;
-  p.slices = 0;
-  *plan = p;
-  return true;
+  auto make = [&](int64_t h, int64_t w) {
+    ooc_plan_t p{};
+    p.mb = ceil_div(pb.M, h);
+    p.nb = ceil_div(pb.N, w);
+    p.kb = K;
+    p.order = OOC_ORDER_COLS;
+    p.nbuf_a = 2;
+    p.nbuf_b = 1;
+    p.nbuf_c = 2;
+    p.nstreams = 2;
+    p.precision = precision;
+    p.slices = precision == OOC_SPLIT_BF16 ? slices : 0;
+    p.nbuf_d = 0;
+    return p;
+  };
+  auto fits = [&](int64_t h, int64_t w) {
+    Layout lay;
+    if (plan_layout(pb, make(h, w), &lay) != OOC_OK) return false;
+    return lay.bytes <= budget_bytes;
+  };
+  if (precision == OOC_FP64) {
+    int64_t h = 1, w = 1;
+    if (!paper_partition(pb.M, pb.N, K, budget_bytes / 8, &h, &w)) return false;
+    *plan = make(h, w);
+    return true;
+  }
+  for (int64_t w = 1; w <= pb.N; ++w) {
+    if (!proper_split(pb.N, w)) continue;
+    if (fits(1, w)) { *plan = make(1, w); return true; }
+    if (pb.M == 1 || !fits(pb.M, w)) continue;
+    int64_t lo = 1, hi = pb.M;
+    while (hi - lo > 1) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (fits(mid, w)) hi = mid; else lo = mid;
+    }
+    *plan = make(hi, w);
+    return true;
+  }
+  return false;
 }
 
 // ---- cost model --------------------------------------------------------------------
@@ -374,11 +396,10 @@ ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts*
                        double* predicted) {
   const int planner = opts ? opts->planner : OOC_PLAN_AUTO;
   if (planner == OOC_PLAN_PAPER) {
-    if (!paper_plan(pb, budget_bytes, plan)) return fail(OOC_ERR_BUDGET, "the paper's partitioner finds no split that fits the budget");
-    if (opts && opts->precision == OOC_SPLIT_BF16) {
-      plan->precision = OOC_SPLIT_BF16;
-      plan->slices = opts->slices > 0 ? opts->slices : 6;
-    }
+    const int prec = opts ? opts->precision : OOC_FP64;
+    const int sl = (opts && opts->slices > 0) ? opts->slices : 6;
+    if (!paper_plan(pb, budget_bytes, plan, prec, sl))
+      return fail(OOC_ERR_BUDGET, "the paper's partitioner finds no split that fits the budget");
     Layout lay;
     ooc_status st = plan_layout(pb, *plan, &lay);
     if (st != OOC_OK) return st;

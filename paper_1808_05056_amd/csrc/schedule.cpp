@@ -180,8 +180,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     return op;
   };
 
-  int64_t split_ws_a = lay.offW;  // slices of the current A and B panels (split path)
-  (void)split_ws_a;
+  int last_ws = -1;  // last split op, which used the (single) slice workspace
   for (int64_t t = 0; t < T; ++t) {
     const Task& tk = tasks[t];
     const int64_t i0 = tk.i * mb, m = std::min(mb, M - i0);
@@ -297,7 +296,9 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
       gw.push_back(pbf.load_op[sb]);
     }
     if (fold_here) gw.push_back(pd.load_op[sd]);
+    if (split) gw.push_back(last_ws);
     int gx = push(g, gw);
+    if (split) last_ws = gx;
     if (gx < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
     if (K > 0) {
       pa.last_reader[sa] = gx;

@@ -166,3 +166,48 @@ def test_argument_errors_before_device_access():
     bad = ooc.make_plan(0, 4, 8)
     with pytest.raises(ooc.OOCError):
         ooc.ooc_plan_footprint(4, 4, 8, 0.0, bad)
+
+
+SPLIT_PLANS = [
+    (41, 37, 29, ooc.make_plan(9, 10, 29, ooc.ORDER_COLS, 2, 1, 2, 2, precision=ooc.SPLIT_BF16, slices=3)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 5, 2, precision=ooc.SPLIT_BF16, slices=2, nbuf_d=1)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=1)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SPLIT_PLANS)))
+def test_split_schedule_race_free(case):
+    from oracle import split_ref
+    M, N, K, plan = SPLIT_PLANS[case]
+    ops, arena = ooc.ooc_schedule(M, N, K, 1.0, 0.5, plan)
+    assert any(op["kind"] == "split_gemm" and op["len_w"] > 0 for op in ops)
+    assert sched_ref.check_hazards(ops) == []
+    assert sched_ref.check_cover(ops, M, N, K) == []
+    A, B, C = _problem(M, N, K, 30 + case)
+    want, _ = oracle.gemm_rows(1.0, A, B, 0.5, C)
+
+    def split_model(op, ar):
+        def view(off, r, c, ld):
+            return np.lib.stride_tricks.as_strided(ar[off:], shape=(r, c), strides=(ld * 8, 8))
+        a = view(op["off_a"], op["m"], op["k"], op["lda"])
+        b = view(op["off_b"], op["k"], op["n"], op["ldb"])
+        c = view(op["off_c"], op["m"], op["n"], op["ldc"])
+        res = op["alpha"] * split_ref.slice_sum(np.array(a), np.array(b), plan.slices)
+        if op["beta"] != 0.0:
+            res = res + op["beta"] * c
+        if op["gamma"] != 0.0:
+            res = res + op["gamma"] * view(op["off_d"], op["m"], op["n"], op["ldd"])
+        c[...] = res
+        ar[op["off_w"]:op["off_w"] + op["len_w"]] = np.nan  # scribble over the workspace
+
+    for seed in range(4):
+        Cw = C.copy()
+        sched_ref.execute(ops, A, B, Cw, arena, seed=seed, kernels={"split_gemm": split_model})
+        assert np.array_equal(Cw, want)
+
+
+def test_split_footprint_counts_workspace():
+    p64 = ooc.make_plan(512, 512, 1024, ooc.ORDER_COLS, 2, 1, 2, 3)
+    ps = ooc.make_plan(512, 512, 1024, ooc.ORDER_COLS, 2, 1, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
+    extra = ooc.ooc_plan_footprint(2048, 2048, 1024, 0.0, ps) - ooc.ooc_plan_footprint(2048, 2048, 1024, 0.0, p64)
+    assert extra >= 2 * 6 * (512 + 512) * 1024

@@ -1,0 +1,126 @@
+"""GPU parity of the split-BF16 tile product (Ozaki-style slices on BF16
+matrix cores) against the split reference (bit-exact: the slice products are
+exact and the final FP64 combination follows the same order) and against the
+FP64 reference (normalised error gate for s >= 6)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import split_ref
+from synth import workloads as W
+import paper_1808_05056_amd as ooc
+from gpu_helpers import PinnedProblem
+
+pytestmark = pytest.mark.gpu
+MiB = 1 << 20
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _device_split(A, B, C0, alpha, beta, s):
+    m, k = A.shape
+    n = B.shape[1]
+    dA = ooc.DeviceBuffer(max(8, A.nbytes)); dB = ooc.DeviceBuffer(max(8, B.nbytes)); dC = ooc.DeviceBuffer(C0.nbytes)
+    if k:
+        dA.upload(A); dB.upload(B)
+    dC.upload(C0)
+    ooc.ooc_split_gemm_device(m, n, k, s, alpha, dA.ptr, max(k, 1), dB.ptr, n, beta, dC.ptr, n)
+    return dC.download((m, n))
+
+
+CASES = [
+    # m, n, k, s, alpha, beta, dist, row/col exponent spread
+    (64, 64, 64, 1, 1.0, 0.0, synth.INT, 0),
+    (100, 70, 130, 3, 1.5, 0.5, synth.NORMAL, 0),
+    (256, 192, 1000, 6, 1.0, 0.0, synth.NORMAL, 20),
+    (129, 257, 77, 8, -0.75, 2.0, synth.UNIFORM, 5),
+    (512, 512, 4096, 6, 1.0, 0.0, synth.NORMAL, 20),
+    (33, 17, 5, 7, 1.0, 1.0, synth.UNIFORM, 0),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_split_kernel_bit_exact_vs_split_reference(case):
+    m, n, k, s, alpha, beta, dist, spread = CASES[case]
+    _say(f"split kernel case {CASES[case]}")
+    A = np.ascontiguousarray(synth.matrix(m, k, synth.spec(200 + case, 0, dist, row_exp=(-spread, spread))))
+    B = np.ascontiguousarray(synth.matrix(k, n, synth.spec(200 + case, 1, dist, col_exp=(-spread, spread))))
+    C0 = np.ascontiguousarray(synth.matrix(m, n, synth.spec(200 + case, 2, synth.UNIFORM)))
+    got = _device_split(A, B, C0, alpha, beta, s)
+    want = split_ref.split_gemm(alpha, A, B, beta, C0, s)
+    assert np.array_equal(got, want), np.max(np.abs(got - want))
+    if s >= 6:
+        ref, D = oracle.gemm_rows(alpha, A, B, beta, C0)
+        assert oracle.normalized_error(got, ref, D) <= oracle.GATE
+
+
+def test_split_chunk_sums_exact_at_largest_slices():
+    # every first slice at its largest magnitude (256) and long K: the FP32 chunk
+    # sums reach their bound; the result must still equal the reference exactly
+    m, n, k, s = 64, 64, 4096, 2
+    A = np.full((m, k), 1.0 - 2.0 ** -9)   # rounds to first slice 256 with exponent 0
+    B = np.full((k, n), -(1.0 - 2.0 ** -9))
+    A[::2, ::3] *= -1
+    got = _device_split(A, B, np.zeros((m, n)), 1.0, 0.0, s)
+    want = split_ref.split_gemm(1.0, A, B, 0.0, None, s)
+    assert np.array_equal(got, want)
+    exact = A @ B  # products of equal magnitudes: exact in FP64 here
+    # two slices drop only the (2,2) pair: 4096 * 128^2 * 2^-32 in magnitude at most
+    assert np.max(np.abs(got - exact)) <= 4096 * 128 ** 2 * 2.0 ** -32
+
+
+def test_split_nonfinite_rows_and_columns_give_nan():
+    m, n, k = 70, 50, 40
+    A = np.ascontiguousarray(synth.matrix(m, k, synth.spec(5, 0)))
+    B = np.ascontiguousarray(synth.matrix(k, n, synth.spec(5, 1)))
+    A[3, 7] = np.nan
+    B[11, 9] = np.inf
+    got = _device_split(A, B, np.zeros((m, n)), 1.0, 0.0, 6)
+    assert np.all(np.isnan(got[3])) and np.all(np.isnan(got[:, 9]))
+    mask = np.ones((m, n), bool); mask[3] = False; mask[:, 9] = False
+    ref, D = oracle.gemm_rows(1.0, A, B, 0.0, None)
+    assert oracle.normalized_error(got[mask], ref[mask], D[mask]) <= oracle.GATE
+
+
+@pytest.mark.parametrize("planner", ["paper", "ksplit"])
+def test_split_pipeline_bit_exact(planner):
+    w = W.Workload("split-small", 1000, 900, 1100, 1.5, 0.5, 8 * MiB, seed=21, dist_a=synth.NORMAL,
+                   dist_b=synth.NORMAL, a_row_exp=(-20, 20), b_col_exp=(-20, 20))
+    pp = PinnedProblem(w)
+    try:
+        C0 = pp.C.copy()
+        if planner == "paper":
+            st, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget,
+                                     ooc.make_opts(planner=ooc.PLAN_PAPER, precision=ooc.SPLIT_BF16, slices=6))
+            kb = None
+        else:
+            plan = ooc.make_plan(256, 320, 384, ooc.ORDER_COLS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
+            st, stats = ooc.ooc_gemm_planned(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, plan)
+            kb = 384
+        assert stats.arena_bytes <= w.budget and stats.plan.precision == ooc.SPLIT_BF16
+        want = split_ref.split_gemm(w.alpha, pp.A, pp.B, w.beta, C0, 6, kb=kb)
+        assert np.array_equal(pp.C, want)
+        ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
+        assert oracle.normalized_error(pp.C, ref, D) <= oracle.GATE
+    finally:
+        pp.free()
+
+
+def test_split_pipeline_model_planner_staged():
+    w = W.Workload("split-model", 1500, 1300, 1700, 1.0, 1.0, 8 * MiB, seed=22)
+    pp = PinnedProblem(w)
+    try:
+        C0 = pp.C.copy()
+        st, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget,
+                                 ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=7))
+        assert stats.arena_bytes <= w.budget
+        ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
+        assert oracle.normalized_error(pp.C, ref, D) <= oracle.GATE
+    finally:
+        pp.free()
