@@ -92,7 +92,7 @@ def main():
         tc = time.time()
         ref, D = oracle.gemm_rows(w.alpha, A, B, w.beta, Cin, rows=rows)
         tcpu = time.time() - tc
-        err = oracle.normalized_error(C[rows], ref, D)
+        err = oracle.normalized_error(C[rows], ref, oracle.gate_denominator(w.alpha, D, w.beta, Cin))
         flops = 2.0 * len(rows) * w.N * w.K
         cpu = {"value": flops / tcpu / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
                "sample": f"{len(rows)} of {w.M} rows of C ({flops:.3e} flop) in {tcpu:.1f}s; "

@@ -247,6 +247,60 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
                                  const double* A, int64_t lda, const double* B, int64_t ldb,
                                  double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
 
+/* ---- the learned planner ------------------------------------------------------ */
+/* A small regression network predicts the log run time of a candidate plan
+ * from its features; OOC_PLAN_MLP takes the candidate with the smallest
+ * prediction.  (The paper fixes its plan by rule, Section V, and observes that
+ * the best stream count depends on the device, Section VI.)  Network: x (d) ->
+ * tanh(x W1 + b1) (H) -> tanh(. W2 + b2) (H) -> . W3 + b3, FP32 on the GPU;
+ * parameters are one flat float array W1 (d x H, row-major), b1 (H), W2 (H x H),
+ * b2 (H), W3 (H), b3 (1).  Host arrays throughout; device work uses `device`. */
+
+#define OOC_MLP_FEATURES 19
+
+/* Features of candidate plans: X_out receives n x OOC_MLP_FEATURES floats
+ * (log2 of M, N, K+1, budget, mb, nb, kb+1; order one-hot (4); nbuf_a, nbuf_b,
+ * log2 nbuf_c, nbuf_d, nstreams; log2 of the cost model's time and of the H2D
+ * bytes; split slices or 0).  Host only. */
+ooc_status ooc_mlp_features(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes,
+                            const ooc_plan_t* plans, int64_t n, float* X_out);
+
+/* Network forward pass for n inputs (X: n x d), y_out: n predictions. */
+ooc_status ooc_mlp_forward(int32_t device, int32_t d, int32_t hidden, const float* params, const float* X,
+                           int64_t n, float* y_out);
+
+/* Mean squared error of the predictions against t and its gradient with
+ * respect to every parameter (grad_out: same layout as params). */
+ooc_status ooc_mlp_grad(int32_t device, int32_t d, int32_t hidden, const float* params, const float* X,
+                        const float* t, int64_t n, float* grad_out, float* loss_out);
+
+/* One Adam step (bias-corrected; step counts from 1) on count parameters;
+ * params, m and v are updated in place. */
+ooc_status ooc_mlp_adam(int32_t device, int64_t count, float* params, const float* grad, float* m, float* v,
+                        int32_t step, float lr, float beta1, float beta2, float eps);
+
+/* epochs of full-batch Adam (lr, betas 0.9/0.999, eps 1e-8) on the GPU,
+ * params updated in place; loss_hist (optional) receives the loss before each
+ * step. */
+ooc_status ooc_mlp_train(int32_t device, int32_t d, int32_t hidden, float* params, const float* X,
+                         const float* t, int64_t n, int32_t epochs, float lr, float* loss_hist);
+
+/* Train the planner network from measured timings (seconds) of candidate
+ * plans whose features are X (n x OOC_MLP_FEATURES): features and log-times
+ * are standardised, weights drawn from seed, then ooc_mlp_train; the result
+ * becomes the network OOC_PLAN_MLP uses. */
+ooc_status ooc_mlp_fit(int32_t device, const float* X, const float* y_seconds, int64_t n, int32_t hidden,
+                       int32_t epochs, float lr, uint64_t seed, float* loss_hist);
+
+/* Save / load the planner network (text file: sizes, standardisation, weights). */
+ooc_status ooc_mlp_save(const char* path);
+ooc_status ooc_mlp_load(const char* path);
+int32_t ooc_mlp_loaded(void);  /* 1 if a planner network is loaded */
+
+/* The planner network's predicted run time (seconds) of each candidate plan. */
+ooc_status ooc_mlp_predict(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes,
+                           const ooc_plan_t* plans, int64_t n, double* seconds_out);
+
 /* ---- messages and version ----------------------------------------------------- */
 
 const char* ooc_last_error(void);   /* message of the calling thread's last error */

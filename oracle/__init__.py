@@ -95,6 +95,19 @@ def threads():
     return int(lib().oracle_threads())
 
 
+def gate_denominator(alpha, D_ab, beta, Cin):
+    """Denominator of the acceptance gate: |alpha| (|A||B|)_ij + |beta| |C_in|_ij.
+
+    For alpha = 1 and beta = 0 this is exactly (|A||B|)_ij.  The beta term is
+    the scale of the final addition alpha*S + beta*C: where |beta C_in| exceeds
+    (|A||B|)_ij by more than ~2^52 * 1e-12, a single rounding of that addition
+    already exceeds 1e-12 of (|A||B|)_ij, whatever the product's accuracy."""
+    den = abs(alpha) * np.asarray(D_ab, dtype=np.float64)
+    if beta != 0.0 and Cin is not None:
+        den = den + abs(beta) * np.abs(np.asarray(Cin, dtype=np.float64))
+    return den
+
+
 def normalized_error(C, Cref, D):
     """max over entries of |C - Cref| / (|A||B|)_ij; where the denominator is 0
     the entries must agree exactly (else the error is reported as inf)."""
@@ -112,4 +125,4 @@ def normalized_error(C, Cref, D):
     return float(r.max()) if r.size else 0.0
 
 
-GATE = 1e-12  # normalised error bound every result must meet
+GATE = 1e-12  # normalised error bound every result must meet (denominator: gate_denominator)

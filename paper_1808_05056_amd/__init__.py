@@ -108,13 +108,28 @@ _sig("ooc_copy_to_host", i32, [i32, vp, vp, sz])
 _sig("ooc_release", i32, [i32])
 _sig("ooc_dgemm_device", i32, [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 _sig("ooc_split_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
+P_flt = ctypes.POINTER(ctypes.c_float)
+_sig("ooc_mlp_features", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P_flt])
+_sig("ooc_mlp_forward", i32, [i32, i32, i32, P_flt, P_flt, i64, P_flt])
+_sig("ooc_mlp_grad", i32, [i32, i32, i32, P_flt, P_flt, P_flt, i64, P_flt, P_flt])
+_sig("ooc_mlp_adam", i32, [i32, i64, P_flt, P_flt, P_flt, P_flt, i32, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, ctypes.c_float])
+_sig("ooc_mlp_train", i32, [i32, i32, i32, P_flt, P_flt, P_flt, i64, i32, ctypes.c_float, P_flt])
+_sig("ooc_mlp_fit", i32, [i32, P_flt, P_flt, i64, i32, i32, ctypes.c_float, u64, P_flt])
+_sig("ooc_mlp_save", i32, [ctypes.c_char_p])
+_sig("ooc_mlp_load", i32, [ctypes.c_char_p])
+_sig("ooc_mlp_loaded", i32, [])
+_sig("ooc_mlp_predict", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P(dbl)])
 _sig("ooc_last_error", ctypes.c_char_p, [])
 _sig("ooc_version", ctypes.c_char_p, [])
 
 EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_dgemm_device",
-           "ooc_split_gemm_device", "ooc_last_error", "ooc_version"]
+           "ooc_split_gemm_device", "ooc_mlp_features", "ooc_mlp_forward", "ooc_mlp_grad", "ooc_mlp_adam",
+           "ooc_mlp_train", "ooc_mlp_fit", "ooc_mlp_save", "ooc_mlp_load", "ooc_mlp_loaded", "ooc_mlp_predict",
+           "ooc_last_error", "ooc_version"]
+MLP_FEATURES = 19
 
 
 class OOCError(RuntimeError):
@@ -353,3 +368,88 @@ class DeviceBuffer:
             self.free()
         except Exception:
             pass
+
+
+# ---- the learned planner ------------------------------------------------------------------
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(P_flt)
+
+
+def mlp_param_count(d, H):
+    return d * H + H + H * H + H + H + 1
+
+
+def ooc_mlp_features(M, N, K, beta, budget_bytes, plans):
+    arr = (ooc_plan_t * len(plans))(*plans)
+    X = np.zeros((len(plans), MLP_FEATURES), dtype=np.float32)
+    _check(_lib.ooc_mlp_features(M, N, K, beta, budget_bytes, arr, len(plans), X.ctypes.data_as(P_flt)))
+    return X
+
+
+def ooc_mlp_forward(d, H, params, X, device=0):
+    p, pp = _f32(params)
+    x, px = _f32(X)
+    y = np.zeros(x.shape[0], dtype=np.float32)
+    _check(_lib.ooc_mlp_forward(device, d, H, pp, px, x.shape[0], y.ctypes.data_as(P_flt)))
+    return y
+
+
+def ooc_mlp_grad(d, H, params, X, t, device=0):
+    p, pp = _f32(params)
+    x, px = _f32(X)
+    tt, pt = _f32(t)
+    g = np.zeros(p.size, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(_lib.ooc_mlp_grad(device, d, H, pp, px, pt, x.shape[0], g.ctypes.data_as(P_flt), ctypes.byref(loss)))
+    return g, loss.value
+
+
+def ooc_mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, device=0):
+    """One Adam step; returns new (params, m, v) as float32 arrays."""
+    p = np.array(params, dtype=np.float32)
+    mm = np.array(m, dtype=np.float32)
+    vv = np.array(v, dtype=np.float32)
+    g, pg = _f32(grad)
+    _check(_lib.ooc_mlp_adam(device, p.size, p.ctypes.data_as(P_flt), pg, mm.ctypes.data_as(P_flt),
+                             vv.ctypes.data_as(P_flt), step, lr, beta1, beta2, eps))
+    return p, mm, vv
+
+
+def ooc_mlp_train(d, H, params, X, t, epochs, lr=1e-3, device=0):
+    """Full-batch Adam on the GPU; returns (params, loss history)."""
+    p = np.array(params, dtype=np.float32)
+    x, px = _f32(X)
+    tt, pt = _f32(t)
+    hist = np.zeros(max(epochs, 1), dtype=np.float32)
+    _check(_lib.ooc_mlp_train(device, d, H, p.ctypes.data_as(P_flt), px, pt, x.shape[0], epochs, lr,
+                              hist.ctypes.data_as(P_flt)))
+    return p, hist[:epochs]
+
+
+def ooc_mlp_fit(X, seconds, hidden=64, epochs=3000, lr=3e-3, seed=0, device=0):
+    x, px = _f32(X)
+    y, py = _f32(seconds)
+    hist = np.zeros(max(epochs, 1), dtype=np.float32)
+    _check(_lib.ooc_mlp_fit(device, px, py, x.shape[0], hidden, epochs, lr, seed, hist.ctypes.data_as(P_flt)))
+    return hist[:epochs]
+
+
+def ooc_mlp_save(path):
+    _check(_lib.ooc_mlp_save(path.encode()))
+
+
+def ooc_mlp_load(path):
+    _check(_lib.ooc_mlp_load(path.encode()))
+
+
+def ooc_mlp_loaded():
+    return bool(_lib.ooc_mlp_loaded())
+
+
+def ooc_mlp_predict(M, N, K, beta, budget_bytes, plans):
+    arr = (ooc_plan_t * len(plans))(*plans)
+    out = np.zeros(len(plans))
+    _check(_lib.ooc_mlp_predict(M, N, K, beta, budget_bytes, arr, len(plans), out.ctypes.data_as(P(dbl))))
+    return out

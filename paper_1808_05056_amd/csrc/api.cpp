@@ -348,8 +348,6 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
 
 }  // namespace
 
-bool mlp_predict(const Problem&, uint64_t, const std::vector<ooc_plan_t>&, std::vector<double>*) { return false; }
-
 }  // namespace ooc
 
 using namespace ooc;

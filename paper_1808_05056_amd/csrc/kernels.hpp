@@ -21,4 +21,15 @@ hipError_t launch_split_gemm(int64_t m, int64_t n, int64_t k, int s, double alph
                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
                              const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+// The planner network (see mlp.hip): parameter count, scratch size (floats)
+// for a batch of n, forward pass into y, loss and gradient, one Adam step.
+int64_t mlp_param_count(int d, int H);
+int64_t mlp_scratch_floats(int64_t n, int d, int H);
+hipError_t launch_mlp_forward(int64_t n, int d, int H, const float* params, const float* X, float* scratch,
+                              float* y_out, hipStream_t s);
+hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const float* X, const float* t,
+                           float* scratch, float* grad, float* loss, hipStream_t s);
+hipError_t launch_adam(int64_t count, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t s);
+
 }  // namespace ooc

@@ -1,0 +1,177 @@
+// The learned planner's network: forward, backward, loss and optimiser kernels.
+//
+// The paper chooses its partition with a fixed rule (Section V) and finds
+// that the best stream count depends on the device (Section VI: one stream
+// instead of two on the Xeon Phi).  The learned planner predicts the run time
+// of a candidate plan with a small regression network trained on timings the
+// pipeline itself produces, and takes the candidate with the smallest
+// prediction.
+//
+// Network (FP32): x (d) -> tanh(x W1 + b1) (H) -> tanh(. W2 + b2) (H) -> . W3 + b3.
+// Loss: mean squared error over the batch.  Optimiser: Adam with bias
+// correction (Kingma and Ba, 2015).  Parameters are one flat array:
+// W1 (d x H, row-major), b1 (H), W2 (H x H), b2 (H), W3 (H x 1), b3 (1).
+// Every reduction runs in a fixed order in one thread, so results are
+// deterministic.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace ooc {
+namespace {
+
+// Y[r][j] = act(sum_i X[r][i] W[i][j] + b[j]); act = tanh or identity
+__global__ __launch_bounds__(256) void dense_fwd(int64_t n, int din, int dout, const float* __restrict__ X,
+                                                 const float* __restrict__ W, const float* __restrict__ b,
+                                                 float* __restrict__ Y, int use_tanh) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n * dout) return;
+  const int64_t r = idx / dout;
+  const int j = (int)(idx % dout);
+  float acc = b[j];
+  for (int i = 0; i < din; ++i) acc += X[r * din + i] * W[(int64_t)i * dout + j];
+  Y[idx] = use_tanh ? tanhf(acc) : acc;
+}
+
+// loss = (1/n) sum (y - t)^2 (one thread), dY = 2 (y - t) / n
+__global__ __launch_bounds__(256) void mse_grad(int64_t n, const float* __restrict__ y, const float* __restrict__ t,
+                                                float* __restrict__ dy) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  dy[r] = 2.0f * (y[r] - t[r]) / (float)n;
+}
+
+__global__ void mse_loss(int64_t n, const float* __restrict__ y, const float* __restrict__ t, float* __restrict__ loss) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int64_t r = 0; r < n; ++r) {
+    const double d = (double)y[r] - (double)t[r];
+    acc += d * d;
+  }
+  *loss = (float)(acc / (double)n);
+}
+
+// dZ = dH * (1 - H^2) in place (tanh derivative from the stored activations)
+__global__ __launch_bounds__(256) void tanh_bwd(int64_t count, const float* __restrict__ H, float* __restrict__ dH) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  dH[i] = dH[i] * (1.0f - H[i] * H[i]);
+}
+
+// dW[i][j] = sum_r X[r][i] dZ[r][j]; db[j] = sum_r dZ[r][j]
+__global__ __launch_bounds__(256) void dense_wgrad(int64_t n, int din, int dout, const float* __restrict__ X,
+                                                   const float* __restrict__ dZ, float* __restrict__ dW,
+                                                   float* __restrict__ db) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t nw = (int64_t)din * dout;
+  if (idx < nw) {
+    const int i = (int)(idx / dout), j = (int)(idx % dout);
+    float acc = 0.f;
+    for (int64_t r = 0; r < n; ++r) acc += X[r * din + i] * dZ[r * dout + j];
+    dW[idx] = acc;
+  } else if (idx < nw + dout) {
+    const int j = (int)(idx - nw);
+    float acc = 0.f;
+    for (int64_t r = 0; r < n; ++r) acc += dZ[r * dout + j];
+    db[j] = acc;
+  }
+}
+
+// dX[r][i] = sum_j dZ[r][j] W[i][j]
+__global__ __launch_bounds__(256) void dense_xgrad(int64_t n, int din, int dout, const float* __restrict__ dZ,
+                                                   const float* __restrict__ W, float* __restrict__ dX) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n * din) return;
+  const int64_t r = idx / din;
+  const int i = (int)(idx % din);
+  float acc = 0.f;
+  for (int j = 0; j < dout; ++j) acc += dZ[r * dout + j] * W[(int64_t)i * dout + j];
+  dX[idx] = acc;
+}
+
+__global__ __launch_bounds__(256) void adam(int64_t count, float* __restrict__ p, const float* __restrict__ g,
+                                            float* __restrict__ m, float* __restrict__ v, float lr, float b1, float b2,
+                                            float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const float mi = b1 * m[i] + (1.f - b1) * g[i];
+  const float vi = b2 * v[i] + (1.f - b2) * g[i] * g[i];
+  m[i] = mi;
+  v[i] = vi;
+  p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
+
+}  // namespace
+
+int64_t mlp_param_count(int d, int H) { return (int64_t)d * H + H + (int64_t)H * H + H + H + 1; }
+
+int64_t mlp_scratch_floats(int64_t n, int d, int H) {
+  // H1, H2, y, dy, dH2, dH1 (+ dX of layer 1 is not needed)
+  return n * H * 4 + n * 2 + 16;
+}
+
+hipError_t launch_mlp_forward(int64_t n, int d, int H, const float* params, const float* X, float* scratch,
+                              float* y_out, hipStream_t s) {
+  const float* W1 = params;
+  const float* b1 = W1 + (int64_t)d * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + (int64_t)H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H;
+  float* H1 = scratch;
+  float* H2 = H1 + n * H;
+  hipLaunchKernelGGL(dense_fwd, dim3(blocks(n * H)), dim3(256), 0, s, n, d, H, X, W1, b1, H1, 1);
+  hipLaunchKernelGGL(dense_fwd, dim3(blocks(n * H)), dim3(256), 0, s, n, H, H, H1, W2, b2, H2, 1);
+  hipLaunchKernelGGL(dense_fwd, dim3(blocks(n)), dim3(256), 0, s, n, H, 1, H2, W3, b3, y_out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const float* X, const float* t,
+                           float* scratch, float* grad, float* loss, hipStream_t s) {
+  const float* W1 = params;
+  const float* b1 = W1 + (int64_t)d * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + (int64_t)H * H;
+  const float* W3 = b2 + H;
+  (void)b1; (void)b2;
+  float* gW1 = grad;
+  float* gb1 = gW1 + (int64_t)d * H;
+  float* gW2 = gb1 + H;
+  float* gb2 = gW2 + (int64_t)H * H;
+  float* gW3 = gb2 + H;
+  float* gb3 = gW3 + H;
+  float* H1 = scratch;
+  float* H2 = H1 + n * H;
+  float* dH2 = H2 + n * H;
+  float* dH1 = dH2 + n * H;
+  float* y = dH1 + n * H;
+  float* dy = y + n;
+  hipError_t e = launch_mlp_forward(n, d, H, params, X, scratch, y, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mse_loss, dim3(1), dim3(64), 0, s, n, y, t, loss);
+  hipLaunchKernelGGL(mse_grad, dim3(blocks(n)), dim3(256), 0, s, n, y, t, dy);
+  // layer 3 (linear): dW3 = H2^T dy, db3 = sum dy, dH2 = dy W3^T
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H + 1)), dim3(256), 0, s, n, H, 1, H2, dy, gW3, gb3);
+  hipLaunchKernelGGL(dense_xgrad, dim3(blocks(n * H)), dim3(256), 0, s, n, H, 1, dy, W3, dH2);
+  hipLaunchKernelGGL(tanh_bwd, dim3(blocks(n * H)), dim3(256), 0, s, n * H, H2, dH2);
+  // layer 2
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H * H + H)), dim3(256), 0, s, n, H, H, H1, dH2, gW2, gb2);
+  hipLaunchKernelGGL(dense_xgrad, dim3(blocks(n * H)), dim3(256), 0, s, n, H, H, dH2, W2, dH1);
+  hipLaunchKernelGGL(tanh_bwd, dim3(blocks(n * H)), dim3(256), 0, s, n * H, H1, dH1);
+  // layer 1
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)d * H + H)), dim3(256), 0, s, n, d, H, X, dH1, gW1, gb1);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(int64_t count, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
+                       float eps, int step, hipStream_t s) {
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adam, dim3(blocks(count)), dim3(256), 0, s, count, p, g, m, v, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace ooc

@@ -40,12 +40,14 @@ def sample_rows(M, mb, count=16, seed=0):
 
 
 def reference_rows(w, A, B, rows):
-    """Reference rows of the workload's product (initial C regenerated)."""
+    """Reference rows of the workload's product (initial C regenerated) and the
+    gate denominator |alpha| (|A||B|)_ij + |beta| |C_in|_ij for those rows."""
     Cin = None
     if w.beta != 0.0:
         Cin = np.empty((len(rows), w.N))
         synth.fill_rows(Cin, rows, w.spec_c())
-    return oracle.gemm_rows(w.alpha, A, B, w.beta, Cin, rows=rows)
+    ref, D = oracle.gemm_rows(w.alpha, A, B, w.beta, Cin, rows=rows)
+    return ref, oracle.gate_denominator(w.alpha, D, w.beta, Cin)
 
 
 def check_rows(w, pp, rows, gate=oracle.GATE):

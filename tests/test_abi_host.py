@@ -20,7 +20,7 @@ MiB, GiB = 1 << 20, 1 << 30
 
 def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "ooc.h")).read()
-    names = sorted(set(re.findall(r"^(?:ooc_status|const char\*)\s+(ooc_\w+)\s*\(", hdr, re.M)))
+    names = sorted(set(re.findall(r"^(?:ooc_status|const char\*|int32_t)\s+(ooc_\w+)\s*\(", hdr, re.M)))
     assert len(names) >= 15
     for n in names:
         assert hasattr(ooc._lib, n), n
@@ -211,3 +211,13 @@ def test_split_footprint_counts_workspace():
     ps = ooc.make_plan(512, 512, 1024, ooc.ORDER_COLS, 2, 1, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
     extra = ooc.ooc_plan_footprint(2048, 2048, 1024, 0.0, ps) - ooc.ooc_plan_footprint(2048, 2048, 1024, 0.0, p64)
     assert extra >= 2 * 6 * (512 + 512) * 1024
+
+
+def test_planner_features():
+    plans, times = ooc.ooc_plan_candidates(32768, 32768, 32768, 0.5, 4 << 30)
+    X = ooc.ooc_mlp_features(32768, 32768, 32768, 0.5, 4 << 30, plans[:10])
+    assert X.shape == (10, ooc.MLP_FEATURES)
+    assert np.allclose(X[:, 0], 15) and np.allclose(X[:, 3], 32)
+    assert np.allclose(X[:, 7:11].sum(axis=1), 1)
+    # the cost-model feature is log2 of the candidate's modelled time
+    assert np.allclose(X[:, 16], np.log2(times[:10]), atol=1e-5)

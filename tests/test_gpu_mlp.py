@@ -1,0 +1,102 @@
+"""GPU kernels of the learned planner against the FP64 network reference:
+forward pass, loss and gradients per element, one Adam step, and a short
+training run whose loss history follows the reference's."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+import paper_1808_05056_amd as ooc
+
+pytestmark = pytest.mark.gpu
+
+
+def _flat(P):
+    return np.concatenate([P[k].reshape(-1) for k in mlp_ref.PARAM_NAMES])
+
+
+def _unflat(v, d, H):
+    P, off = {}, 0
+    for k, shape in (("W1", (d, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (H, 1)), ("b3", (1,))):
+        size = int(np.prod(shape))
+        P[k] = np.array(v[off:off + size], dtype=np.float64).reshape(shape)
+        off += size
+    return P
+
+
+def _data(n, d, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] - 0.3 * X[:, -1]).astype(np.float32)
+    return X, t
+
+
+def _params(d, H, seed):
+    P = mlp_ref.init(d, H, seed)
+    rng = np.random.default_rng(seed + 1)
+    P["b1"] = 0.1 * rng.standard_normal(H)
+    P["b2"] = 0.1 * rng.standard_normal(H)
+    P["b3"] = 0.1 * rng.standard_normal(1)
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
+
+
+@pytest.mark.parametrize("d,H,n", [(19, 64, 300), (5, 16, 7), (19, 128, 1000)])
+def test_forward_and_gradients(d, H, n):
+    P = _params(d, H, 3)
+    X, t = _data(n, d, 4)
+    y_ref, cache = mlp_ref.forward(P, X.astype(np.float64))
+    y = ooc.ooc_mlp_forward(d, H, _flat(P), X)
+    assert np.max(np.abs(y - y_ref)) <= 1e-5 * (1 + np.max(np.abs(y_ref)))
+    L_ref, dy = mlp_ref.mse(y_ref, t.astype(np.float64))
+    g_ref = _flat(mlp_ref.backward(P, cache, dy))
+    g, L = ooc.ooc_mlp_grad(d, H, _flat(P), X, t)
+    assert abs(L - L_ref) <= 1e-5 * (1 + L_ref)
+    # per element, normalised by the largest gradient of its parameter block
+    off = 0
+    Gr = mlp_ref.backward(P, cache, dy)
+    for k in mlp_ref.PARAM_NAMES:
+        size = Gr[k].size
+        scale = np.max(np.abs(Gr[k])) + 1e-12
+        assert np.max(np.abs(g[off:off + size] - g_ref[off:off + size])) <= 1e-4 * scale, k
+        off += size
+
+
+def test_adam_step_matches_reference():
+    rng = np.random.default_rng(5)
+    count = ooc.mlp_param_count(19, 64)
+    p = rng.standard_normal(count).astype(np.float32)
+    g = rng.standard_normal(count).astype(np.float32)
+    m = (0.1 * rng.standard_normal(count)).astype(np.float32)
+    v = (0.01 * rng.random(count)).astype(np.float32)
+    step = 7
+    p2, m2, v2 = ooc.ooc_mlp_adam(p, g, m, v, step, lr=1e-2)
+    # reference in FP64 with the same state
+    P = {k: None for k in mlp_ref.PARAM_NAMES}
+    st = {"t": step - 1, "m": {"W1": m.astype(np.float64)}, "v": {"W1": v.astype(np.float64)}}
+    Pd = {"W1": p.astype(np.float64)}
+    # apply the reference update to the single flat block
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 1e-2
+    mr = b1 * st["m"]["W1"] + (1 - b1) * g
+    vr = b2 * st["v"]["W1"] + (1 - b2) * g.astype(np.float64) ** 2
+    pr = Pd["W1"] - lr * (mr / (1 - b1 ** step)) / (np.sqrt(vr / (1 - b2 ** step)) + eps)
+    assert np.max(np.abs(m2 - mr)) <= 1e-6 * (1 + np.max(np.abs(mr)))
+    assert np.max(np.abs(v2 - vr)) <= 1e-6 * (1 + np.max(np.abs(vr)))
+    assert np.max(np.abs(p2 - pr)) <= 1e-5
+
+
+def test_training_follows_reference():
+    d, H, n = 6, 32, 256
+    P = _params(d, H, 7)
+    X, t = _data(n, d, 8)
+    p, hist = ooc.ooc_mlp_train(d, H, _flat(P), X, t, epochs=200, lr=3e-3)
+    Pref = {k: v.copy() for k, v in P.items()}
+    ref_hist = []
+    st = mlp_ref.adam_init(Pref)
+    for _ in range(200):
+        y, c = mlp_ref.forward(Pref, X.astype(np.float64))
+        L, dy = mlp_ref.mse(y, t.astype(np.float64))
+        ref_hist.append(L)
+        mlp_ref.adam_step(Pref, mlp_ref.backward(Pref, c, dy), st, lr=3e-3)
+    ref_hist = np.array(ref_hist)
+    assert hist[-1] < 0.3 * hist[0]
+    assert np.max(np.abs(hist[:50] - ref_hist[:50]) / ref_hist[:50]) < 1e-3
+    assert abs(hist[-1] - ref_hist[-1]) / ref_hist[-1] < 0.05

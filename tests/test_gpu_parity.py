@@ -57,7 +57,7 @@ def test_dgemm_kernel_parity(case):
     ref, D = oracle.gemm_rows(alpha, A, B, beta, C0)
     if dist == synth.INT:
         assert np.array_equal(got, ref)
-    assert oracle.normalized_error(got, ref, D) <= oracle.GATE
+    assert oracle.normalized_error(got, ref, oracle.gate_denominator(alpha, D, beta, C0)) <= oracle.GATE
 
 
 def test_dgemm_kernel_beta_zero_ignores_nan():

@@ -57,7 +57,7 @@ def test_split_kernel_bit_exact_vs_split_reference(case):
     assert np.array_equal(got, want), np.max(np.abs(got - want))
     if s >= 6:
         ref, D = oracle.gemm_rows(alpha, A, B, beta, C0)
-        assert oracle.normalized_error(got, ref, D) <= oracle.GATE
+        assert oracle.normalized_error(got, ref, oracle.gate_denominator(alpha, D, beta, C0)) <= oracle.GATE
 
 
 def test_split_chunk_sums_exact_at_largest_slices():
@@ -107,7 +107,7 @@ def test_split_pipeline_bit_exact(planner):
         want = split_ref.split_gemm(w.alpha, pp.A, pp.B, w.beta, C0, 6, kb=kb)
         assert np.array_equal(pp.C, want)
         ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
-        assert oracle.normalized_error(pp.C, ref, D) <= oracle.GATE
+        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
     finally:
         pp.free()
 
@@ -121,6 +121,6 @@ def test_split_pipeline_model_planner_staged():
                                  ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=7))
         assert stats.arena_bytes <= w.budget
         ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
-        assert oracle.normalized_error(pp.C, ref, D) <= oracle.GATE
+        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
     finally:
         pp.free()

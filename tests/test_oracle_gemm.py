@@ -152,3 +152,15 @@ def test_generator_is_counter_based():
     assert u.min() >= -1 and u.max() < 1 and abs(u.mean()) < 0.01
     nrm = synth.matrix(400, 500, synth.spec(1, 0, synth.NORMAL))
     assert abs(nrm.mean()) < 0.01 and abs(nrm.std() - 1) < 0.01
+
+
+def test_gate_denominator():
+    D = np.array([[2.0, 1e-9]])
+    Cin = np.array([[4.0, 0.5]])
+    assert np.array_equal(oracle.gate_denominator(1.0, D, 0.0, Cin), D)
+    assert np.array_equal(oracle.gate_denominator(-2.0, D, 0.5, Cin), np.array([[6.0, 0.25 + 2e-9]]))
+    # one rounding of a beta*C-dominated entry is within the gate with the full denominator
+    c = 0.48
+    one_ulp = np.spacing(c)
+    assert one_ulp / 1.2e-5 > oracle.GATE
+    assert one_ulp / oracle.gate_denominator(1.5, np.array(1.2e-5), 0.5, np.array(c / 0.5)) < oracle.GATE
