@@ -43,7 +43,15 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=128, help="rows of C the CPU reference computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", type=int, default=1, help="time every op with HIP events in the timed steps")
+    ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
+                    help="only run the library's device copy kernel once on BYTES (traffic-counter reference)")
     args = ap.parse_args()
+    if args.copy_kernel:
+        import paper_1808_05056_amd as ooc
+        src, dst = ooc.DeviceBuffer(args.copy_kernel), ooc.DeviceBuffer(args.copy_kernel)
+        ooc.ooc_device_copy(dst.ptr, src.ptr, args.copy_kernel)
+        print(json.dumps({"copy_kernel_bytes": args.copy_kernel}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the out-of-core product is "

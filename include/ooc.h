@@ -226,6 +226,10 @@ ooc_status ooc_device_free(int32_t device, void* ptr);
 ooc_status ooc_copy_to_device(int32_t device, void* dst, const void* src, size_t bytes);
 ooc_status ooc_copy_to_host(int32_t device, void* dst, const void* src, size_t bytes);
 
+/* Device-to-device copy with a plain streaming kernel (16-byte aligned pointers,
+ * bytes a multiple of 16); a reference workload for hardware traffic counters. */
+ooc_status ooc_device_copy(int32_t device, void* dst, const void* src, size_t bytes);
+
 /* Free the device buffers, streams and events cached for a device (-1: all). */
 ooc_status ooc_release(int32_t device);
 

@@ -106,6 +106,7 @@ _sig("ooc_device_free", i32, [i32, vp])
 _sig("ooc_copy_to_device", i32, [i32, vp, vp, sz])
 _sig("ooc_copy_to_host", i32, [i32, vp, vp, sz])
 _sig("ooc_release", i32, [i32])
+_sig("ooc_device_copy", i32, [i32, vp, vp, sz])
 _sig("ooc_dgemm_device", i32, [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 _sig("ooc_split_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 P_flt = ctypes.POINTER(ctypes.c_float)
@@ -125,7 +126,7 @@ _sig("ooc_version", ctypes.c_char_p, [])
 
 EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
-           "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_dgemm_device",
+           "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_device_copy", "ooc_dgemm_device",
            "ooc_split_gemm_device", "ooc_mlp_features", "ooc_mlp_forward", "ooc_mlp_grad", "ooc_mlp_adam",
            "ooc_mlp_train", "ooc_mlp_fit", "ooc_mlp_save", "ooc_mlp_load", "ooc_mlp_loaded", "ooc_mlp_predict",
            "ooc_last_error", "ooc_version"]
@@ -291,6 +292,10 @@ def ooc_schedule(M, N, K, alpha, beta, plan):
                      off_w=o.off_w, len_w=o.len_w, alpha=o.alpha, beta=o.beta, gamma=o.gamma)
         ops.append(d)
     return ops, ab.value // 8
+
+
+def ooc_device_copy(dst, src, nbytes, device=0):
+    _check(_lib.ooc_device_copy(device, dst, src, nbytes))
 
 
 def ooc_release(device=-1):

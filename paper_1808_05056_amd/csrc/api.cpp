@@ -627,6 +627,18 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
   return OOC_OK;
 }
 
+ooc_status ooc_device_copy(int32_t device, void* dst, const void* src, size_t bytes) {
+  if (!dst || !src || bytes % 16 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
+    return fail(OOC_ERR_ARG, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+  ooc_status st = ensure_device(device);
+  if (st != OOC_OK) return st;
+  DevCtx& c = g_dev[device];
+  std::lock_guard<std::mutex> lock(c.mu);
+  HIPCHK(launch_copy(dst, src, bytes, c.st[1]), "copy launch");
+  HIPCHK(hipStreamSynchronize(c.st[1]), "hipStreamSynchronize");
+  return OOC_OK;
+}
+
 const char* ooc_last_error(void) { return g_err.c_str(); }
 
 const char* ooc_version(void) { return "ooc-mi355x 0.1 (gfx950)"; }

@@ -79,6 +79,9 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
 ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
                        ooc_plan_t* plan, double* predicted);
 
+// Forget cached plan choices (after a new planner network is loaded).
+void clear_plan_cache();
+
 // MLP planner hook: predicted times for candidate plans, or false if no model is loaded.
 bool mlp_predict(const Problem& pb, uint64_t budget_bytes, const std::vector<ooc_plan_t>& plans,
                  std::vector<double>* seconds);

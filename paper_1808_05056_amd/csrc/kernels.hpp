@@ -32,4 +32,7 @@ hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const f
 hipError_t launch_adam(int64_t count, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);
 
+// Device-to-device copy kernel (bytes and pointers multiples of 16).
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 }  // namespace ooc

@@ -105,7 +105,20 @@ __global__ __launch_bounds__(256) void adam(int64_t count, float* __restrict__ p
 
 inline unsigned blocks(int64_t count) { return (unsigned)((count + 255) / 256); }
 
+// Plain copy, 16 bytes per thread per step (for calibrating traffic counters).
+__global__ __launch_bounds__(256) void copy16(int64_t n16, const double2* __restrict__ src, double2* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes % 16 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16) return hipErrorInvalidValue;
+  const int64_t n16 = (int64_t)(bytes / 16);
+  hipLaunchKernelGGL(copy16, dim3(8192), dim3(256), 0, s, n16, static_cast<const double2*>(src),
+                     static_cast<double2*>(dst));
+  return hipGetLastError();
+}
 
 int64_t mlp_param_count(int d, int H) { return (int64_t)d * H + H + (int64_t)H * H + H + H + 1; }
 

@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <set>
 #include <tuple>
 
@@ -392,8 +394,56 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
   return OOC_OK;
 }
 
+namespace {
+// Plans already chosen, keyed by everything the choice depends on.
+struct PlanKey {
+  int64_t M, N, K;
+  bool beta_nonzero;
+  uint64_t budget;
+  int planner, precision, slices, nstreams;
+  bool operator<(const PlanKey& o) const {
+    return std::tie(M, N, K, beta_nonzero, budget, planner, precision, slices, nstreams) <
+           std::tie(o.M, o.N, o.K, o.beta_nonzero, o.budget, o.planner, o.precision, o.slices, o.nstreams);
+  }
+};
+std::mutex g_plan_mu;
+std::map<PlanKey, std::pair<ooc_plan_t, double>> g_plan_cache;
+}  // namespace
+
+void clear_plan_cache() {
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  g_plan_cache.clear();
+}
+
+static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
+                                       ooc_plan_t* plan, double* predicted);
+
 ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts, ooc_plan_t* plan,
                        double* predicted) {
+  PlanKey key{pb.M, pb.N, pb.keff(), pb.beta != 0.0, budget_bytes,
+              opts ? opts->planner : 0, opts ? opts->precision : 0, opts ? opts->slices : 0,
+              opts ? opts->nstreams : 0};
+  {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto it = g_plan_cache.find(key);
+    if (it != g_plan_cache.end()) {
+      *plan = it->second.first;
+      if (predicted) *predicted = it->second.second;
+      return OOC_OK;
+    }
+  }
+  double pred = 0.0;
+  ooc_status st = choose_plan_uncached(pb, budget_bytes, opts, plan, &pred);
+  if (st != OOC_OK) return st;
+  if (predicted) *predicted = pred;
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  if (g_plan_cache.size() > 4096) g_plan_cache.clear();
+  g_plan_cache[key] = {*plan, pred};
+  return OOC_OK;
+}
+
+static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
+                                       ooc_plan_t* plan, double* predicted) {
   const int planner = opts ? opts->planner : OOC_PLAN_AUTO;
   if (planner == OOC_PLAN_PAPER) {
     const int prec = opts ? opts->precision : OOC_FP64;

@@ -7,6 +7,7 @@
 // decades.  The network predicts the log of the measured run time; features
 // and targets are standardised with the training set's mean and deviation,
 // which are stored with the weights.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -19,6 +20,8 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+
+extern "C" ooc_status ooc_mlp_load(const char* path);
 
 namespace ooc {
 namespace {
@@ -149,8 +152,29 @@ ooc_status features_for(const Problem& pb, uint64_t budget, const ooc_plan_t* pl
   return OOC_OK;
 }
 
+// The planner network shipped next to the library (planner_mlp.txt in the
+// directory holding libooc.so), loaded on first use when no other is loaded.
+static void load_default_network() {
+  static bool tried = false;
+  {
+    std::lock_guard<std::mutex> lock(g_net_mu);
+    if (g_net.loaded || tried) return;
+    tried = true;
+  }
+  Dl_info info;
+  if (!dladdr(reinterpret_cast<void*>(&load_default_network), &info) || !info.dli_fname) return;
+  std::string path(info.dli_fname);
+  const size_t slash = path.rfind('/');
+  path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/planner_mlp.txt";
+  if (FILE* f = std::fopen(path.c_str(), "r")) {
+    std::fclose(f);
+    (void)ooc_mlp_load(path.c_str());
+  }
+}
+
 bool mlp_predict(const Problem& pb, uint64_t budget_bytes, const std::vector<ooc_plan_t>& plans,
                  std::vector<double>* seconds) {
+  load_default_network();
   Net net;
   {
     std::lock_guard<std::mutex> lock(g_net_mu);
@@ -290,8 +314,11 @@ ooc_status ooc_mlp_fit(int32_t device, const float* X, const float* y_seconds, i
   ooc_status st = train_impl(device, d, hidden, net.params.data(), Xs.data(), t.data(), n, epochs, lr, loss_hist);
   if (st != OOC_OK) return st;
   net.loaded = true;
-  std::lock_guard<std::mutex> lock(g_net_mu);
-  g_net = net;
+  {
+    std::lock_guard<std::mutex> lock(g_net_mu);
+    g_net = net;
+  }
+  clear_plan_cache();
   return OOC_OK;
 }
 
@@ -330,8 +357,11 @@ ooc_status ooc_mlp_load(const char* path) {
   std::fclose(f);
   if (!ok) return fail(OOC_ERR_ARG, std::string("malformed planner network file ") + path);
   net.loaded = true;
-  std::lock_guard<std::mutex> lock(g_net_mu);
-  g_net = net;
+  {
+    std::lock_guard<std::mutex> lock(g_net_mu);
+    g_net = net;
+  }
+  clear_plan_cache();
   return OOC_OK;
 }
 
