@@ -16,6 +16,9 @@ hipError_t launch_dgemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const
 
 // Split-BF16 tile product (s slices): same result contract as launch_dgemm_f64
 // up to the split scheme's error; uses `workspace` (split_workspace_bytes).
+// K is processed in panels of at most kSplitMaxK (exact int32 slice sums):
+// C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C.
+constexpr int64_t kSplitMaxK = 8192;
 size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s);
 hipError_t launch_split_gemm(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,

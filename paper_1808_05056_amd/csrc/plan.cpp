@@ -286,6 +286,7 @@ static std::vector<int64_t> split_sizes(int64_t n, int64_t align, int max_parts)
 static std::vector<int64_t> panel_sizes(int64_t K) {
   std::set<int64_t> out;
   out.insert(K);
+  if (K > kSplitMaxK) out.insert(kSplitMaxK);
   for (int64_t d = 2; d <= 64; d *= 2) {
     int64_t s = ceil_div(ceil_div(K, d), 64) * 64;
     if (s >= 256 && s < K) out.insert(s);
@@ -308,6 +309,9 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
     Layout lay;
     p.precision = prec;
     p.slices = prec == OOC_SPLIT_BF16 ? slices : 0;
+    // split tiles run K in panels of kSplitMaxK inside the kernel; plan panels
+    // are kept to that size or below so both levels of panels coincide
+    if (prec == OOC_SPLIT_BF16 && K > kSplitMaxK && p.kb > kSplitMaxK) return;
     if (plan_layout(pb, p, &lay) != OOC_OK) return;
     if (lay.bytes > budget_bytes) return;
     // analytic lower bound: operand traffic vs link, flops vs kernel rate

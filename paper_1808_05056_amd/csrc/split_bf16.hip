@@ -23,10 +23,8 @@
 // A row or column holding a non-finite value gives NaN in its output row or
 // column.
 //
-// Workspace layout (bytes): A planes [s][mpad][kpad] bf16, B planes
-// [s][npad][kpad] bf16 (B transposed so MFMA operands are contiguous in k),
-// row exponents [mpad] int32, column exponents [npad] int32, where mpad,
-// npad and kpad are m, n and k rounded up to 64 and the padding is zero.
+// Workspace layout: see split_workspace_bytes (B planes are stored transposed
+// so MFMA operands are contiguous in k; all padding is zero).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -150,97 +148,221 @@ __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const do
   }
 }
 
-// Slice products: 4 waves in 2 x 2, each a 32 x 32 output block (one MFMA block).
+// Slice products.  A workgroup of 4 waves (2 x 2) computes a 128 x 128 block
+// of C; each wave a 64 x 64 block as 2 x 2 tiles of V_MFMA_F32_32X32X16_BF16.
+// For each weight t (from s+1 down to 2) the kernel walks the K range in
+// chunks of 64; every chunk of every pair (p, t-p) is staged in LDS (A plane
+// rows and transposed B plane rows, k contiguous), double-buffered with the
+// next chunk prefetched into registers.  FP32 accumulators are folded into
+// integer sums U_t after windows of 256 (t <= 3), 128 (t <= 7) or 64 k, the
+// longest windows whose partial sums provably stay below 2^24; with at most
+// 8192 k per launch |U_t| < 8192 * 10 * 2^14 < 2^31, so int32 holds U_t
+// exactly.  Between weights the FP64 slice sum S lives in a workspace tile;
+// the last weight's pass finishes S and writes C.
 // Operand layout of V_MFMA_F32_32X32X16_BF16: lane l supplies A[l%32][8*(l/32) .. +8]
 // and B[8*(l/32) .. +8][l%32]; accumulator element v of lane l is
 // D[8*(v/4) + 4*(l/32) + v%4][l%32].
-__global__ __launch_bounds__(256) void split_gemm(int64_t m, int64_t n, int64_t kpad, int s,
-                                                  const uint16_t* __restrict__ Ap, const uint16_t* __restrict__ Bp,
-                                                  int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
-                                                  const int32_t* __restrict__ fb, double alpha, double beta,
-                                                  double* __restrict__ C, int64_t ldc, double gamma,
-                                                  const double* __restrict__ D, int64_t ldd) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.y * 64 + (w >> 1) * 32;
-  const int64_t col0 = (int64_t)blockIdx.x * 64 + (w & 1) * 32;
-  const int64_t arow = row0 + (lane & 31), bcol = col0 + (lane & 31);
-  const int koff = 8 * (lane >> 5);
-  double S[16];
+constexpr int SBM = 128, SBN = 128, SKC = 64, SPAD = 8;  // tile, k chunk, LDS row padding (bf16)
+
+__device__ inline int fold_window_chunks(int t) { return t <= 3 ? 4 : (t <= 7 ? 2 : 1); }
+
+__global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64_t kpad, int s,
+                                                     const uint16_t* __restrict__ Ap, const uint16_t* __restrict__ Bp,
+                                                     int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
+                                                     const int32_t* __restrict__ fb, double* __restrict__ Sws,
+                                                     double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                                     double gamma, const double* __restrict__ D, int64_t ldd) {
+  // staging buffers for two chunks of A and B, or the tile's integer sums during a fold
+  __shared__ __attribute__((aligned(16))) union {
+    struct {
+      uint16_t A[2][SBM][SKC + SPAD];
+      uint16_t B[2][SBN][SKC + SPAD];
+    } st;
+    int32_t U[SBM * SBN];
+  } sm;
+  static_assert(sizeof(int32_t) * SBM * SBN <= 2 * (SBM + SBN) * (SKC + SPAD) * sizeof(uint16_t), "fold buffer");
+  auto& As = sm.st.A;
+  auto& Bs = sm.st.B;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * SBM, n0 = (int64_t)blockIdx.x * SBN;
+  // global -> register staging: each thread moves 4 x 16 bytes of A and of B per chunk
+  // (row r = tid/2 and the next 64 rows, 32-element half h = tid%2 of the 64-k chunk)
+  const int lr = tid >> 2, lq = (tid & 3) * 16;  // row within 64-row half, 16-element quarter
+  uint4 ra[2][2], rb[2][2];
+  const int nchunks = (int)(kpad / SKC);
+
+  auto gload = [&](int p, int q, int cc) {
+    const uint16_t* pa = Ap + ((int64_t)(p - 1) * mpad + m0) * kpad + (int64_t)cc * SKC;
+    const uint16_t* pb = Bp + ((int64_t)(q - 1) * npad + n0) * kpad + (int64_t)cc * SKC;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) S[v] = 0.0;
-  int32_t er[16], fc;
+    for (int h = 0; h < 2; ++h) {
+      const int row = lr + 64 * h;
+      const uint4* a4 = reinterpret_cast<const uint4*>(pa + (int64_t)row * kpad + lq);
+      const uint4* b4 = reinterpret_cast<const uint4*>(pb + (int64_t)row * kpad + lq);
+      ra[h][0] = a4[0]; ra[h][1] = a4[1];
+      rb[h][0] = b4[0]; rb[h][1] = b4[1];
+    }
+  };
+  auto lstore = [&](int buf) {
 #pragma unroll
-  for (int v = 0; v < 16; ++v) er[v] = ea[row0 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4)];
-  fc = fb[bcol];
+    for (int h = 0; h < 2; ++h) {
+      const int row = lr + 64 * h;
+      *reinterpret_cast<uint4*>(&As[buf][row][lq]) = ra[h][0];
+      *reinterpret_cast<uint4*>(&As[buf][row][lq + 8]) = ra[h][1];
+      *reinterpret_cast<uint4*>(&Bs[buf][row][lq]) = rb[h][0];
+      *reinterpret_cast<uint4*>(&Bs[buf][row][lq + 8]) = rb[h][1];
+    }
+  };
+
+  const int fr = lane & 31, fk = 8 * (lane >> 5);
   for (int t = s + 1; t >= 2; --t) {
-    double U[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) U[v] = 0.0;
     const int plo = t - s > 1 ? t - s : 1, phi = t - 1 < s ? t - 1 : s;
-    for (int64_t kc = 0; kc < kpad; kc += 64) {
-      f32x16 acc;
+    const int np = phi - plo + 1;
+    const int wc = fold_window_chunks(t);
+    int32_t U[2][2][16];  // exact: |U_t| < 8192 * 10 * 2^14 < 2^31 for K panels of at most 8192
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-      for (int p = plo; p <= phi; ++p) {
-        const int q = t - p;
-        const uint16_t* pa = Ap + ((int64_t)(p - 1) * mpad + arow) * kpad + kc + koff;
-        const uint16_t* pb = Bp + ((int64_t)(q - 1) * npad + bcol) * kpad + kc + koff;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int kk = 0; kk < 64; kk += 16) {
-          const bf16x8 a = *reinterpret_cast<const bf16x8*>(pa + kk);
-          const bf16x8 b = *reinterpret_cast<const bf16x8*>(pb + kk);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) U[i][j][v] = 0;
+    // steps run window by window; inside a window over the pairs, then the window's chunks
+    for (int c0 = 0; c0 < nchunks; c0 += wc) {
+      const int wlen = (nchunks - c0) < wc ? (nchunks - c0) : wc;
+      const int nsteps = np * wlen;
+      f32x16 acc[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+      gload(plo, t - plo, c0);
+      __syncthreads();  // the previous window's readers are done with buffer 0
+      lstore(0);
+      __syncthreads();
+      for (int st = 0; st < nsteps; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nsteps) {
+          const int p1 = plo + (st + 1) / wlen, cc1 = c0 + (st + 1) % wlen;
+          gload(p1, t - p1, cc1);
+        }
+#pragma unroll
+        for (int kk = 0; kk < SKC; kk += 16) {
+          bf16x8 a[2], b[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 32 + fr][kk + fk]);
+#pragma unroll
+          for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 32 + fr][kk + fk]);
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (st + 1 < nsteps) lstore(buf ^ 1);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) U[i][j][v] += (int32_t)acc[i][j][v];
+    }
+    // S = S + U_t 2^(e_i + f_j - 8t), from the smallest weight up.  The sums go
+    // through LDS (the staging buffers are idle now) so that the update below
+    // walks the tile row by row with consecutive threads on consecutive columns.
+    int32_t* Ul = sm.U;  // [SBM][SBN]
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          Ul[(wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4)) * SBN + wn * 64 + j * 32 + (lane & 31)] =
+              U[i][j][v];
+    __syncthreads();
+    {
+      const int c = tid & (SBN - 1);
+      const int64_t col = n0 + c;
+      const int32_t ff = fb[col];
+#pragma unroll 4
+      for (int r = tid / SBN; r < SBM; r += 256 / SBN) {
+        const int64_t row = m0 + r;
+        const int32_t ee = ea[row];
+        const bool bad = ee == kBad || ff == kBad;
+        double* ps = Sws + row * npad + col;
+        const double term = bad ? 0.0 : ldexp((double)Ul[r * SBN + c], ee + ff - 8 * t);
+        const double S = (t == s + 1) ? term : (*ps + term);
+        if (t > 2) {
+          *ps = S;
+        } else if (row < m && col < n) {
+          double val;
+          if (bad) {
+            val = __builtin_nan("");
+          } else {
+            val = __dmul_rn(alpha, S);
+            if (beta != 0.0) val = __dadd_rn(val, __dmul_rn(beta, C[row * ldc + col]));
+            if (gamma != 0.0) val = __dadd_rn(val, __dmul_rn(gamma, D[row * ldd + col]));
+          }
+          C[row * ldc + col] = val;
         }
       }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) U[v] += (double)acc[v];
     }
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int32_t ee = er[v];
-      if (ee != kBad && fc != kBad) S[v] = S[v] + ldexp(U[v], ee + fc - 8 * t);
-    }
-  }
-  const int64_t col = bcol;
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int64_t row = row0 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-    if (row < m && col < n) {
-      double val;
-      if (er[v] == kBad || fc == kBad) {
-        val = __builtin_nan("");
-      } else {
-        val = __dmul_rn(alpha, S[v]);
-        if (beta != 0.0) val = __dadd_rn(val, __dmul_rn(beta, C[row * ldc + col]));
-        if (gamma != 0.0) val = __dadd_rn(val, __dmul_rn(gamma, D[row * ldd + col]));
-      }
-      C[row * ldc + col] = val;
-    }
+    __syncthreads();  // LDS is staging space again
   }
 }
 
 inline int64_t pad64(int64_t x) { return (x + 63) / 64 * 64; }
+inline int64_t pad128(int64_t x) { return (x + 127) / 128 * 128; }
 
 }  // namespace
 
+// Workspace: A planes [s][mp][kp], B planes [s][np][kp] (bf16), row and column
+// exponents (int32), column maxima (uint64), slice-sum tile [mp][np] (FP64),
+// with mp, np = m, n rounded up to 128 and kp = k rounded up to 64.
 size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s) {
-  const int64_t mp = pad64(m), np = pad64(n), kp = pad64(k);
-  return (size_t)(2 * s * (mp + np) * kp + 4 * (mp + np) + 8 * np);
+  const int64_t mp = pad128(m), np = pad128(n), kp = pad64(k < kSplitMaxK ? k : kSplitMaxK);
+  return (size_t)(2 * s * (mp + np) * kp + 4 * (mp + np) + 8 * np + 8 * mp * np);
 }
+
+static hipError_t split_panel(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
+                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
+                              const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream);
 
 hipError_t launch_split_gemm(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
                              const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream) {
+  // K panels of at most kSplitMaxK: C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (k <= kSplitMaxK)
+    return split_panel(m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, workspace, ws_bytes, stream);
+  for (int64_t k0 = 0; k0 < k; k0 += kSplitMaxK) {
+    const int64_t kk = (k - k0) < kSplitMaxK ? (k - k0) : kSplitMaxK;
+    const bool first = k0 == 0;
+    hipError_t e = split_panel(m, n, kk, s, alpha, A + k0, lda, B + k0 * ldb, ldb, first ? beta : 1.0, C, ldc,
+                               first ? gamma : 0.0, D, ldd, workspace, ws_bytes, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t split_panel(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
+                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
+                              const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (s < 1 || s > 8) return hipErrorInvalidValue;
   if (k <= 0) return launch_dgemm_f64(m, n, 0, alpha, nullptr, 1, nullptr, 1, beta, C, ldc, gamma, D, ldd, stream);
-  const int64_t mp = pad64(m), np = pad64(n), kp = pad64(k);
+  const int64_t mp = pad128(m), np = pad128(n), kp = pad64(k);
   if (split_workspace_bytes(m, n, k, s) > ws_bytes) return hipErrorInvalidValue;
   uint16_t* Ap = static_cast<uint16_t*>(workspace);
   uint16_t* Bp = Ap + (size_t)s * mp * kp;
   int32_t* ea = reinterpret_cast<int32_t*>(Bp + (size_t)s * np * kp);
   int32_t* fb = ea + mp;
   unsigned long long* bmax = reinterpret_cast<unsigned long long*>(fb + np);  // 8-byte aligned: mp, np even
+  double* Sws = reinterpret_cast<double*>(bmax + np);
   if (gamma == 0.0) D = nullptr;
   hipLaunchKernelGGL(split_rows, dim3((unsigned)(mp / 4)), dim3(256), 0, stream, m, k, A, lda, s, mp, kp, Ap, ea);
   hipLaunchKernelGGL(zero_u64, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream,
@@ -250,8 +372,8 @@ hipError_t launch_split_gemm(int64_t m, int64_t n, int64_t k, int s, double alph
   hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
   hipLaunchKernelGGL(split_cols, dim3((unsigned)(kp / 64), (unsigned)(np / 64)), dim3(256), 0, stream, k, n, B, ldb, s,
                      np, kp, fb, Bp);
-  hipLaunchKernelGGL(split_gemm, dim3((unsigned)(np / 64), (unsigned)(mp / 64)), dim3(256), 0, stream, m, n, kp, s, Ap,
-                     Bp, mp, np, ea, fb, alpha, beta, C, ldc, gamma, D, ldd);
+  hipLaunchKernelGGL(split_gemm, dim3((unsigned)(np / SBN), (unsigned)(mp / SBM)), dim3(256), 0, stream, m, n, kp, s,
+                     Ap, Bp, mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
   return hipGetLastError();
 }
 

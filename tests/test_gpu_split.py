@@ -42,6 +42,8 @@ CASES = [
     (129, 257, 77, 8, -0.75, 2.0, synth.UNIFORM, 5),
     (512, 512, 4096, 6, 1.0, 0.0, synth.NORMAL, 20),
     (33, 17, 5, 7, 1.0, 1.0, synth.UNIFORM, 0),
+    (200, 150, 9000, 6, 1.0, 0.5, synth.NORMAL, 10),   # more than one 8192-k panel
+    (300, 260, 2048, 2, 1.0, 0.0, synth.UNIFORM, 0),   # long exactness windows (t <= 3)
 ]
 
 
@@ -53,7 +55,7 @@ def test_split_kernel_bit_exact_vs_split_reference(case):
     B = np.ascontiguousarray(synth.matrix(k, n, synth.spec(200 + case, 1, dist, col_exp=(-spread, spread))))
     C0 = np.ascontiguousarray(synth.matrix(m, n, synth.spec(200 + case, 2, synth.UNIFORM)))
     got = _device_split(A, B, C0, alpha, beta, s)
-    want = split_ref.split_gemm(alpha, A, B, beta, C0, s)
+    want = split_ref.split_gemm(alpha, A, B, beta, C0, s, kb=8192 if k > 8192 else None)
     assert np.array_equal(got, want), np.max(np.abs(got - want))
     if s >= 6:
         ref, D = oracle.gemm_rows(alpha, A, B, beta, C0)
