@@ -50,7 +50,11 @@ struct Cfg {
   static constexpr size_t LDS_BYTES = 2 * (size_t)BK * ((BM + PAD) + (BN + PAD)) * 8;
 };
 
-template <int BM, int BN, int BK, int WM, int WN, bool VEC, int MINBLOCKS>
+// Tuning knobs: GM = tile rows per L2 group, PRIO = raise the wave priority
+// while it issues its MFMA block, PIPE = load the next k sub-step's operands
+// from LDS before issuing the current sub-step's MFMAs.
+template <int BM, int BN, int BK, int WM, int WN, bool VEC, int MINBLOCKS, int GM = GROUP_M, bool PRIO = false,
+          bool PIPE = false>
 __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
@@ -66,10 +70,10 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
   const int xcd = b & 7, local = b >> 3;
   const int q = ntiles >> 3, r = ntiles & 7;
   const int lin = xcd * q + (xcd < r ? xcd : r) + local;
-  const int group = lin / (GROUP_M * tiles_n);
-  const int first_m = group * GROUP_M;
-  const int gm = (tiles_m - first_m) < GROUP_M ? (tiles_m - first_m) : GROUP_M;
-  const int in_group = lin - group * GROUP_M * tiles_n;
+  const int group = lin / (GM * tiles_n);
+  const int first_m = group * GM;
+  const int gm = (tiles_m - first_m) < GM ? (tiles_m - first_m) : GM;
+  const int in_group = lin - group * GM * tiles_n;
   const int tm = first_m + in_group % gm;
   const int tn = in_group / gm;
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
@@ -146,19 +150,45 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = (int)(kt & 1);
     if (kt + 1 < nk) gload((kt + 1) * BK);
+    if (PRIO) __builtin_amdgcn_s_setprio(1);
+    if (PIPE) {
+      double a[2][FM], bb[2][FN];
 #pragma unroll
-    for (int s = 0; s < BK / 4; ++s) {
-      const int kk = s * 4 + lk;
-      double a[FM], bb[FN];
+      for (int i = 0; i < FM; ++i) a[0][i] = As[buf][lk][am0 + i * 16 + lrow];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = As[buf][kk][am0 + i * 16 + lrow];
+      for (int j = 0; j < FN; ++j) bb[0][j] = Bs[buf][lk][bn0 + j * 16 + lrow];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bb[j] = Bs[buf][kk][bn0 + j * 16 + lrow];
+      for (int s = 0; s < BK / 4; ++s) {
+        const int cur = s & 1;
+        if (s + 1 < BK / 4) {
+          const int kn = (s + 1) * 4 + lk;
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+          for (int i = 0; i < FM; ++i) a[cur ^ 1][i] = As[buf][kn][am0 + i * 16 + lrow];
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < FN; ++j) bb[cur ^ 1][j] = Bs[buf][kn][bn0 + j * 16 + lrow];
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][i], bb[cur][j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < BK / 4; ++s) {
+        const int kk = s * 4 + lk;
+        double a[FM], bb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) a[i] = As[buf][kk][am0 + i * 16 + lrow];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bb[j] = Bs[buf][kk][bn0 + j * 16 + lrow];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+      }
     }
+    if (PRIO) __builtin_amdgcn_s_setprio(0);
     if (kt + 1 < nk) lstore(buf ^ 1);
     __syncthreads();
   }
@@ -186,7 +216,8 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
 
 // Launch one configuration; checks the grid size and picks 16-byte loads when
 // the operands allow them.
-template <int BM, int BN, int BK, int WM, int WN, int MINBLOCKS>
+template <int BM, int BN, int BK, int WM, int WN, int MINBLOCKS, int GM = GROUP_M, bool PRIO = false,
+          bool PIPE = false>
 hipError_t launch(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double beta, double* C, int64_t ldc, double gamma, const double* D, int64_t ldd,
                   hipStream_t stream) {
@@ -200,11 +231,11 @@ hipError_t launch(int64_t m, int64_t n, int64_t k, double alpha, const double* A
   if (gamma == 0.0) D = nullptr;
   dim3 grid((unsigned)(tm * tn)), block(CF::NT);
   if (vec)
-    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, true, MINBLOCKS>), grid, block, 0, stream, m, n, k, alpha, A, lda,
-                       B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn);
+    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, true, MINBLOCKS, GM, PRIO, PIPE>), grid, block, 0, stream, m, n, k,
+                       alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn);
   else
-    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, false, MINBLOCKS>), grid, block, 0, stream, m, n, k, alpha, A,
-                       lda, B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn);
+    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, false, MINBLOCKS, GM, PRIO, PIPE>), grid, block, 0, stream, m, n,
+                       k, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn);
   return hipGetLastError();
 }
 
