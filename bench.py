@@ -31,6 +31,32 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ["paper_1808_05056_amd/csrc/dgemm_f64_kernel.hpp", "paper_1808_05056_amd/csrc/dgemm_f64.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(workload, plan):
+    """HBM bytes per launch of the tile kernel from the committed rocprofv3 counter
+    summary for this workload and plan, if it was taken on the current kernel source."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"dgemm_f64_mfma_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)\s+kernel_source:\s*([0-9a-f]+)\s+plan:\s*(\S+)", text)
+    if not m or m.group(2) != kernel_source_hash() or m.group(3) != plan:
+        return None
+    return float(m.group(1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,8 +154,10 @@ def main():
     roof = None
     if args.profile and kbusy > 0:
         achieved = w.flops * args.steps / kbusy / 1e12
+        plan_tag = "{mb}x{nb}x{kb}/o{order}".format(**plan.as_dict())
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": measured_traffic(w.name, plan_tag),
+                "kernel_source": kernel_source_hash(), "plan_tag": plan_tag,
                 "kernel": "dgemm_f64_mfma", "launches_per_step": nkern // args.steps,
                 "avg_launch_ms": round(kbusy / nkern * 1e3, 4)}
     link = None

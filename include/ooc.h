@@ -93,6 +93,9 @@ typedef struct {
                            >0 (beta != 0 only): C blocks start from zero and the initial C of a block
                            is staged in one of nbuf_d extra buffers (mb x nb) and added, scaled by
                            beta, at one K-panel step chosen to spread these copies over time */
+  int32_t group;        /* orders COLS_P and ROWS_P: C blocks per group; the blocks of a group are
+                           walked K panel by K panel, groups one after another (0: the whole block
+                           column or row is one group); ignored by the other orders */
 } ooc_plan_t;
 
 /* Options; a NULL pointer means all defaults (zero-initialised struct). */

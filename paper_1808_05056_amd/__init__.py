@@ -42,7 +42,8 @@ i32, i64, u64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ct
 
 class ooc_plan_t(ctypes.Structure):
     _fields_ = [("mb", i64), ("nb", i64), ("kb", i64), ("order", i32), ("nbuf_a", i32), ("nbuf_b", i32),
-                ("nbuf_c", i32), ("nstreams", i32), ("precision", i32), ("slices", i32), ("nbuf_d", i32)]
+                ("nbuf_c", i32), ("nstreams", i32), ("precision", i32), ("slices", i32), ("nbuf_d", i32),
+                ("group", i32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -175,8 +176,8 @@ def make_opts(device=0, planner=PLAN_AUTO, precision=FP64, slices=0, nstreams=0,
 
 
 def make_plan(mb, nb, kb, order=ORDER_COLS, nbuf_a=2, nbuf_b=1, nbuf_c=2, nstreams=3, precision=FP64, slices=0,
-              nbuf_d=0):
-    return ooc_plan_t(mb, nb, kb, order, nbuf_a, nbuf_b, nbuf_c, nstreams, precision, slices, nbuf_d)
+              nbuf_d=0, group=0):
+    return ooc_plan_t(mb, nb, kb, order, nbuf_a, nbuf_b, nbuf_c, nstreams, precision, slices, nbuf_d, group)
 
 
 # ---- entry points ---------------------------------------------------------------------

@@ -37,6 +37,7 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
   if (plan.precision == OOC_SPLIT_BF16 && (plan.slices < 1 || plan.slices > 8))
     return fail(OOC_ERR_ARG, "plan: slices must be 1..8");
   if (plan.nbuf_d < 0) return fail(OOC_ERR_ARG, "plan: nbuf_d must be >= 0");
+  if (plan.group < 0) return fail(OOC_ERR_ARG, "plan: group must be >= 0");
   // clamp to the problem (a block larger than the matrix is the matrix)
   const int64_t mb = std::min(plan.mb, std::max<int64_t>(pb.M, 1));
   const int64_t nb = std::min(plan.nb, std::max<int64_t>(pb.N, 1));
@@ -321,8 +322,18 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
     switch (p.order) {
       case OOC_ORDER_COLS: a_loads = (p.nbuf_a >= h * P) ? 1 : (double)w; b_loads = (P == 1 || p.nbuf_b >= P) ? 1 : (double)h; break;
       case OOC_ORDER_ROWS: b_loads = (p.nbuf_b >= w * P) ? 1 : (double)h; a_loads = (P == 1 || p.nbuf_a >= P) ? 1 : (double)w; break;
-      case OOC_ORDER_COLS_P: a_loads = (double)w; b_loads = 1; break;
-      case OOC_ORDER_ROWS_P: a_loads = 1; b_loads = (double)h; break;
+      case OOC_ORDER_COLS_P: {
+        const int64_t gs = p.group > 0 ? std::min<int64_t>(p.group, h) : h;
+        a_loads = (double)w;
+        b_loads = (P == 1 || p.nbuf_b >= P) ? 1 : (double)ceil_div(h, gs);
+        break;
+      }
+      case OOC_ORDER_ROWS_P: {
+        const int64_t gs = p.group > 0 ? std::min<int64_t>(p.group, w) : w;
+        b_loads = (double)h;
+        a_loads = (P == 1 || p.nbuf_a >= P) ? 1 : (double)ceil_div(w, gs);
+        break;
+      }
     }
     const double h2d = 8.0 * ((double)M * K * a_loads + (double)K * N * b_loads + (pb.beta != 0 ? (double)M * N : 0));
     const double d2h = 8.0 * (double)M * N;
@@ -361,16 +372,43 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
             if (w > 1 && w <= 8) { p.order = OOC_ORDER_ROWS; p.nbuf_a = 2; p.nbuf_b = (int)w; p.nbuf_c = 2; consider(p); }
           } else {
             // C-stationary blocks with K panels streamed
+            const int64_t P = ceil_div(K, kb);
             for (int nd : {0, 1}) {
               if (nd && pb.beta == 0.0) continue;
               p.nbuf_d = nd;
               p.nbuf_a = 2; p.nbuf_b = 2; p.nbuf_c = 2;
               p.order = OOC_ORDER_COLS; consider(p);
               p.order = OOC_ORDER_ROWS; consider(p);
+              // a block row's A panels (block column's B panels) resident, plus a
+              // spare buffer so the next row's panels can arrive early
+              if (P <= 16) {
+                p.order = OOC_ORDER_ROWS; p.nbuf_a = (int)P + 1; p.nbuf_b = 2; consider(p);
+                p.order = OOC_ORDER_COLS; p.nbuf_a = 2; p.nbuf_b = (int)P + 1; consider(p);
+                p.nbuf_a = 2; p.nbuf_b = 2;
+              }
               // a resident column (row) of C blocks, K panels outside; with the
               // initial C staged, no spare C buffer is needed at a column change
               if (h <= 64) { p.order = OOC_ORDER_COLS_P; p.nbuf_c = (int)h + (nd ? 0 : 1); consider(p); }
               if (w <= 64) { p.order = OOC_ORDER_ROWS_P; p.nbuf_c = (int)w + (nd ? 0 : 1); consider(p); }
+              // small groups of C blocks walked K panel by K panel with the row's A
+              // panels (column's B panels) resident: the last group of a row frees
+              // its first panels a group's worth of tiles before the row ends, so
+              // the next row's first panels arrive while the row finishes
+              if (P <= 16) {
+                for (int g : {2, 3, 4}) {
+                  for (int spare : {0, 1}) {
+                    if (g < w) {
+                      p.order = OOC_ORDER_ROWS_P; p.group = g; p.nbuf_a = (int)P + spare; p.nbuf_b = 2;
+                      p.nbuf_c = g + (nd ? 0 : 1); consider(p);
+                    }
+                    if (g < h) {
+                      p.order = OOC_ORDER_COLS_P; p.group = g; p.nbuf_a = 2; p.nbuf_b = (int)P + spare;
+                      p.nbuf_c = g + (nd ? 0 : 1); consider(p);
+                    }
+                  }
+                }
+                p.group = 0; p.nbuf_a = 2; p.nbuf_b = 2;
+              }
             }
             p.nbuf_d = 0;
           }

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <climits>
 #include <map>
+#include <set>
 #include <string>
 
 #include "internal.hpp"
@@ -70,7 +71,10 @@ struct Pool {
   }
 };
 
-std::vector<Task> make_tasks(int order, int64_t h, int64_t w, int64_t P) {
+// Tasks in walk order.  The _P orders walk groups of g C blocks of a block
+// column (row) K panel by K panel, the blocks of a group inside; g = 0 means
+// the whole column (row).
+std::vector<Task> make_tasks(int order, int64_t h, int64_t w, int64_t P, int64_t g) {
   std::vector<Task> t;
   t.reserve((size_t)(h * w * P));
   switch (order) {
@@ -84,16 +88,22 @@ std::vector<Task> make_tasks(int order, int64_t h, int64_t w, int64_t P) {
         for (int64_t j = 0; j < w; ++j)
           for (int64_t p = 0; p < P; ++p) t.push_back({i, j, p});
       break;
-    case OOC_ORDER_COLS_P:
+    case OOC_ORDER_COLS_P: {
+      const int64_t gs = g > 0 ? std::min(g, h) : h;
       for (int64_t j = 0; j < w; ++j)
-        for (int64_t p = 0; p < P; ++p)
-          for (int64_t i = 0; i < h; ++i) t.push_back({i, j, p});
+        for (int64_t i0 = 0; i0 < h; i0 += gs)
+          for (int64_t p = 0; p < P; ++p)
+            for (int64_t i = i0; i < std::min(h, i0 + gs); ++i) t.push_back({i, j, p});
       break;
-    case OOC_ORDER_ROWS_P:
+    }
+    case OOC_ORDER_ROWS_P: {
+      const int64_t gs = g > 0 ? std::min(g, w) : w;
       for (int64_t i = 0; i < h; ++i)
-        for (int64_t p = 0; p < P; ++p)
-          for (int64_t j = 0; j < w; ++j) t.push_back({i, j, p});
+        for (int64_t j0 = 0; j0 < w; j0 += gs)
+          for (int64_t p = 0; p < P; ++p)
+            for (int64_t j = j0; j < std::min(w, j0 + gs); ++j) t.push_back({i, j, p});
       break;
+    }
   }
   return t;
 }
@@ -112,6 +122,8 @@ std::vector<int64_t> next_uses(const std::vector<int64_t>& keys) {
 
 }  // namespace
 
+void reorder_h2d(std::vector<ooc_op>* ops);
+
 ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layout& lay,
                           std::vector<ooc_op>* ops_out) {
   std::vector<ooc_op>& ops = *ops_out;
@@ -125,7 +137,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
   const bool split = plan.precision == OOC_SPLIT_BF16 && K > 0;
   const int ns = plan.nstreams;
 
-  std::vector<Task> tasks = make_tasks(plan.order, h, w, P);
+  std::vector<Task> tasks = make_tasks(plan.order, h, w, P, plan.group);
   const int64_t T = (int64_t)tasks.size();
   std::vector<int64_t> ka(T), kbk(T);
   for (int64_t t = 0; t < T; ++t) {
@@ -141,10 +153,16 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
   // K-panel step, spread over the panels so the copies do not bunch up
   const bool staged = lay.nbufD > 0 && pb.beta != 0.0;
   pd.init(staged ? lay.nbufD : 0);
+  // (position within its group * P) / group size for the _P orders
+  auto spread = [&](int64_t x, int64_t n) {
+    const int64_t gs = plan.group > 0 ? std::min<int64_t>(plan.group, n) : n;
+    const int64_t x0 = (x / gs) * gs, len = std::min(n, x0 + gs) - x0;
+    return ((x - x0) * P) / len;
+  };
   auto fold_panel = [&](const Task& tk) -> int64_t {
     if (!staged || P == 1) return 0;
-    if (plan.order == OOC_ORDER_COLS_P) return (tk.i * P) / h;
-    if (plan.order == OOC_ORDER_ROWS_P) return (tk.j * P) / w;
+    if (plan.order == OOC_ORDER_COLS_P) return spread(tk.i, h);
+    if (plan.order == OOC_ORDER_ROWS_P) return spread(tk.j, w);
     return P - 1;
   };
   // C bookkeeping: block key -> buffer, the op that last wrote it
@@ -320,7 +338,69 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
       c_closed_at[sc] = t;
     }
   }
+  if (ns == 3) reorder_h2d(&ops);
   return OOC_OK;
+}
+
+// With a stream of its own for host-to-device copies, the copies run in the
+// order of the buffers they overwrite becoming free (the index of the kernel
+// they wait for; copies into never-used buffers first), not in task order, so a
+// copy whose buffer frees early is not held up behind one that must wait for a
+// later kernel.  This cannot create a cycle: a copy's wait is on a kernel of an
+// earlier task than the copy's own consumer.  The list is then re-emitted as a
+// topological order of waits plus per-stream order, close to the original.
+void reorder_h2d(std::vector<ooc_op>* ops_io) {
+  std::vector<ooc_op>& ops = *ops_io;
+  const int n = (int)ops.size();
+  std::vector<int> h2d;
+  for (int x = 0; x < n; ++x)
+    if (ops[x].kind == OOC_OP_H2D) h2d.push_back(x);
+  auto war = [&](int x) {
+    int w = -1;
+    for (int k = 0; k < ops[x].nwait; ++k) w = std::max(w, ops[x].wait[k]);
+    return w;
+  };
+  std::stable_sort(h2d.begin(), h2d.end(), [&](int a, int b) { return war(a) < war(b); });
+  // predecessors: waits, plus the previous op of the same stream in the new stream order
+  std::vector<std::vector<int>> succ(n);
+  std::vector<int> indeg(n, 0);
+  auto edge = [&](int from, int to) {
+    succ[from].push_back(to);
+    ++indeg[to];
+  };
+  for (int x = 0; x < n; ++x)
+    for (int k = 0; k < ops[x].nwait; ++k) edge(ops[x].wait[k], x);
+  for (size_t q = 1; q < h2d.size(); ++q) edge(h2d[q - 1], h2d[q]);
+  std::vector<int> last(4, -1);
+  for (int x = 0; x < n; ++x) {
+    if (ops[x].kind == OOC_OP_H2D) continue;
+    int& l = last[ops[x].stream];
+    if (l >= 0) edge(l, x);
+    l = x;
+  }
+  // Kahn's algorithm, smallest original index first
+  std::vector<int> order;
+  order.reserve(n);
+  std::set<int> ready;
+  for (int x = 0; x < n; ++x)
+    if (indeg[x] == 0) ready.insert(x);
+  while (!ready.empty()) {
+    const int x = *ready.begin();
+    ready.erase(ready.begin());
+    order.push_back(x);
+    for (int y : succ[x])
+      if (--indeg[y] == 0) ready.insert(y);
+  }
+  if ((int)order.size() != n) return;  // cannot happen (see above); keep the task order
+  std::vector<int> pos(n);
+  for (int q = 0; q < n; ++q) pos[order[q]] = q;
+  std::vector<ooc_op> out(n);
+  for (int q = 0; q < n; ++q) {
+    ooc_op o = ops[order[q]];
+    for (int k = 0; k < o.nwait; ++k) o.wait[k] = pos[o.wait[k]];
+    out[q] = o;
+  }
+  ops.swap(out);
 }
 
 }  // namespace ooc

@@ -75,7 +75,46 @@ PLANS = [
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS, 2, 2, 2, 2, nbuf_d=1)),
     (41, 37, 29, ooc.make_plan(9, 10, 29, ooc.ORDER_COLS, 2, 1, 2, 3, nbuf_d=1)),  # one panel: fold at once
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 5, 1, nbuf_d=1)),
+    # groups of C blocks walked K panel by K panel (ragged last group)
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 4, 2, 4, 3, group=3)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 5, 2, 3, 2, group=2)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 4, 3, 3, nbuf_d=1, group=2)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 3, 2, 3, nbuf_d=2, group=2)),
 ]
+
+
+def test_group_walk_order():
+    # w = 4 C blocks per row, P = 4 panels, groups of 3: blocks 0-2 panel by panel, then block 3
+    plan = ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 4, 2, 4, 3, group=3)
+    ops, _ = ooc.ooc_schedule(41, 37, 29, 1.0, 0.0, plan)
+    walk = [(op["i0"] // 9, op["j0"] // 10, op["k0"] // 8) for op in ops if op["kind"] == "gemm"]
+    row0 = [(0, j, p) for p in range(4) for j in range(3)] + [(0, 3, p) for p in range(4)]
+    assert walk[:16] == row0
+    assert len(walk) == 5 * 4 * 4
+    # group 0 is the whole row; the group size is clamped to the row
+    for g in (0, 4, 9):
+        p0 = ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 4, 2, 5, 3, group=g)
+        ops, _ = ooc.ooc_schedule(41, 37, 29, 1.0, 0.0, p0)
+        walk = [(op["i0"] // 9, op["j0"] // 10, op["k0"] // 8) for op in ops if op["kind"] == "gemm"]
+        assert walk[:16] == [(0, j, p) for p in range(4) for j in range(4)]
+    with pytest.raises(ooc.OOCError):
+        ooc.ooc_schedule(41, 37, 29, 1.0, 0.0, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 4, 2, 4, 3, group=-1))
+
+
+def test_copies_in_order_of_free_buffers():
+    # with a copy stream, each copy waits for at most kernels that precede every
+    # later copy's wait: the copy stream never idles behind a copy whose buffer
+    # frees later than the next one's
+    M, N, K = 41, 37, 29
+    plan = ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 4, 2, 4, 3, group=3)
+    ops, _ = ooc.ooc_schedule(M, N, K, 1.0, 0.5, plan)
+    rank = {x: r for r, x in enumerate(x for x, op in enumerate(ops) if op["kind"] == "gemm")}
+    for x, op in enumerate(ops):  # a copy back to the host ranks just after its kernel
+        if op["kind"] == "d2h":
+            rank[x] = max(rank[y] for y in op["waits"]) + 0.5
+    war = [max([rank[y] for y in op["waits"]], default=-1) for op in ops if op["kind"] == "h2d"]
+    assert war == sorted(war)
+    assert sched_ref.check_hazards(ops) == []
 
 
 @pytest.mark.parametrize("beta", [0.0, 0.5])

@@ -85,6 +85,8 @@ SMALL_PLANS = [
     ("one-stream", ooc.make_plan(128, 512, 1024, ooc.ORDER_COLS, 2, 1, 2, 1), None),
     ("colsp-staged", ooc.make_plan(256, 256, 256, ooc.ORDER_COLS_P, 2, 2, 4, 3, nbuf_d=1), None),
     ("rows-ksplit-staged", ooc.make_plan(384, 256, 320, ooc.ORDER_ROWS, 2, 2, 2, 3, nbuf_d=1), None),
+    ("rowsp-group2", ooc.make_plan(256, 256, 256, ooc.ORDER_ROWS_P, 4, 2, 3, 3, group=2), None),
+    ("colsp-group3-staged", ooc.make_plan(256, 256, 256, ooc.ORDER_COLS_P, 2, 4, 3, 3, nbuf_d=1, group=3), None),
 ]
 
 

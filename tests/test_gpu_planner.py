@@ -1,0 +1,53 @@
+"""The learned planner on the GPU: fitting a network to synthetic timings with
+the library's kernels, and what the trained planner network gains over the
+method without it (the paper's partition rule) on problems of the evaluation
+batch, measured."""
+import os
+
+import numpy as np
+import pytest
+
+from synth import workloads as W
+import paper_1808_05056_amd as ooc
+from gpu_helpers import PinnedProblem
+
+pytestmark = pytest.mark.gpu
+WEIGHTS = os.path.join(os.path.dirname(ooc.LIB_PATH), "planner_mlp.txt")
+
+
+def test_fit_learns_a_timing_function():
+    plans, model_s = ooc.ooc_plan_candidates(20000, 16000, 12000, 0.0, 2 << 30)
+    X = ooc.ooc_mlp_features(20000, 16000, 12000, 0.0, 2 << 30, plans)
+    # a synthetic "measured" time: the model's time with a penalty for one stream
+    t = np.array(model_s) * np.where(X[:, 15] == 1, 1.8, 1.0)
+    hist = ooc.ooc_mlp_fit(X, t, hidden=32, epochs=1500, lr=3e-3, seed=3)
+    assert hist[-1] < 0.05 * hist[0]
+    pred = ooc.ooc_mlp_predict(20000, 16000, 12000, 0.0, 2 << 30, plans)
+    assert np.corrcoef(np.log(pred), np.log(t))[0, 1] > 0.95
+    # restore the shipped network (if any) for the planner tests
+    if os.path.exists(WEIGHTS):
+        ooc.ooc_mlp_load(WEIGHTS)
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained planner network shipped with the library")
+def test_learned_planner_beats_the_papers_rule():
+    ooc.ooc_mlp_load(WEIGHTS)
+    problems = [w for w in W.problem_batch(4, count=64) if w.flops < 4e12][:4]
+    assert problems
+    gains = []
+    for w in problems:
+        pp = PinnedProblem(w)
+        try:
+            times = {}
+            for name, planner in (("mlp", ooc.PLAN_MLP), ("paper", ooc.PLAN_PAPER)):
+                opts = ooc.make_opts(planner=planner)
+                ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, opts)
+                best = min(ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, opts)[1].t_pipeline_s
+                           for _ in range(2))
+                times[name] = best
+            gains.append(times["paper"] / times["mlp"])
+            print(f"M={w.M} N={w.N} K={w.K} budget={w.budget >> 20} MiB: paper {times['paper']:.4f}s "
+                  f"learned {times['mlp']:.4f}s", flush=True)
+        finally:
+            pp.free()
+    assert np.mean(gains) > 1.0, gains
