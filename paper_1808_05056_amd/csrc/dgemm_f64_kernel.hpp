@@ -12,6 +12,9 @@
 //     two steps, so one barrier per step suffices;
 //   * A is stored transposed in LDS (k-major) so that the 16 lanes feeding one
 //     MFMA row read 16 consecutive doubles, like the B reads;
+//   * optionally (PRIO) a wave raises its priority while it issues the step's
+//     matrix instructions and lowers it before its global-load and LDS-store
+//     phase, so the wave sharing its SIMD that has MFMAs ready is favoured;
 //   * workgroups are numbered so that each of the 8 XCDs (workgroups are dealt
 //     to them round robin) receives a contiguous band of tiles, ordered in
 //     groups of GROUP_M tile rows so that concurrently running tiles share A

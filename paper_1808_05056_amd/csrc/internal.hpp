@@ -56,12 +56,12 @@ struct Machine {
   double d2h_gbs = 57.1;      // device -> pinned host
   double duplex_gbs = 48.7;   // each direction when both are active
   double copy_latency_s = 12e-6;
-  double kernel_tflops = 66.9;     // FP64 tile kernel, two workgroups per CU, large k
-  double kernel_tflops_1wg = 55.8; // same with one workgroup per CU
-  double kernel_k0 = 64.0;         // per-tile fixed cost in units of k
+  double kernel_tflops = 72.85;    // FP64 tile kernel, two workgroups per CU, large k
+  double kernel_tflops_1wg = 38.0; // same with one workgroup per CU
+  double kernel_k0 = 30.0;         // per-tile fixed cost in units of k
   double kernel_scalar_factor = 1.15;  // odd leading dimensions (8-byte loads)
   double kernel_launch_s = 6e-6;
-  double split_tflops_per_product = 1500.0; // BF16 slice-product rate (TFLOP/s of BF16 work)
+  double split_tflops_per_product = 177.0;  // BF16 slice-product rate incl. slicing (TFLOP/s of BF16 work)
   int cus = 256;
 };
 const Machine& machine();

@@ -260,3 +260,14 @@ def test_planner_features():
     assert np.allclose(X[:, 7:11].sum(axis=1), 1)
     # the cost-model feature is log2 of the candidate's modelled time
     assert np.allclose(X[:, 16], np.log2(times[:10]), atol=1e-5)
+
+
+def test_gpu_test_plans_fit_their_budgets():
+    # the fixed plans of the GPU tests must fit the 8 MiB budget of their workload
+    import test_gpu_parity
+    for name, plan, _ in test_gpu_parity.SMALL_PLANS:
+        if plan is not None:
+            for beta in (0.0, 0.5):
+                assert ooc.ooc_plan_footprint(1024, 1024, 1024, beta, plan) <= 8 << 20, name
+    split_plan = ooc.make_plan(256, 320, 320, ooc.ORDER_COLS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
+    assert ooc.ooc_plan_footprint(1000, 900, 1100, 0.5, split_plan) <= 8 << 20

@@ -102,9 +102,9 @@ def test_split_pipeline_bit_exact(planner):
                                      ooc.make_opts(planner=ooc.PLAN_PAPER, precision=ooc.SPLIT_BF16, slices=6))
             kb = None
         else:
-            plan = ooc.make_plan(256, 320, 384, ooc.ORDER_COLS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
+            plan = ooc.make_plan(256, 320, 320, ooc.ORDER_COLS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
             st, stats = ooc.ooc_gemm_planned(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, plan)
-            kb = 384
+            kb = 320
         assert stats.arena_bytes <= w.budget and stats.plan.precision == ooc.SPLIT_BF16
         want = split_ref.split_gemm(w.alpha, pp.A, pp.B, w.beta, C0, 6, kb=kb)
         assert np.array_equal(pp.C, want)
