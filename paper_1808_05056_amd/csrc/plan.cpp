@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <thread>
 #include <tuple>
 
 #include "internal.hpp"
@@ -276,10 +277,12 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
 
 static std::vector<int64_t> split_sizes(int64_t n, int64_t align, int max_parts) {
   std::set<int64_t> out;
+  // block sizes are multiples of the kernel tile (or the whole extent when
+  // it is smaller): a block narrower than a tile wastes most of the tile
   for (int parts = 1; parts <= max_parts; ++parts) {
     int64_t s = ceil_div(n, parts);
-    if (align > 1 && s > align) s = ceil_div(s, align) * align;
-    if (s >= 1) out.insert(std::min(s, n));
+    if (align > 1) s = ceil_div(s, align) * align;
+    out.insert(std::min(s, n));
   }
   return std::vector<int64_t>(out.begin(), out.end());
 }
@@ -306,6 +309,9 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
   const Machine& mc = machine();
   struct Cand { ooc_plan_t p; double lb; };
   std::vector<Cand> cands;
+  std::vector<int> stream_opts = {1, 2, 3};
+  if (want_streams >= 1 && want_streams <= 3) stream_opts = {want_streams};
+  double t_comp = 0.0;  // kernel-time bound of the current (mb, nb, kb)
   auto consider = [&](ooc_plan_t p) {
     Layout lay;
     p.precision = prec;
@@ -338,95 +344,119 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
     const double h2d = 8.0 * ((double)M * K * a_loads + (double)K * N * b_loads + (pb.beta != 0 ? (double)M * N : 0));
     const double d2h = 8.0 * (double)M * N;
     const double t_link = std::max(h2d / (mc.h2d_gbs * 1e9), d2h / (mc.d2h_gbs * 1e9));
-    // kernel time from the tile model: full blocks plus the ragged edge blocks
-    const int64_t mr = M - (h - 1) * p.mb, nr = N - (w - 1) * p.nb;
-    const int64_t kr = K > 0 ? K - (P - 1) * p.kb : 0;
-    auto kt = [&](int64_t m, int64_t n) {
-      double t = (double)(P - 1) * kernel_seconds(mc, m, n, p.kb, prec == OOC_SPLIT_BF16, p.slices);
-      return t + kernel_seconds(mc, m, n, kr, prec == OOC_SPLIT_BF16, p.slices);
-    };
-    const double t_comp = (double)(h - 1) * (w - 1) * kt(p.mb, p.nb) + (double)(h - 1) * kt(p.mb, nr) +
-                          (double)(w - 1) * kt(mr, p.nb) + kt(mr, nr);
-    cands.push_back({p, std::max(t_link, t_comp)});
+    // the bound does not depend on the stream count: one entry per count
+    for (int ns : stream_opts) {
+      p.nstreams = ns;
+      cands.push_back({p, std::max(t_link, t_comp)});
+    }
   };
   const int max_parts = 64;
   std::vector<int64_t> mbs = split_sizes(M, 128, max_parts), nbs = split_sizes(N, 128, max_parts);
   std::vector<int64_t> kbs = K > 0 ? panel_sizes(K) : std::vector<int64_t>{0};
-  std::vector<int> stream_opts = {1, 2, 3};
-  if (want_streams >= 1 && want_streams <= 3) stream_opts = {want_streams};
-  for (int ns : stream_opts) {
-    for (int64_t mb : mbs) {
-      for (int64_t nb : nbs) {
-        const int64_t h = ceil_div(M, mb), w = ceil_div(N, nb);
-        for (int64_t kb : kbs) {
-          ooc_plan_t p{};
-          p.mb = mb; p.nb = nb; p.kb = kb; p.nstreams = ns;
-          const bool fullk = (K == 0 || kb >= K);
-          // the paper's structure and its transpose (K whole)
-          if (fullk) {
-            for (int nbr : {1, 2}) {
-              p.order = OOC_ORDER_COLS; p.nbuf_a = 2; p.nbuf_b = nbr; p.nbuf_c = 2; consider(p);
-              p.order = OOC_ORDER_ROWS; p.nbuf_a = nbr; p.nbuf_b = 2; p.nbuf_c = 2; consider(p);
+  for (int64_t mb : mbs) {
+    for (int64_t nb : nbs) {
+      const int64_t h = ceil_div(M, mb), w = ceil_div(N, nb);
+      for (int64_t kb : kbs) {
+        // kernel time from the tile model (full blocks plus the ragged edge
+        // blocks), the same for every buffer and order variant below
+        {
+          const int64_t P = K > 0 ? ceil_div(K, kb) : 1;
+          const int64_t mr = M - (h - 1) * mb, nr = N - (w - 1) * nb;
+          const int64_t kr = K > 0 ? K - (P - 1) * kb : 0;
+          auto kt = [&](int64_t m, int64_t n) {
+            double t = (double)(P - 1) * kernel_seconds(mc, m, n, kb, prec == OOC_SPLIT_BF16, slices);
+            return t + kernel_seconds(mc, m, n, kr, prec == OOC_SPLIT_BF16, slices);
+          };
+          t_comp = (double)(h - 1) * (w - 1) * kt(mb, nb) + (double)(h - 1) * kt(mb, nr) +
+                   (double)(w - 1) * kt(mr, nb) + kt(mr, nr);
+        }
+        ooc_plan_t p{};
+        p.mb = mb; p.nb = nb; p.kb = kb; p.nstreams = 3;
+        const bool fullk = (K == 0 || kb >= K);
+        // the paper's structure and its transpose (K whole)
+        if (fullk) {
+          for (int nbr : {1, 2}) {
+            p.order = OOC_ORDER_COLS; p.nbuf_a = 2; p.nbuf_b = nbr; p.nbuf_c = 2; consider(p);
+            p.order = OOC_ORDER_ROWS; p.nbuf_a = nbr; p.nbuf_b = 2; p.nbuf_c = 2; consider(p);
+          }
+          if (h > 1 && h <= 8) { p.order = OOC_ORDER_COLS; p.nbuf_a = (int)h; p.nbuf_b = 2; p.nbuf_c = 2; consider(p); }
+          if (w > 1 && w <= 8) { p.order = OOC_ORDER_ROWS; p.nbuf_a = 2; p.nbuf_b = (int)w; p.nbuf_c = 2; consider(p); }
+        } else {
+          // C-stationary blocks with K panels streamed
+          const int64_t P = ceil_div(K, kb);
+          for (int nd : {0, 1}) {
+            if (nd && pb.beta == 0.0) continue;
+            p.nbuf_d = nd;
+            p.nbuf_a = 2; p.nbuf_b = 2; p.nbuf_c = 2;
+            p.order = OOC_ORDER_COLS; consider(p);
+            p.order = OOC_ORDER_ROWS; consider(p);
+            // a block row's A panels (block column's B panels) resident, plus a
+            // spare buffer so the next row's panels can arrive early
+            if (P <= 16) {
+              p.order = OOC_ORDER_ROWS; p.nbuf_a = (int)P + 1; p.nbuf_b = 2; consider(p);
+              p.order = OOC_ORDER_COLS; p.nbuf_a = 2; p.nbuf_b = (int)P + 1; consider(p);
+              p.nbuf_a = 2; p.nbuf_b = 2;
             }
-            if (h > 1 && h <= 8) { p.order = OOC_ORDER_COLS; p.nbuf_a = (int)h; p.nbuf_b = 2; p.nbuf_c = 2; consider(p); }
-            if (w > 1 && w <= 8) { p.order = OOC_ORDER_ROWS; p.nbuf_a = 2; p.nbuf_b = (int)w; p.nbuf_c = 2; consider(p); }
-          } else {
-            // C-stationary blocks with K panels streamed
-            const int64_t P = ceil_div(K, kb);
-            for (int nd : {0, 1}) {
-              if (nd && pb.beta == 0.0) continue;
-              p.nbuf_d = nd;
-              p.nbuf_a = 2; p.nbuf_b = 2; p.nbuf_c = 2;
-              p.order = OOC_ORDER_COLS; consider(p);
-              p.order = OOC_ORDER_ROWS; consider(p);
-              // a block row's A panels (block column's B panels) resident, plus a
-              // spare buffer so the next row's panels can arrive early
-              if (P <= 16) {
-                p.order = OOC_ORDER_ROWS; p.nbuf_a = (int)P + 1; p.nbuf_b = 2; consider(p);
-                p.order = OOC_ORDER_COLS; p.nbuf_a = 2; p.nbuf_b = (int)P + 1; consider(p);
-                p.nbuf_a = 2; p.nbuf_b = 2;
-              }
-              // a resident column (row) of C blocks, K panels outside; with the
-              // initial C staged, no spare C buffer is needed at a column change
-              if (h <= 64) { p.order = OOC_ORDER_COLS_P; p.nbuf_c = (int)h + (nd ? 0 : 1); consider(p); }
-              if (w <= 64) { p.order = OOC_ORDER_ROWS_P; p.nbuf_c = (int)w + (nd ? 0 : 1); consider(p); }
-              // small groups of C blocks walked K panel by K panel with the row's A
-              // panels (column's B panels) resident: the last group of a row frees
-              // its first panels a group's worth of tiles before the row ends, so
-              // the next row's first panels arrive while the row finishes
-              if (P <= 16) {
-                for (int g : {2, 3, 4}) {
-                  for (int spare : {0, 1}) {
+            // a resident column (row) of C blocks, K panels outside; with the
+            // initial C staged, no spare C buffer is needed at a column change
+            if (h <= 64) { p.order = OOC_ORDER_COLS_P; p.nbuf_c = (int)h + (nd ? 0 : 1); consider(p); }
+            if (w <= 64) { p.order = OOC_ORDER_ROWS_P; p.nbuf_c = (int)w + (nd ? 0 : 1); consider(p); }
+            // small groups of C blocks walked K panel by K panel with the row's A
+            // panels (column's B panels) resident: the last group of a row frees
+            // its first panels a group's worth of tiles before the row ends, so
+            // the next row's first panels arrive while the row finishes
+            if (P <= 16) {
+              for (int g : {2, 3, 4}) {
+                for (int spare : {0, 1}) {
+                  for (int stream_buf : {2, 3}) {  // buffers of the streamed operand
                     if (g < w) {
-                      p.order = OOC_ORDER_ROWS_P; p.group = g; p.nbuf_a = (int)P + spare; p.nbuf_b = 2;
+                      p.order = OOC_ORDER_ROWS_P; p.group = g; p.nbuf_a = (int)P + spare; p.nbuf_b = stream_buf;
                       p.nbuf_c = g + (nd ? 0 : 1); consider(p);
                     }
                     if (g < h) {
-                      p.order = OOC_ORDER_COLS_P; p.group = g; p.nbuf_a = 2; p.nbuf_b = (int)P + spare;
+                      p.order = OOC_ORDER_COLS_P; p.group = g; p.nbuf_a = stream_buf; p.nbuf_b = (int)P + spare;
                       p.nbuf_c = g + (nd ? 0 : 1); consider(p);
                     }
                   }
                 }
-                p.group = 0; p.nbuf_a = 2; p.nbuf_b = 2;
               }
+              p.group = 0; p.nbuf_a = 2; p.nbuf_b = 2;
             }
-            p.nbuf_d = 0;
           }
+          p.nbuf_d = 0;
         }
       }
     }
   }
   if (cands.empty()) return fail(OOC_ERR_BUDGET, "no plan fits in the device budget");
   std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.lb < b.lb; });
-  const size_t keep = std::min<size_t>(cands.size(), 96);
-  std::vector<std::pair<double, ooc_plan_t>> sim;
-  for (size_t c = 0; c < keep; ++c) {
-    Layout lay;
-    plan_layout(pb, cands[c].p, &lay);
-    std::vector<ooc_op> ops;
-    if (build_schedule(pb, cands[c].p, lay, &ops) != OOC_OK) continue;
-    sim.push_back({simulate(pb, cands[c].p, ops), cands[c].p});
+  // simulate the most promising candidates (fewer for products that take
+  // milliseconds, where planning time would show), spread over host threads;
+  // results are collected in candidate order, so the choice is deterministic
+  const bool small = 2.0 * (double)M * N * std::max<int64_t>(K, 1) < 1e11;
+  const size_t keep = std::min<size_t>(cands.size(), small ? 64 : 384);
+  std::vector<double> simt(keep, -1.0);
+  auto work = [&](size_t first, size_t stride) {
+    for (size_t c = first; c < keep; c += stride) {
+      Layout lay;
+      plan_layout(pb, cands[c].p, &lay);
+      std::vector<ooc_op> ops;
+      if (build_schedule(pb, cands[c].p, lay, &ops) != OOC_OK) continue;
+      simt[c] = simulate(pb, cands[c].p, ops);
+    }
+  };
+  const size_t nthreads = std::min<size_t>({(size_t)std::max(1u, std::thread::hardware_concurrency()), 8, keep});
+  if (nthreads <= 1 || small) {
+    work(0, 1);
+  } else {
+    std::vector<std::thread> pool;
+    for (size_t t = 1; t < nthreads; ++t) pool.emplace_back(work, t, nthreads);
+    work(0, nthreads);
+    for (auto& th : pool) th.join();
   }
+  std::vector<std::pair<double, ooc_plan_t>> sim;
+  for (size_t c = 0; c < keep; ++c)
+    if (simt[c] >= 0) sim.push_back({simt[c], cands[c].p});
   if (sim.empty()) return fail(OOC_ERR_BUDGET, "no schedulable plan fits in the device budget");
   std::stable_sort(sim.begin(), sim.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
   for (auto& s : sim) {
