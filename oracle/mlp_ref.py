@@ -7,7 +7,9 @@ small regression network that predicts the log run time of a candidate plan
 from its features; the plan with the smallest prediction is taken.
 
 Network (FP64 here): x (d) -> tanh(x W1 + b1) (H) -> tanh(. W2 + b2) (H) -> . W3 + b3 (1)
-Loss: mean squared error L = (1/n) sum (y - t)^2.
+Loss: mean squared error L = (1/n) sum (y - t)^2, optionally plus an L2
+penalty (wd/2) * (|W1|^2 + |W2|^2 + |W3|^2) on the weight matrices (biases are
+not penalised), whose gradient adds wd * W to each weight matrix's gradient.
 Optimiser: Adam (Kingma and Ba, ICLR 2015) with bias correction:
     m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
     theta -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
@@ -47,8 +49,14 @@ def mse(y, t):
     return float(np.sum(d * d) / n), 2.0 * d / n
 
 
-def backward(P, cache, dy):
-    """Gradients of the loss w.r.t. every parameter, given dL/dy (shape (n,))."""
+def penalty(P, wd):
+    """The L2 penalty (wd/2) * sum of the squared weight-matrix entries."""
+    return 0.5 * wd * sum(float(np.sum(P[k] * P[k])) for k in ("W1", "W2", "W3"))
+
+
+def backward(P, cache, dy, wd=0.0):
+    """Gradients of the loss w.r.t. every parameter, given dL/dy (shape (n,)),
+    plus the gradient wd * W of the L2 penalty on the weight matrices."""
     X, H1, H2 = cache
     g = {}
     dY = dy[:, None]
@@ -60,6 +68,9 @@ def backward(P, cache, dy):
     dZ1 = (dZ2 @ P["W2"].T) * (1.0 - H1 * H1)
     g["W1"] = X.T @ dZ1
     g["b1"] = dZ1.sum(axis=0)
+    if wd:
+        for k in ("W1", "W2", "W3"):
+            g[k] = g[k] + wd * P[k]
     return g
 
 
@@ -79,8 +90,9 @@ def adam_step(P, g, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return P
 
 
-def train(P, X, t, epochs, lr=1e-3, batch=None, seed=0):
-    """Full-batch (batch=None) or minibatch Adam training; returns the loss history."""
+def train(P, X, t, epochs, lr=1e-3, batch=None, seed=0, wd=0.0):
+    """Full-batch (batch=None) or minibatch Adam training; returns the history of
+    the objective (loss plus penalty)."""
     st = adam_init(P)
     rng = np.random.default_rng(seed)
     hist = []
@@ -89,14 +101,14 @@ def train(P, X, t, epochs, lr=1e-3, batch=None, seed=0):
         if batch is None:
             y, c = forward(P, X)
             L, dy = mse(y, t)
-            adam_step(P, backward(P, c, dy), st, lr=lr)
-            hist.append(L)
+            hist.append(L + penalty(P, wd))
+            adam_step(P, backward(P, c, dy, wd), st, lr=lr)
         else:
             perm = rng.permutation(n)
             for s in range(0, n, batch):
                 idx = perm[s:s + batch]
                 y, c = forward(P, X[idx])
                 L, dy = mse(y, t[idx])
-                adam_step(P, backward(P, c, dy), st, lr=lr)
-            hist.append(mse(forward(P, X)[0], t)[0])
+                adam_step(P, backward(P, c, dy, wd), st, lr=lr)
+            hist.append(mse(forward(P, X)[0], t)[0] + penalty(P, wd))
     return hist

@@ -73,3 +73,35 @@ def test_training_reduces_loss():
     P = mlp_ref.init(5, 32, seed=5)
     hist = mlp_ref.train(P, X, t, epochs=300, lr=3e-3)
     assert hist[-1] < 0.2 * hist[0]
+
+
+def test_weight_decay_gradient_matches_finite_differences():
+    # objective = mse + (wd/2)|W|^2 over the weight matrices; biases unpenalised
+    d, H, n, wd = 4, 5, 9, 0.37
+    P = mlp_ref.init(d, H, seed=11)
+    for k in P:
+        P[k] = P[k] + 0.2 * np.random.default_rng(12).standard_normal(P[k].shape)
+    X, t = _data(n, d, 13)
+    y, c = mlp_ref.forward(P, X)
+    _, dy = mlp_ref.mse(y, t)
+    g = mlp_ref.backward(P, c, dy, wd)
+
+    def objective():
+        return mlp_ref.mse(mlp_ref.forward(P, X)[0], t)[0] + mlp_ref.penalty(P, wd)
+
+    h = 1e-6
+    for k in mlp_ref.PARAM_NAMES:
+        flat = P[k].reshape(-1)
+        for idx in range(flat.size):
+            old = flat[idx]
+            flat[idx] = old + h
+            Lp = objective()
+            flat[idx] = old - h
+            Lm = objective()
+            flat[idx] = old
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - g[k].reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)), (k, idx)
+    # the penalty of a hand-made parameter set
+    Q = {"W1": np.array([[1.0, 2.0]]), "b1": np.array([5.0, 5.0]), "W2": np.array([[3.0, 0.0], [0.0, 0.0]]),
+         "b2": np.zeros(2), "W3": np.array([[0.0], [-1.0]]), "b3": np.array([9.0])}
+    assert mlp_ref.penalty(Q, 0.5) == 0.25 * (1 + 4 + 9 + 1)
