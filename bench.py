@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "OOC DGEMM end-to-end TFLOP/s, FP64 vs split-BF16 at equal error; link GB/s"
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+LINK_PEAK_GBPS = 63.0  # PCIe 5.0 x16, one direction (32 GT/s x 16 lanes, 128b/130b)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -153,19 +155,33 @@ def main():
 
     roof = None
     if args.profile and kbusy > 0:
-        achieved = w.flops * args.steps / kbusy / 1e12
         plan_tag = "{mb}x{nb}x{kb}/o{order}".format(**plan.as_dict())
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": measured_traffic(w.name, plan_tag),
+        if prec == ooc.FP64:
+            peak, work, kname = PEAK_FP64_TFLOPS, w.flops, "dgemm_f64_mfma"
+            traffic = measured_traffic(w.name, plan_tag)
+        else:  # BF16 matrix work of the slice products (kernel time includes slicing)
+            peak, work, kname = PEAK_BF16_TFLOPS, w.flops * args.slices * (args.slices + 1) / 2, "split_gemm"
+            traffic = None
+        achieved = work * args.steps / kbusy / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel_source": kernel_source_hash(), "plan_tag": plan_tag,
-                "kernel": "dgemm_f64_mfma", "launches_per_step": nkern // args.steps,
+                "kernel": kname, "launches_per_step": nkern // args.steps,
                 "avg_launch_ms": round(kbusy / nkern * 1e3, 4)}
     link = None
     if args.profile and hbusy > 0:
         link = {"h2d_GBps": round(s1.bytes_h2d * args.steps / hbusy / 1e9, 2),
                 "d2h_GBps": round(s1.bytes_d2h * args.steps / dbusy / 1e9, 2) if dbusy > 0 else None,
                 "h2d_bytes_per_step": int(s1.bytes_h2d), "d2h_bytes_per_step": int(s1.bytes_d2h),
-                "h2d_busy_frac": round(hbusy / elapsed, 3), "kernel_busy_frac": round(kbusy / elapsed, 3)}
+                "h2d_busy_frac": round(hbusy / elapsed, 3), "kernel_busy_frac": round(kbusy / elapsed, 3),
+                "h2d_frac_of_link_peak": round(s1.bytes_h2d * args.steps / hbusy / 1e9 / LINK_PEAK_GBPS, 3)}
+    # end-to-end roofline: min(matrix peak, link peak x the plan's flops per host-to-device byte)
+    ai = w.flops / max(s1.bytes_h2d, 1)
+    compute_peak = (PEAK_FP64_TFLOPS if prec == ooc.FP64
+                    else PEAK_BF16_TFLOPS / (args.slices * (args.slices + 1) / 2))  # FP64-equivalent
+    e2e_roof = min(compute_peak, ai * LINK_PEAK_GBPS * 1e9 / 1e12)
+    e2e = {"tflops": round(e2e_roof, 3), "flop_per_h2d_byte": round(ai, 2), "link_peak_GBps": LINK_PEAK_GBPS,
+           "frac": round(value / e2e_roof, 4)}
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak",
@@ -174,7 +190,7 @@ def main():
         "config": {"workload": w.name, "M": w.M, "N": w.N, "K": w.K, "alpha": w.alpha, "beta": w.beta,
                    "budget_bytes": w.budget, "planner": args.planner, "plan": plan.as_dict(),
                    "arena_bytes": int(s1.arena_bytes), "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "link": link,
+        "roofline": roof, "cpu_baseline": cpu, "link": link, "end_to_end_roofline": e2e,
         "max_normalized_error": err, "predicted_s": round(s1.t_predicted_s, 4),
     }
     print(json.dumps(out), flush=True)

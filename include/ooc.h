@@ -276,28 +276,31 @@ ooc_status ooc_mlp_features(int64_t M, int64_t N, int64_t K, double beta, size_t
 ooc_status ooc_mlp_forward(int32_t device, int32_t d, int32_t hidden, const float* params, const float* X,
                            int64_t n, float* y_out);
 
-/* Mean squared error of the predictions against t and its gradient with
- * respect to every parameter (grad_out: same layout as params). */
+/* Objective = mean squared error of the predictions against t plus
+ * (weight_decay/2) times the sum of squares of the weight matrices W1, W2, W3
+ * (biases unpenalised; weight_decay >= 0), and its gradient with respect to
+ * every parameter (grad_out: same layout as params). */
 ooc_status ooc_mlp_grad(int32_t device, int32_t d, int32_t hidden, const float* params, const float* X,
-                        const float* t, int64_t n, float* grad_out, float* loss_out);
+                        const float* t, int64_t n, float weight_decay, float* grad_out, float* loss_out);
 
 /* One Adam step (bias-corrected; step counts from 1) on count parameters;
  * params, m and v are updated in place. */
 ooc_status ooc_mlp_adam(int32_t device, int64_t count, float* params, const float* grad, float* m, float* v,
                         int32_t step, float lr, float beta1, float beta2, float eps);
 
-/* epochs of full-batch Adam (lr, betas 0.9/0.999, eps 1e-8) on the GPU,
- * params updated in place; loss_hist (optional) receives the loss before each
- * step. */
+/* epochs of full-batch Adam (lr, betas 0.9/0.999, eps 1e-8) on the GPU on the
+ * objective of ooc_mlp_grad, params updated in place; loss_hist (optional)
+ * receives the objective before each step. */
 ooc_status ooc_mlp_train(int32_t device, int32_t d, int32_t hidden, float* params, const float* X,
-                         const float* t, int64_t n, int32_t epochs, float lr, float* loss_hist);
+                         const float* t, int64_t n, int32_t epochs, float lr, float weight_decay,
+                         float* loss_hist);
 
 /* Train the planner network from measured timings (seconds) of candidate
  * plans whose features are X (n x OOC_MLP_FEATURES): features and log-times
  * are standardised, weights drawn from seed, then ooc_mlp_train; the result
  * becomes the network OOC_PLAN_MLP uses. */
 ooc_status ooc_mlp_fit(int32_t device, const float* X, const float* y_seconds, int64_t n, int32_t hidden,
-                       int32_t epochs, float lr, uint64_t seed, float* loss_hist);
+                       int32_t epochs, float lr, float weight_decay, uint64_t seed, float* loss_hist);
 
 /* Save / load the planner network (text file: sizes, standardisation, weights). */
 ooc_status ooc_mlp_save(const char* path);

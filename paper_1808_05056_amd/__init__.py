@@ -113,11 +113,11 @@ _sig("ooc_split_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i
 P_flt = ctypes.POINTER(ctypes.c_float)
 _sig("ooc_mlp_features", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P_flt])
 _sig("ooc_mlp_forward", i32, [i32, i32, i32, P_flt, P_flt, i64, P_flt])
-_sig("ooc_mlp_grad", i32, [i32, i32, i32, P_flt, P_flt, P_flt, i64, P_flt, P_flt])
+_sig("ooc_mlp_grad", i32, [i32, i32, i32, P_flt, P_flt, P_flt, i64, ctypes.c_float, P_flt, P_flt])
 _sig("ooc_mlp_adam", i32, [i32, i64, P_flt, P_flt, P_flt, P_flt, i32, ctypes.c_float, ctypes.c_float,
                            ctypes.c_float, ctypes.c_float])
-_sig("ooc_mlp_train", i32, [i32, i32, i32, P_flt, P_flt, P_flt, i64, i32, ctypes.c_float, P_flt])
-_sig("ooc_mlp_fit", i32, [i32, P_flt, P_flt, i64, i32, i32, ctypes.c_float, u64, P_flt])
+_sig("ooc_mlp_train", i32, [i32, i32, i32, P_flt, P_flt, P_flt, i64, i32, ctypes.c_float, ctypes.c_float, P_flt])
+_sig("ooc_mlp_fit", i32, [i32, P_flt, P_flt, i64, i32, i32, ctypes.c_float, ctypes.c_float, u64, P_flt])
 _sig("ooc_mlp_save", i32, [ctypes.c_char_p])
 _sig("ooc_mlp_load", i32, [ctypes.c_char_p])
 _sig("ooc_mlp_loaded", i32, [])
@@ -402,13 +402,14 @@ def ooc_mlp_forward(d, H, params, X, device=0):
     return y
 
 
-def ooc_mlp_grad(d, H, params, X, t, device=0):
+def ooc_mlp_grad(d, H, params, X, t, weight_decay=0.0, device=0):
     p, pp = _f32(params)
     x, px = _f32(X)
     tt, pt = _f32(t)
     g = np.zeros(p.size, dtype=np.float32)
     loss = ctypes.c_float()
-    _check(_lib.ooc_mlp_grad(device, d, H, pp, px, pt, x.shape[0], g.ctypes.data_as(P_flt), ctypes.byref(loss)))
+    _check(_lib.ooc_mlp_grad(device, d, H, pp, px, pt, x.shape[0], weight_decay, g.ctypes.data_as(P_flt),
+                             ctypes.byref(loss)))
     return g, loss.value
 
 
@@ -423,22 +424,24 @@ def ooc_mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=
     return p, mm, vv
 
 
-def ooc_mlp_train(d, H, params, X, t, epochs, lr=1e-3, device=0):
+def ooc_mlp_train(d, H, params, X, t, epochs, lr=1e-3, weight_decay=0.0, device=0):
     """Full-batch Adam on the GPU; returns (params, loss history)."""
     p = np.array(params, dtype=np.float32)
     x, px = _f32(X)
     tt, pt = _f32(t)
     hist = np.zeros(max(epochs, 1), dtype=np.float32)
-    _check(_lib.ooc_mlp_train(device, d, H, p.ctypes.data_as(P_flt), px, pt, x.shape[0], epochs, lr,
+    _check(_lib.ooc_mlp_train(device, d, H, p.ctypes.data_as(P_flt), px, pt, x.shape[0], epochs, lr, weight_decay,
                               hist.ctypes.data_as(P_flt)))
     return p, hist[:epochs]
 
 
-def ooc_mlp_fit(X, seconds, hidden=64, epochs=3000, lr=3e-3, seed=0, device=0):
+def ooc_mlp_fit(X, seconds, hidden=64, epochs=1000, lr=3e-3, weight_decay=1e-3, seed=0, device=0):
+    """Fit the planner network to measured seconds of candidate plans (features X)."""
     x, px = _f32(X)
     y, py = _f32(seconds)
     hist = np.zeros(max(epochs, 1), dtype=np.float32)
-    _check(_lib.ooc_mlp_fit(device, px, py, x.shape[0], hidden, epochs, lr, seed, hist.ctypes.data_as(P_flt)))
+    _check(_lib.ooc_mlp_fit(device, px, py, x.shape[0], hidden, epochs, lr, weight_decay, seed,
+                            hist.ctypes.data_as(P_flt)))
     return hist[:epochs]
 
 

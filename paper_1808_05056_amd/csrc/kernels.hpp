@@ -30,7 +30,7 @@ int64_t mlp_param_count(int d, int H);
 int64_t mlp_scratch_floats(int64_t n, int d, int H);
 hipError_t launch_mlp_forward(int64_t n, int d, int H, const float* params, const float* X, float* scratch,
                               float* y_out, hipStream_t s);
-hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const float* X, const float* t,
+hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const float* X, const float* t, float wd,
                            float* scratch, float* grad, float* loss, hipStream_t s);
 hipError_t launch_adam(int64_t count, float* p, const float* g, float* m, float* v, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);

@@ -8,7 +8,8 @@
 // prediction.
 //
 // Network (FP32): x (d) -> tanh(x W1 + b1) (H) -> tanh(. W2 + b2) (H) -> . W3 + b3.
-// Loss: mean squared error over the batch.  Optimiser: Adam with bias
+// Loss: mean squared error over the batch, plus optionally (wd/2) times the
+// sum of squares of the weight matrices (biases are not penalised).  Optimiser: Adam with bias
 // correction (Kingma and Ba, 2015).  Parameters are one flat array:
 // W1 (d x H, row-major), b1 (H), W2 (H x H), b2 (H), W3 (H x 1), b3 (1).
 // Every reduction runs in a fixed order in one thread, so results are
@@ -53,6 +54,17 @@ __global__ void mse_loss(int64_t n, const float* __restrict__ y, const float* __
   *loss = (float)(acc / (double)n);
 }
 
+// loss += (wd/2) * sum of squares of the weight matrices (one thread, fixed order)
+__global__ void l2_penalty(const float* __restrict__ W1, int64_t n1, const float* __restrict__ W2, int64_t n2,
+                           const float* __restrict__ W3, int64_t n3, float wd, float* __restrict__ loss) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int64_t i = 0; i < n1; ++i) acc += (double)W1[i] * W1[i];
+  for (int64_t i = 0; i < n2; ++i) acc += (double)W2[i] * W2[i];
+  for (int64_t i = 0; i < n3; ++i) acc += (double)W3[i] * W3[i];
+  *loss = (float)((double)*loss + 0.5 * (double)wd * acc);
+}
+
 // dZ = dH * (1 - H^2) in place (tanh derivative from the stored activations)
 __global__ __launch_bounds__(256) void tanh_bwd(int64_t count, const float* __restrict__ H, float* __restrict__ dH) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -60,17 +72,17 @@ __global__ __launch_bounds__(256) void tanh_bwd(int64_t count, const float* __re
   dH[i] = dH[i] * (1.0f - H[i] * H[i]);
 }
 
-// dW[i][j] = sum_r X[r][i] dZ[r][j]; db[j] = sum_r dZ[r][j]
+// dW[i][j] = sum_r X[r][i] dZ[r][j] + wd W[i][j]; db[j] = sum_r dZ[r][j]
 __global__ __launch_bounds__(256) void dense_wgrad(int64_t n, int din, int dout, const float* __restrict__ X,
-                                                   const float* __restrict__ dZ, float* __restrict__ dW,
-                                                   float* __restrict__ db) {
+                                                   const float* __restrict__ dZ, const float* __restrict__ W,
+                                                   float wd, float* __restrict__ dW, float* __restrict__ db) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t nw = (int64_t)din * dout;
   if (idx < nw) {
     const int i = (int)(idx / dout), j = (int)(idx % dout);
     float acc = 0.f;
     for (int64_t r = 0; r < n; ++r) acc += X[r * din + i] * dZ[r * dout + j];
-    dW[idx] = acc;
+    dW[idx] = acc + wd * W[idx];
   } else if (idx < nw + dout) {
     const int j = (int)(idx - nw);
     float acc = 0.f;
@@ -143,14 +155,13 @@ hipError_t launch_mlp_forward(int64_t n, int d, int H, const float* params, cons
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const float* X, const float* t,
+hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const float* X, const float* t, float wd,
                            float* scratch, float* grad, float* loss, hipStream_t s) {
   const float* W1 = params;
   const float* b1 = W1 + (int64_t)d * H;
   const float* W2 = b1 + H;
   const float* b2 = W2 + (int64_t)H * H;
   const float* W3 = b2 + H;
-  (void)b1; (void)b2;
   float* gW1 = grad;
   float* gb1 = gW1 + (int64_t)d * H;
   float* gW2 = gb1 + H;
@@ -166,17 +177,22 @@ hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const f
   hipError_t e = launch_mlp_forward(n, d, H, params, X, scratch, y, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(mse_loss, dim3(1), dim3(64), 0, s, n, y, t, loss);
+  if (wd != 0.f)
+    hipLaunchKernelGGL(l2_penalty, dim3(1), dim3(64), 0, s, W1, (int64_t)d * H, W2, (int64_t)H * H, W3, (int64_t)H, wd,
+                       loss);
   hipLaunchKernelGGL(mse_grad, dim3(blocks(n)), dim3(256), 0, s, n, y, t, dy);
   // layer 3 (linear): dW3 = H2^T dy, db3 = sum dy, dH2 = dy W3^T
-  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H + 1)), dim3(256), 0, s, n, H, 1, H2, dy, gW3, gb3);
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H + 1)), dim3(256), 0, s, n, H, 1, H2, dy, W3, wd, gW3, gb3);
   hipLaunchKernelGGL(dense_xgrad, dim3(blocks(n * H)), dim3(256), 0, s, n, H, 1, dy, W3, dH2);
   hipLaunchKernelGGL(tanh_bwd, dim3(blocks(n * H)), dim3(256), 0, s, n * H, H2, dH2);
   // layer 2
-  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H * H + H)), dim3(256), 0, s, n, H, H, H1, dH2, gW2, gb2);
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H * H + H)), dim3(256), 0, s, n, H, H, H1, dH2, W2, wd, gW2,
+                     gb2);
   hipLaunchKernelGGL(dense_xgrad, dim3(blocks(n * H)), dim3(256), 0, s, n, H, H, dH2, W2, dH1);
   hipLaunchKernelGGL(tanh_bwd, dim3(blocks(n * H)), dim3(256), 0, s, n * H, H1, dH1);
   // layer 1
-  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)d * H + H)), dim3(256), 0, s, n, d, H, X, dH1, gW1, gb1);
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)d * H + H)), dim3(256), 0, s, n, d, H, X, dH1, W1, wd, gW1,
+                     gb1);
   return hipGetLastError();
 }
 

@@ -64,7 +64,7 @@ ooc_status select_device(int device) {
 
 // Full-batch Adam on the GPU; params are updated in place (host array).
 ooc_status train_impl(int device, int d, int H, float* params, const float* X, const float* t, int64_t n, int epochs,
-                      float lr, float* loss_hist) {
+                      float lr, float wd, float* loss_hist) {
   ooc_status st = select_device(device);
   if (st != OOC_OK) return st;
   const int64_t np = mlp_param_count(d, H);
@@ -84,7 +84,7 @@ ooc_status train_impl(int device, int d, int H, float* params, const float* X, c
   MLPCHK(hipMemcpy(dM.p, zeros.data(), np * 4, hipMemcpyHostToDevice));
   MLPCHK(hipMemcpy(dV.p, zeros.data(), np * 4, hipMemcpyHostToDevice));
   for (int ep = 0; ep < epochs; ++ep) {
-    MLPCHK(launch_mlp_grad(n, d, H, dP.f(), dX.f(), dT.f(), dS.f(), dG.f(), dL.f() + ep, nullptr));
+    MLPCHK(launch_mlp_grad(n, d, H, dP.f(), dX.f(), dT.f(), wd, dS.f(), dG.f(), dL.f() + ep, nullptr));
     MLPCHK(launch_adam(np, dP.f(), dG.f(), dM.f(), dV.f(), lr, 0.9f, 0.999f, 1e-8f, ep + 1, nullptr));
   }
   MLPCHK(hipDeviceSynchronize());
@@ -216,8 +216,9 @@ ooc_status ooc_mlp_forward(int32_t device, int32_t d, int32_t hidden, const floa
 }
 
 ooc_status ooc_mlp_grad(int32_t device, int32_t d, int32_t hidden, const float* params, const float* X,
-                        const float* t, int64_t n, float* grad_out, float* loss_out) {
-  if (!params || !X || !t || !grad_out || d <= 0 || hidden <= 0 || n <= 0) return fail(OOC_ERR_ARG, "bad argument");
+                        const float* t, int64_t n, float weight_decay, float* grad_out, float* loss_out) {
+  if (!params || !X || !t || !grad_out || d <= 0 || hidden <= 0 || n <= 0 || !(weight_decay >= 0.f))
+    return fail(OOC_ERR_ARG, "bad argument");
   ooc_status st = select_device(device);
   if (st != OOC_OK) return st;
   const int64_t np = mlp_param_count(d, hidden);
@@ -231,7 +232,7 @@ ooc_status ooc_mlp_grad(int32_t device, int32_t d, int32_t hidden, const float* 
   MLPCHK(hipMemcpy(dP.p, params, np * 4, hipMemcpyHostToDevice));
   MLPCHK(hipMemcpy(dX.p, X, (size_t)n * d * 4, hipMemcpyHostToDevice));
   MLPCHK(hipMemcpy(dT.p, t, (size_t)n * 4, hipMemcpyHostToDevice));
-  MLPCHK(launch_mlp_grad(n, d, hidden, dP.f(), dX.f(), dT.f(), dS.f(), dG.f(), dL.f(), nullptr));
+  MLPCHK(launch_mlp_grad(n, d, hidden, dP.f(), dX.f(), dT.f(), weight_decay, dS.f(), dG.f(), dL.f(), nullptr));
   MLPCHK(hipDeviceSynchronize());
   MLPCHK(hipMemcpy(grad_out, dG.p, np * 4, hipMemcpyDeviceToHost));
   if (loss_out) MLPCHK(hipMemcpy(loss_out, dL.p, 4, hipMemcpyDeviceToHost));
@@ -261,15 +262,17 @@ ooc_status ooc_mlp_adam(int32_t device, int64_t count, float* params, const floa
 }
 
 ooc_status ooc_mlp_train(int32_t device, int32_t d, int32_t hidden, float* params, const float* X, const float* t,
-                         int64_t n, int32_t epochs, float lr, float* loss_hist) {
-  if (!params || !X || !t || d <= 0 || hidden <= 0 || n <= 0 || epochs < 0) return fail(OOC_ERR_ARG, "bad argument");
-  return train_impl(device, d, hidden, params, X, t, n, epochs, lr, loss_hist);
+                         int64_t n, int32_t epochs, float lr, float weight_decay, float* loss_hist) {
+  if (!params || !X || !t || d <= 0 || hidden <= 0 || n <= 0 || epochs < 0 || !(weight_decay >= 0.f))
+    return fail(OOC_ERR_ARG, "bad argument");
+  return train_impl(device, d, hidden, params, X, t, n, epochs, lr, weight_decay, loss_hist);
 }
 
 ooc_status ooc_mlp_fit(int32_t device, const float* X, const float* y_seconds, int64_t n, int32_t hidden,
-                       int32_t epochs, float lr, uint64_t seed, float* loss_hist) {
+                       int32_t epochs, float lr, float weight_decay, uint64_t seed, float* loss_hist) {
   const int d = OOC_MLP_FEATURES;
-  if (!X || !y_seconds || n <= 1 || hidden <= 0 || epochs < 0) return fail(OOC_ERR_ARG, "bad argument");
+  if (!X || !y_seconds || n <= 1 || hidden <= 0 || epochs < 0 || !(weight_decay >= 0.f))
+    return fail(OOC_ERR_ARG, "bad argument");
   Net net;
   net.d = d;
   net.H = hidden;
@@ -311,7 +314,8 @@ ooc_status ooc_mlp_fit(int32_t device, const float* X, const float* y_seconds, i
   for (int64_t i = 0; i < (int64_t)d * hidden; ++i) W1[i] = (float)(nd(rng) / std::sqrt((double)d));
   for (int64_t i = 0; i < (int64_t)hidden * hidden; ++i) W2[i] = (float)(nd(rng) / std::sqrt((double)hidden));
   for (int64_t i = 0; i < hidden; ++i) W3[i] = (float)(nd(rng) / std::sqrt((double)hidden));
-  ooc_status st = train_impl(device, d, hidden, net.params.data(), Xs.data(), t.data(), n, epochs, lr, loss_hist);
+  ooc_status st =
+      train_impl(device, d, hidden, net.params.data(), Xs.data(), t.data(), n, epochs, lr, weight_decay, loss_hist);
   if (st != OOC_OK) return st;
   net.loaded = true;
   {

@@ -8,7 +8,8 @@ device, Section VI).  This tool
   train   times a set of candidates per problem of a training batch (M, N, K
           log-uniform in [4096, 24576], budgets log-uniform 256 MiB - 8 GiB,
           seed 40), fits the network with the library's GPU kernels
-          (ooc_mlp_fit) and writes the weights;
+          (ooc_mlp_fit: full-batch Adam, L2 weight decay) and writes the weights;
+  fit     refits the network from the timings a train run saved;
   eval    times every candidate of the evaluation batch (seed 4) that the cost
           model, the network or the paper's rule would consider, and reports
           the regret t(choice) / t(best measured) - 1 of each planner.
@@ -115,9 +116,19 @@ def train(args):
     np.savez(args.data, X=X, y=y)
     with open(args.data + ".json", "w") as f:
         json.dump(meta, f)
-    hist = ooc.ooc_mlp_fit(X, y, hidden=args.hidden, epochs=args.epochs, lr=args.lr, seed=args.seed)
+    fit_and_save(X, y, args)
+
+
+def fit_and_save(X, y, args):
+    hist = ooc.ooc_mlp_fit(X, y, hidden=args.hidden, epochs=args.epochs, lr=args.lr, weight_decay=args.weight_decay,
+                           seed=args.seed)
     ooc.ooc_mlp_save(args.out)
-    _log(f"[train] {len(y)} samples; loss {hist[0]:.4f} -> {hist[-1]:.4f}; weights in {args.out}")
+    _log(f"[fit] {len(y)} samples; objective {hist[0]:.4f} -> {hist[-1]:.4f}; weights in {args.out}")
+
+
+def fit(args):
+    d = np.load(args.data)
+    fit_and_save(d["X"], d["y"], args)
 
 
 def evaluate(args):
@@ -177,12 +188,15 @@ def main(argv=None):
     t.add_argument("--n-model", type=int, default=8)
     t.add_argument("--n-random", type=int, default=6)
     t.add_argument("--reps", type=int, default=1)
-    t.add_argument("--hidden", type=int, default=64)
-    t.add_argument("--epochs", type=int, default=4000)
-    t.add_argument("--lr", type=float, default=3e-3)
-    t.add_argument("--seed", type=int, default=0)
-    t.add_argument("--data", default="planner_sweep_train.npz")
-    t.add_argument("--out", default="planner_mlp.txt")
+    f = sub.add_parser("fit")
+    for q in (t, f):
+        q.add_argument("--hidden", type=int, default=64)
+        q.add_argument("--epochs", type=int, default=1000)
+        q.add_argument("--lr", type=float, default=3e-3)
+        q.add_argument("--weight-decay", type=float, default=1e-3)
+        q.add_argument("--seed", type=int, default=0)
+        q.add_argument("--data", default="planner_sweep_train.npz")
+        q.add_argument("--out", default="planner_mlp.txt")
     e = sub.add_parser("eval")
     e.add_argument("--count", type=int, default=64)
     e.add_argument("--n-model", type=int, default=6)
@@ -191,10 +205,7 @@ def main(argv=None):
     e.add_argument("--weights", default=None)
     e.add_argument("--report", default="planner_eval.json")
     args = ap.parse_args(argv)
-    if args.cmd == "train":
-        train(args)
-    else:
-        evaluate(args)
+    {"train": train, "fit": fit, "eval": evaluate}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -39,20 +39,22 @@ def _params(d, H, seed):
     return {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
 
 
-@pytest.mark.parametrize("d,H,n", [(19, 64, 300), (5, 16, 7), (19, 128, 1000)])
-def test_forward_and_gradients(d, H, n):
+@pytest.mark.parametrize("d,H,n,wd", [(19, 64, 300, 0.0), (5, 16, 7, 0.0), (19, 128, 1000, 0.0), (19, 64, 300, 0.05),
+                                      (5, 16, 7, 0.3)])
+def test_forward_and_gradients(d, H, n, wd):
     P = _params(d, H, 3)
     X, t = _data(n, d, 4)
     y_ref, cache = mlp_ref.forward(P, X.astype(np.float64))
     y = ooc.ooc_mlp_forward(d, H, _flat(P), X)
     assert np.max(np.abs(y - y_ref)) <= 1e-5 * (1 + np.max(np.abs(y_ref)))
     L_ref, dy = mlp_ref.mse(y_ref, t.astype(np.float64))
-    g_ref = _flat(mlp_ref.backward(P, cache, dy))
-    g, L = ooc.ooc_mlp_grad(d, H, _flat(P), X, t)
+    L_ref += mlp_ref.penalty(P, wd)
+    g_ref = _flat(mlp_ref.backward(P, cache, dy, wd))
+    g, L = ooc.ooc_mlp_grad(d, H, _flat(P), X, t, weight_decay=wd)
     assert abs(L - L_ref) <= 1e-5 * (1 + L_ref)
     # per element, normalised by the largest gradient of its parameter block
     off = 0
-    Gr = mlp_ref.backward(P, cache, dy)
+    Gr = mlp_ref.backward(P, cache, dy, wd)
     for k in mlp_ref.PARAM_NAMES:
         size = Gr[k].size
         scale = np.max(np.abs(Gr[k])) + 1e-12
@@ -83,19 +85,20 @@ def test_adam_step_matches_reference():
     assert np.max(np.abs(p2 - pr)) <= 1e-5
 
 
-def test_training_follows_reference():
+@pytest.mark.parametrize("wd", [0.0, 0.01])
+def test_training_follows_reference(wd):
     d, H, n = 6, 32, 256
     P = _params(d, H, 7)
     X, t = _data(n, d, 8)
-    p, hist = ooc.ooc_mlp_train(d, H, _flat(P), X, t, epochs=200, lr=3e-3)
+    p, hist = ooc.ooc_mlp_train(d, H, _flat(P), X, t, epochs=200, lr=3e-3, weight_decay=wd)
     Pref = {k: v.copy() for k, v in P.items()}
     ref_hist = []
     st = mlp_ref.adam_init(Pref)
     for _ in range(200):
         y, c = mlp_ref.forward(Pref, X.astype(np.float64))
         L, dy = mlp_ref.mse(y, t.astype(np.float64))
-        ref_hist.append(L)
-        mlp_ref.adam_step(Pref, mlp_ref.backward(Pref, c, dy), st, lr=3e-3)
+        ref_hist.append(L + mlp_ref.penalty(Pref, wd))
+        mlp_ref.adam_step(Pref, mlp_ref.backward(Pref, c, dy, wd), st, lr=3e-3)
     ref_hist = np.array(ref_hist)
     assert hist[-1] < 0.3 * hist[0]
     assert np.max(np.abs(hist[:50] - ref_hist[:50]) / ref_hist[:50]) < 1e-3

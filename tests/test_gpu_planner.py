@@ -20,7 +20,7 @@ def test_fit_learns_a_timing_function():
     X = ooc.ooc_mlp_features(20000, 16000, 12000, 0.0, 2 << 30, plans)
     # a synthetic "measured" time: the model's time with a penalty for one stream
     t = np.array(model_s) * np.where(X[:, 15] == 1, 1.8, 1.0)
-    hist = ooc.ooc_mlp_fit(X, t, hidden=32, epochs=1500, lr=3e-3, seed=3)
+    hist = ooc.ooc_mlp_fit(X, t, hidden=32, epochs=1500, lr=3e-3, weight_decay=0.0, seed=3)
     assert hist[-1] < 0.05 * hist[0]
     pred = ooc.ooc_mlp_predict(20000, 16000, 12000, 0.0, 2 << 30, plans)
     assert np.corrcoef(np.log(pred), np.log(t))[0, 1] > 0.95
