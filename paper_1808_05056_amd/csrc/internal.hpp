@@ -52,9 +52,10 @@ bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan, int 
 // Hardware figures the cost model uses.
 // Measured on an MI355X (PCIe Gen5 x16 host link, pinned host memory).
 struct Machine {
-  double h2d_gbs = 57.6;      // pinned host -> device, one direction active (GB/s)
-  double d2h_gbs = 57.1;      // device -> pinned host
-  double duplex_gbs = 48.7;   // each direction when both are active
+  double h2d_gbs = 56.6;          // pinned host -> device, one direction active (GB/s, 2-D copies)
+  double d2h_gbs = 57.1;          // device -> pinned host
+  double duplex_h2d_gbs = 56.5;   // host -> device while device -> host is active
+  double duplex_d2h_gbs = 47.3;   // device -> host while host -> device is active
   double copy_latency_s = 12e-6;
   double kernel_tflops = 72.85;    // FP64 tile kernel, two workgroups per CU, large k
   double kernel_tflops_1wg = 38.0; // same with one workgroup per CU

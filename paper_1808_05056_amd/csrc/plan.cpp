@@ -240,8 +240,8 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
     if (running.empty()) return std::numeric_limits<double>::infinity();  // deadlock
     int nh = 0, nd = 0, nk = 0;
     for (int x : running) { if (lat[x] > 0) continue; if (cls[x] == 0) ++nh; else if (cls[x] == 1) ++nd; else ++nk; }
-    const double bw_h = (nd ? mc.duplex_gbs : mc.h2d_gbs) * 1e9;
-    const double bw_d = (nh ? mc.duplex_gbs : mc.d2h_gbs) * 1e9;
+    const double bw_h = (nd ? mc.duplex_h2d_gbs : mc.h2d_gbs) * 1e9;
+    const double bw_d = (nh ? mc.duplex_d2h_gbs : mc.d2h_gbs) * 1e9;
     double dt = std::numeric_limits<double>::infinity();
     std::vector<double> rate(running.size());
     for (size_t r = 0; r < running.size(); ++r) {
