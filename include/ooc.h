@@ -63,8 +63,10 @@ typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1 } ooc_precision;
  * a column, their A slices and the column's B slice fit), two streams used
  * round robin, A and C double-buffered, B single-buffered.  MODEL: the
  * candidate with the smallest simulated pipeline time under the analytic
- * cost model.  MLP: the candidate with the smallest time predicted by the
- * loaded MLP (falls back to MODEL when none is loaded).  AUTO = MODEL. */
+ * cost model.  MLP: among the cost model's 8 best candidates, the one with the
+ * smallest time predicted by the loaded network (the network shipped beside
+ * the library is loaded on first use; falls back to MODEL when none is
+ * loaded).  AUTO = MODEL. */
 typedef enum { OOC_PLAN_AUTO = 0, OOC_PLAN_PAPER = 1, OOC_PLAN_MODEL = 2, OOC_PLAN_MLP = 3 } ooc_planner;
 
 /* Task orders over the grid of C blocks (i: block row, j: block column) and

@@ -539,8 +539,13 @@ static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes,
   if (st != OOC_OK) return st;
   size_t best = 0;
   if (planner == OOC_PLAN_MLP) {
+    // the network ranks the cost model's shortlist: the plans it was trained
+    // on are the model's best candidates plus a few random others, so outside
+    // the shortlist its predictions are extrapolations
+    const size_t shortlist = std::min<size_t>(plans.size(), 8);
+    std::vector<ooc_plan_t> top(plans.begin(), plans.begin() + shortlist);
     std::vector<double> pred;
-    if (mlp_predict(pb, budget_bytes, plans, &pred)) {
+    if (mlp_predict(pb, budget_bytes, top, &pred)) {
       for (size_t c = 1; c < pred.size(); ++c)
         if (pred[c] < pred[best]) best = c;
     }
