@@ -9,7 +9,7 @@ import pytest
 
 from synth import workloads as W
 import paper_1808_05056_amd as ooc
-from gpu_helpers import PinnedProblem
+from gpu_helpers import PinnedProblem, check_rows, sample_rows
 
 pytestmark = pytest.mark.gpu
 WEIGHTS = os.path.join(os.path.dirname(ooc.LIB_PATH), "planner_mlp.txt")
@@ -33,7 +33,7 @@ def test_fit_learns_a_timing_function():
 def test_learned_planner_beats_the_papers_rule():
     ooc.ooc_mlp_load(WEIGHTS)
     problems = [w for w in W.problem_batch(4, count=64) if w.flops < 4e12][:4]
-    assert problems
+    assert problems and all(w.beta == 0.0 for w in problems)
     gains = []
     for w in problems:
         pp = PinnedProblem(w)
@@ -41,7 +41,10 @@ def test_learned_planner_beats_the_papers_rule():
             times = {}
             for name, planner in (("mlp", ooc.PLAN_MLP), ("paper", ooc.PLAN_PAPER)):
                 opts = ooc.make_opts(planner=planner)
-                ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, opts)
+                _, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, opts)
+                assert stats.arena_bytes <= w.budget
+                # beta = 0 in this batch, so every call leaves C = alpha*A*B: check it
+                check_rows(w, pp, sample_rows(w.M, stats.plan.mb, count=8))
                 best = min(ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, opts)[1].t_pipeline_s
                            for _ in range(2))
                 times[name] = best
