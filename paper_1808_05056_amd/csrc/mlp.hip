@@ -12,8 +12,8 @@
 // sum of squares of the weight matrices (biases are not penalised).  Optimiser: Adam with bias
 // correction (Kingma and Ba, 2015).  Parameters are one flat array:
 // W1 (d x H, row-major), b1 (H), W2 (H x H), b2 (H), W3 (H x 1), b3 (1).
-// Every reduction runs in a fixed order in one thread, so results are
-// deterministic.
+// Every reduction runs in a fixed order (per-thread strided partial sums, then
+// a fixed LDS tree or wave butterfly), so results are deterministic.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -44,25 +44,42 @@ __global__ __launch_bounds__(256) void mse_grad(int64_t n, const float* __restri
   dy[r] = 2.0f * (y[r] - t[r]) / (float)n;
 }
 
-__global__ void mse_loss(int64_t n, const float* __restrict__ y, const float* __restrict__ t, float* __restrict__ loss) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// Sum of one value per thread over a 256-thread block in a fixed order (an LDS
+// tree), so the result does not depend on scheduling.
+__device__ double block_sum256(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+// loss = (1/n) sum (y - t)^2 (one block of 256 threads)
+__global__ __launch_bounds__(256) void mse_loss(int64_t n, const float* __restrict__ y, const float* __restrict__ t,
+                                                float* __restrict__ loss) {
   double acc = 0.0;
-  for (int64_t r = 0; r < n; ++r) {
+  for (int64_t r = threadIdx.x; r < n; r += 256) {
     const double d = (double)y[r] - (double)t[r];
     acc += d * d;
   }
-  *loss = (float)(acc / (double)n);
+  acc = block_sum256(acc);
+  if (threadIdx.x == 0) *loss = (float)(acc / (double)n);
 }
 
-// loss += (wd/2) * sum of squares of the weight matrices (one thread, fixed order)
-__global__ void l2_penalty(const float* __restrict__ W1, int64_t n1, const float* __restrict__ W2, int64_t n2,
-                           const float* __restrict__ W3, int64_t n3, float wd, float* __restrict__ loss) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+// loss += (wd/2) * sum of squares of the weight matrices (one block of 256 threads)
+__global__ __launch_bounds__(256) void l2_penalty(const float* __restrict__ W1, int64_t n1,
+                                                  const float* __restrict__ W2, int64_t n2,
+                                                  const float* __restrict__ W3, int64_t n3, float wd,
+                                                  float* __restrict__ loss) {
   double acc = 0.0;
-  for (int64_t i = 0; i < n1; ++i) acc += (double)W1[i] * W1[i];
-  for (int64_t i = 0; i < n2; ++i) acc += (double)W2[i] * W2[i];
-  for (int64_t i = 0; i < n3; ++i) acc += (double)W3[i] * W3[i];
-  *loss = (float)((double)*loss + 0.5 * (double)wd * acc);
+  for (int64_t i = threadIdx.x; i < n1; i += 256) acc += (double)W1[i] * W1[i];
+  for (int64_t i = threadIdx.x; i < n2; i += 256) acc += (double)W2[i] * W2[i];
+  for (int64_t i = threadIdx.x; i < n3; i += 256) acc += (double)W3[i] * W3[i];
+  acc = block_sum256(acc);
+  if (threadIdx.x == 0) *loss = (float)((double)*loss + 0.5 * (double)wd * acc);
 }
 
 // dZ = dH * (1 - H^2) in place (tanh derivative from the stored activations)
@@ -72,22 +89,30 @@ __global__ __launch_bounds__(256) void tanh_bwd(int64_t count, const float* __re
   dH[i] = dH[i] * (1.0f - H[i] * H[i]);
 }
 
-// dW[i][j] = sum_r X[r][i] dZ[r][j] + wd W[i][j]; db[j] = sum_r dZ[r][j]
+// dW[i][j] = sum_r X[r][i] dZ[r][j] + wd W[i][j]; db[j] = sum_r dZ[r][j].
+// One wave per output (din*dout weights, then dout biases): lane l sums rows
+// l, l+64, ..., then a fixed butterfly over the wave.
 __global__ __launch_bounds__(256) void dense_wgrad(int64_t n, int din, int dout, const float* __restrict__ X,
                                                    const float* __restrict__ dZ, const float* __restrict__ W,
                                                    float wd, float* __restrict__ dW, float* __restrict__ db) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t o = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int64_t nw = (int64_t)din * dout;
-  if (idx < nw) {
-    const int i = (int)(idx / dout), j = (int)(idx % dout);
-    float acc = 0.f;
-    for (int64_t r = 0; r < n; ++r) acc += X[r * din + i] * dZ[r * dout + j];
-    dW[idx] = acc + wd * W[idx];
-  } else if (idx < nw + dout) {
-    const int j = (int)(idx - nw);
-    float acc = 0.f;
-    for (int64_t r = 0; r < n; ++r) acc += dZ[r * dout + j];
-    db[j] = acc;
+  if (o >= nw + dout) return;  // the whole wave leaves together
+  float acc = 0.f;
+  if (o < nw) {
+    const int i = (int)(o / dout), j = (int)(o % dout);
+    for (int64_t r = lane; r < n; r += 64) acc += X[r * din + i] * dZ[r * dout + j];
+  } else {
+    const int j = (int)(o - nw);
+    for (int64_t r = lane; r < n; r += 64) acc += dZ[r * dout + j];
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    if (o < nw)
+      dW[o] = acc + wd * W[o];
+    else
+      db[o - nw] = acc;
   }
 }
 
@@ -176,22 +201,22 @@ hipError_t launch_mlp_grad(int64_t n, int d, int H, const float* params, const f
   float* dy = y + n;
   hipError_t e = launch_mlp_forward(n, d, H, params, X, scratch, y, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mse_loss, dim3(1), dim3(64), 0, s, n, y, t, loss);
+  hipLaunchKernelGGL(mse_loss, dim3(1), dim3(256), 0, s, n, y, t, loss);
   if (wd != 0.f)
-    hipLaunchKernelGGL(l2_penalty, dim3(1), dim3(64), 0, s, W1, (int64_t)d * H, W2, (int64_t)H * H, W3, (int64_t)H, wd,
+    hipLaunchKernelGGL(l2_penalty, dim3(1), dim3(256), 0, s, W1, (int64_t)d * H, W2, (int64_t)H * H, W3, (int64_t)H, wd,
                        loss);
   hipLaunchKernelGGL(mse_grad, dim3(blocks(n)), dim3(256), 0, s, n, y, t, dy);
   // layer 3 (linear): dW3 = H2^T dy, db3 = sum dy, dH2 = dy W3^T
-  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H + 1)), dim3(256), 0, s, n, H, 1, H2, dy, W3, wd, gW3, gb3);
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks(((int64_t)H + 1) * 64)), dim3(256), 0, s, n, H, 1, H2, dy, W3, wd, gW3, gb3);
   hipLaunchKernelGGL(dense_xgrad, dim3(blocks(n * H)), dim3(256), 0, s, n, H, 1, dy, W3, dH2);
   hipLaunchKernelGGL(tanh_bwd, dim3(blocks(n * H)), dim3(256), 0, s, n * H, H2, dH2);
   // layer 2
-  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)H * H + H)), dim3(256), 0, s, n, H, H, H1, dH2, W2, wd, gW2,
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks(((int64_t)H * H + H) * 64)), dim3(256), 0, s, n, H, H, H1, dH2, W2, wd, gW2,
                      gb2);
   hipLaunchKernelGGL(dense_xgrad, dim3(blocks(n * H)), dim3(256), 0, s, n, H, H, dH2, W2, dH1);
   hipLaunchKernelGGL(tanh_bwd, dim3(blocks(n * H)), dim3(256), 0, s, n * H, H1, dH1);
   // layer 1
-  hipLaunchKernelGGL(dense_wgrad, dim3(blocks((int64_t)d * H + H)), dim3(256), 0, s, n, d, H, X, dH1, W1, wd, gW1,
+  hipLaunchKernelGGL(dense_wgrad, dim3(blocks(((int64_t)d * H + H) * 64)), dim3(256), 0, s, n, d, H, X, dH1, W1, wd, gW1,
                      gb1);
   return hipGetLastError();
 }
