@@ -36,8 +36,9 @@ namespace {
 constexpr int kMaxDevices = 64;
 
 struct DevCtx {
-  std::mutex mu;
-  bool init = false;
+  std::mutex mu;       // guards everything below; held for the whole of a call on the device
+  bool arch_ok = false;  // the device was checked to be a gfx950
+  bool init = false;     // streams created
   hipStream_t st[3] = {nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> ev;   // dependency events (no timing)
   std::vector<hipEvent_t> tev;  // timing events (profile mode)
@@ -61,7 +62,7 @@ ooc_status hip_fail(hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
-// Select the device and create its streams once.
+// Select the device (checked once to be a gfx950).
 ooc_status ensure_device(int dev) {
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
@@ -72,11 +73,21 @@ ooc_status ensure_device(int dev) {
   if (dev < 0 || dev >= count || dev >= kMaxDevices) return fail(OOC_ERR_NO_DEVICE, "device ordinal out of range");
   HIPCHK(hipSetDevice(dev), "hipSetDevice");
   DevCtx& c = g_dev[dev];
-  if (!c.init) {
+  std::lock_guard<std::mutex> lock(c.mu);
+  if (!c.arch_ok) {
     hipDeviceProp_t prop;
     HIPCHK(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       return fail(OOC_ERR_NO_DEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    c.arch_ok = true;
+  }
+  return OOC_OK;
+}
+
+// Create the device's three streams (default priority) if they do not exist;
+// the caller holds c.mu, so ooc_release cannot destroy them during the call.
+ooc_status ensure_streams(DevCtx& c) {
+  if (!c.init) {
     for (int s = 0; s < 3; ++s) HIPCHK(hipStreamCreateWithFlags(&c.st[s], hipStreamNonBlocking), "hipStreamCreate");
     c.init = true;
   }
@@ -292,6 +303,8 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
 
   DevCtx& c = g_dev[dev];
   std::lock_guard<std::mutex> lock(c.mu);
+  st = ensure_streams(c);
+  if (st != OOC_OK) return st;
   double* arena = nullptr;
   if (opts && opts->arena) {
     if (opts->arena_bytes < lay.bytes) return fail(OOC_ERR_ARG, "opts->arena is smaller than the plan's footprint");
@@ -563,25 +576,30 @@ ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, dou
   if (st != OOC_OK) return st;
   DevCtx& c = g_dev[device];
   std::lock_guard<std::mutex> lock(c.mu);
+  st = ensure_streams(c);
+  if (st != OOC_OK) return st;
   hipStream_t s = c.st[1];
   const int r = reps > 0 ? reps : 1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
   if (ms_out) {
-    HIPCHK(hipEventCreate(&e0), "hipEventCreate");
-    HIPCHK(hipEventCreate(&e1), "hipEventCreate");
-    HIPCHK(hipEventRecord(e0, s), "hipEventRecord");
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
   }
-  for (int x = 0; x < r; ++x)
-    HIPCHK(launch_dgemm_f64(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 0.0, nullptr, 0, s), "dgemm launch");
-  if (ms_out) HIPCHK(hipEventRecord(e1, s), "hipEventRecord");
-  HIPCHK(hipStreamSynchronize(s), "hipStreamSynchronize");
-  if (ms_out) {
+  for (int x = 0; x < r && e == hipSuccess; ++x)
+    e = launch_dgemm_f64(m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, 0.0, nullptr, 0, s);
+  if (e == hipSuccess && ms_out) e = hipEventRecord(e1, s);
+  const hipError_t es = hipStreamSynchronize(s);  // also after a failed launch: nothing outlives the call
+  if (e == hipSuccess) e = es;
+  if (e == hipSuccess && ms_out) {
     float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    e = hipEventElapsedTime(&ms, e0, e1);
     *ms_out = ms / r;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
   }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "dgemm");
   return OOC_OK;
 }
 
@@ -597,6 +615,8 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
   if (st != OOC_OK) return st;
   DevCtx& c = g_dev[device];
   std::lock_guard<std::mutex> lock(c.mu);
+  st = ensure_streams(c);
+  if (st != OOC_OK) return st;
   hipStream_t strm = c.st[1];
   const size_t wsb = split_workspace_bytes(m, n, k, s);
   void* ws = nullptr;
@@ -612,7 +632,8 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
   for (int x = 0; x < r && e == hipSuccess; ++x)
     e = launch_split_gemm(m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, 0.0, nullptr, 0, ws, wsb, strm);
   if (e == hipSuccess && ms_out) e = hipEventRecord(e1, strm);
-  if (e == hipSuccess) e = hipStreamSynchronize(strm);
+  const hipError_t es = hipStreamSynchronize(strm);  // also after a failed launch, before the workspace is freed
+  if (e == hipSuccess) e = es;
   if (e == hipSuccess && ms_out) {
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, e0, e1);
@@ -632,8 +653,12 @@ ooc_status ooc_device_copy(int32_t device, void* dst, const void* src, size_t by
   if (st != OOC_OK) return st;
   DevCtx& c = g_dev[device];
   std::lock_guard<std::mutex> lock(c.mu);
-  HIPCHK(launch_copy(dst, src, bytes, c.st[1]), "copy launch");
-  HIPCHK(hipStreamSynchronize(c.st[1]), "hipStreamSynchronize");
+  st = ensure_streams(c);
+  if (st != OOC_OK) return st;
+  const hipError_t e = launch_copy(dst, src, bytes, c.st[1]);
+  const hipError_t es = hipStreamSynchronize(c.st[1]);
+  if (e != hipSuccess) return hip_fail(e, "copy launch");
+  HIPCHK(es, "hipStreamSynchronize");
   return OOC_OK;
 }
 
