@@ -186,33 +186,33 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int64_t m0 = (int64_t)blockIdx.y * SBM, n0 = (int64_t)blockIdx.x * SBN;
-  // global -> register staging: each thread moves 4 x 16 bytes of A and of B per chunk
-  // (row r = tid/2 and the next 64 rows, 32-element half h = tid%2 of the 64-k chunk)
-  const int lr = tid >> 2, lq = (tid & 3) * 16;  // row within 64-row half, 16-element quarter
-  uint4 ra[2][2], rb[2][2];
+  // global -> register staging: each thread moves 4 x 16 bytes of A and of B per
+  // chunk: a 16-element quarter lq of rows lr and lr + 64 of the 64-k chunk
+  const int lr = tid >> 2, lq = (tid & 3) * 16;
+  // (named registers, not arrays: an array here was placed in scratch memory,
+  // which serialised every global load behind its store)
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
   const int nchunks = (int)(kpad / SKC);
 
   auto gload = [&](int p, int q, int cc) {
-    const uint16_t* pa = Ap + ((int64_t)(p - 1) * mpad + m0) * kpad + (int64_t)cc * SKC;
-    const uint16_t* pb = Bp + ((int64_t)(q - 1) * npad + n0) * kpad + (int64_t)cc * SKC;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int row = lr + 64 * h;
-      const uint4* a4 = reinterpret_cast<const uint4*>(pa + (int64_t)row * kpad + lq);
-      const uint4* b4 = reinterpret_cast<const uint4*>(pb + (int64_t)row * kpad + lq);
-      ra[h][0] = a4[0]; ra[h][1] = a4[1];
-      rb[h][0] = b4[0]; rb[h][1] = b4[1];
-    }
+    const uint16_t* pa = Ap + ((int64_t)(p - 1) * mpad + m0) * kpad + (int64_t)cc * SKC + lq;
+    const uint16_t* pb = Bp + ((int64_t)(q - 1) * npad + n0) * kpad + (int64_t)cc * SKC + lq;
+    const uint4* a0 = reinterpret_cast<const uint4*>(pa + (int64_t)lr * kpad);
+    const uint4* a1 = reinterpret_cast<const uint4*>(pa + (int64_t)(lr + 64) * kpad);
+    const uint4* b0 = reinterpret_cast<const uint4*>(pb + (int64_t)lr * kpad);
+    const uint4* b1 = reinterpret_cast<const uint4*>(pb + (int64_t)(lr + 64) * kpad);
+    ra0 = a0[0]; ra1 = a0[1]; ra2 = a1[0]; ra3 = a1[1];
+    rb0 = b0[0]; rb1 = b0[1]; rb2 = b1[0]; rb3 = b1[1];
   };
   auto lstore = [&](int buf) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int row = lr + 64 * h;
-      *reinterpret_cast<uint4*>(&As[buf][row][lq]) = ra[h][0];
-      *reinterpret_cast<uint4*>(&As[buf][row][lq + 8]) = ra[h][1];
-      *reinterpret_cast<uint4*>(&Bs[buf][row][lq]) = rb[h][0];
-      *reinterpret_cast<uint4*>(&Bs[buf][row][lq + 8]) = rb[h][1];
-    }
+    *reinterpret_cast<uint4*>(&As[buf][lr][lq]) = ra0;
+    *reinterpret_cast<uint4*>(&As[buf][lr][lq + 8]) = ra1;
+    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq]) = ra2;
+    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq + 8]) = ra3;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq]) = rb0;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq + 8]) = rb1;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq]) = rb2;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq + 8]) = rb3;
   };
 
   const int fr = lane & 31, fk = 8 * (lane >> 5);
