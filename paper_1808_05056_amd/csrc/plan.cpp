@@ -185,7 +185,9 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
     const double products = slices * (slices + 1) / 2.0;
     const double rate = mc.split_tflops_per_product * 1e12 / products;
     const double slice_s = (double)(m + n) * k * (8.0 + 2.0 * slices) / 4e12;
-    return mc.kernel_launch_s * 3 + slice_s + 2.0 * m * n * k / rate;
+    // the FP64 slice-sum tile is read and written once per weight (s weights)
+    const double sum_s = (double)slices * 16.0 * m * n / mc.hbm_bytes_per_s;
+    return mc.kernel_launch_s * 3 + slice_s + sum_s + 2.0 * m * n * k / rate;
   }
   return mc.kernel_launch_s + t;
 }
