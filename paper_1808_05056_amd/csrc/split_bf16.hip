@@ -153,7 +153,8 @@ __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const do
 // For each weight t (from s+1 down to 2) the kernel walks the K range in
 // chunks of 64; every chunk of every pair (p, t-p) is staged in LDS (A plane
 // rows and transposed B plane rows, k contiguous), double-buffered with the
-// next chunk prefetched into registers.  FP32 accumulators are folded into
+// next chunk prefetched into registers without a break at window or weight
+// boundaries.  FP32 accumulators are folded into
 // integer sums U_t after windows of 256 (t <= 3), 128 (t <= 7) or 64 k, the
 // longest windows whose partial sums provably stay below 2^24; with at most
 // 8192 k per launch |U_t| < 8192 * 10 * 2^14 < 2^31, so int32 holds U_t
@@ -216,8 +217,22 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
   };
 
   const int fr = lane & 31, fk = 8 * (lane >> 5);
+  // The steps of one weight t run window by window; inside a window over the
+  // pairs (p, t-p), each over the window's chunks.  The next step is always
+  // prefetched, also across window boundaries (a window only folds the FP32
+  // accumulators into the integer sums) and across weights (the next weight's
+  // first step is loaded into registers before the slice-sum update).
+  struct Step { int c0, wlen, pi, ci; };
+  auto first_step = [&](int t) { return Step{0, nchunks < fold_window_chunks(t) ? nchunks : fold_window_chunks(t), 0, 0}; };
+  auto plo_of = [&](int t) { return t - s > 1 ? t - s : 1; };
+  {
+    const int t0 = s + 1;
+    gload(plo_of(t0), t0 - plo_of(t0), 0);
+    lstore(0);
+    __syncthreads();
+  }
   for (int t = s + 1; t >= 2; --t) {
-    const int plo = t - s > 1 ? t - s : 1, phi = t - 1 < s ? t - 1 : s;
+    const int plo = plo_of(t), phi = t - 1 < s ? t - 1 : s;
     const int np = phi - plo + 1;
     const int wc = fold_window_chunks(t);
     int32_t U[2][2][16];  // exact: |U_t| < 8192 * 10 * 2^14 < 2^31 for K panels of at most 8192
@@ -227,49 +242,60 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) U[i][j][v] = 0;
-    // steps run window by window; inside a window over the pairs, then the window's chunks
-    for (int c0 = 0; c0 < nchunks; c0 += wc) {
-      const int wlen = (nchunks - c0) < wc ? (nchunks - c0) : wc;
-      const int nsteps = np * wlen;
-      f32x16 acc[2][2];
+    f32x16 acc[2][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
-      gload(plo, t - plo, c0);
-      __syncthreads();  // the previous window's readers are done with buffer 0
-      lstore(0);
-      __syncthreads();
-      for (int st = 0; st < nsteps; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nsteps) {
-          const int p1 = plo + (st + 1) / wlen, cc1 = c0 + (st + 1) % wlen;
-          gload(p1, t - p1, cc1);
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+    const int nsteps = np * nchunks;
+    Step cur = first_step(t);
+    for (int st = 0; st < nsteps; ++st) {
+      const int buf = st & 1;
+      // the step after this one (within weight t)
+      Step nx = cur;
+      bool window_end = false;
+      if (++nx.ci == nx.wlen) {
+        nx.ci = 0;
+        if (++nx.pi == np) {
+          nx.pi = 0;
+          window_end = true;
+          nx.c0 += nx.wlen;
+          nx.wlen = (nchunks - nx.c0) < wc ? (nchunks - nx.c0) : wc;
         }
-#pragma unroll
-        for (int kk = 0; kk < SKC; kk += 16) {
-          bf16x8 a[2], b[2];
-#pragma unroll
-          for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 32 + fr][kk + fk]);
-#pragma unroll
-          for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 32 + fr][kk + fk]);
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        if (st + 1 < nsteps) lstore(buf ^ 1);
-        __syncthreads();
       }
+      const bool more = st + 1 < nsteps;
+      if (more) gload(plo + nx.pi, t - (plo + nx.pi), nx.c0 + nx.ci);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int kk = 0; kk < SKC; kk += 16) {
+        bf16x8 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 32 + fr][kk + fk]);
 #pragma unroll
-          for (int v = 0; v < 16; ++v) U[i][j][v] += (int32_t)acc[i][j][v];
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 32 + fr][kk + fk]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      if (window_end || !more) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              U[i][j][v] += (int32_t)acc[i][j][v];
+              acc[i][j][v] = 0.f;
+            }
+      }
+      if (more) lstore(buf ^ 1);
+      __syncthreads();
+      cur = nx;
     }
+    // prefetch the next weight's first step while the slice sums are added
+    if (t > 2) gload(plo_of(t - 1), (t - 1) - plo_of(t - 1), 0);
     // S = S + U_t 2^(e_i + f_j - 8t), from the smallest weight up.  The sums go
     // through LDS (the staging buffers are idle now) so that the update below
     // walks the tile row by row with consecutive threads on consecutive columns.
@@ -312,6 +338,10 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
       }
     }
     __syncthreads();  // LDS is staging space again
+    if (t > 2) {
+      lstore(0);
+      __syncthreads();
+    }
   }
 }
 
