@@ -280,12 +280,14 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
 static std::vector<int64_t> split_sizes(int64_t n, int64_t align, int max_parts) {
   std::set<int64_t> out;
   // block sizes are multiples of the kernel tile (or the whole extent when
-  // it is smaller): a block narrower than a tile wastes most of the tile
+  // it is smaller): a block narrower than a tile wastes most of the tile;
+  // narrower powers of two are kept for budgets too small for a whole tile
   for (int parts = 1; parts <= max_parts; ++parts) {
     int64_t s = ceil_div(n, parts);
     if (align > 1) s = ceil_div(s, align) * align;
     out.insert(std::min(s, n));
   }
+  for (int64_t s = 1; s < align && s < n; s *= 2) out.insert(s);
   return std::vector<int64_t>(out.begin(), out.end());
 }
 
@@ -297,6 +299,8 @@ static std::vector<int64_t> panel_sizes(int64_t K) {
     int64_t s = ceil_div(ceil_div(K, d), 64) * 64;
     if (s >= 256 && s < K) out.insert(s);
   }
+  // short panels for budgets too small for longer ones
+  for (int64_t s = 16; s < 256 && s < K; s *= 2) out.insert(s);
   return std::vector<int64_t>(out.begin(), out.end());
 }
 
@@ -430,13 +434,33 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
       }
     }
   }
+  if (cands.empty()) {
+    // the paper's partition covers every budget its footprint rule allows
+    ooc_plan_t pp{};
+    if (paper_plan(pb, budget_bytes, &pp, prec, slices)) cands.push_back({pp, 0.0});
+  }
   if (cands.empty()) return fail(OOC_ERR_BUDGET, "no plan fits in the device budget");
   std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.lb < b.lb; });
-  // simulate the most promising candidates (fewer for products that take
-  // milliseconds, where planning time would show), spread over host threads;
-  // results are collected in candidate order, so the choice is deterministic
+  // simulate the most promising candidates, spread over host threads; fewer
+  // for products that take milliseconds, where planning time would show, and
+  // fewer when the schedules are long (about 3 million simulated operations
+  // in total).  Results are collected in candidate order, so the choice is
+  // deterministic.
   const bool small = 2.0 * (double)M * N * std::max<int64_t>(K, 1) < 1e11;
-  const size_t keep = std::min<size_t>(cands.size(), small ? 64 : 384);
+  size_t keep = std::min<size_t>(cands.size(), small ? 64 : 384);
+  {
+    double ops_total = 0.0;
+    for (size_t c = 0; c < keep; ++c) {
+      const ooc_plan_t& q = cands[c].p;
+      const double tasks = (double)ceil_div(M, q.mb) * (double)ceil_div(N, q.nb) *
+                           (double)(K > 0 ? ceil_div(K, q.kb) : 1);
+      ops_total += 4.0 * tasks;
+      if (ops_total > 3e6 && c >= 8) {
+        keep = c;
+        break;
+      }
+    }
+  }
   std::vector<double> simt(keep, -1.0);
   auto work = [&](size_t first, size_t stride) {
     for (size_t c = first; c < keep; c += stride) {

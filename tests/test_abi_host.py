@@ -271,3 +271,39 @@ def test_gpu_test_plans_fit_their_budgets():
                 assert ooc.ooc_plan_footprint(1024, 1024, 1024, beta, plan) <= 8 << 20, name
     split_plan = ooc.make_plan(256, 320, 320, ooc.ORDER_COLS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
     assert ooc.ooc_plan_footprint(1000, 900, 1100, 0.5, split_plan) <= 8 << 20
+
+
+DEGENERATE = [
+    # M, N, K, beta, budget bytes, precision
+    (1, 1, 1, 0.5, 64 << 10, ooc.FP64),
+    (1, 5000, 300, 0.5, 256 << 10, ooc.FP64),     # a row vector times a wide matrix
+    (5000, 1, 300, 1.0, 256 << 10, ooc.FP64),     # a matrix times a column vector
+    (3000, 3000, 1, 0.5, 1 << 20, ooc.FP64),      # rank-one update
+    (2000, 17, 2000, 0.0, 512 << 10, ooc.FP64),   # skinny C
+    (1500, 1300, 1700, 0.5, 3 << 20, ooc.SPLIT_BF16),
+    (257, 3001, 129, 0.5, 2 << 20, ooc.SPLIT_BF16),
+]
+
+
+@pytest.mark.parametrize("case", range(len(DEGENERATE)))
+def test_model_planner_covers_small_budgets(case):
+    M, N, K, beta, budget, prec = DEGENERATE[case]
+    opts = ooc.make_opts(precision=prec, slices=5)
+    plan = ooc.ooc_plan(M, N, K, beta, budget, opts)
+    assert ooc.ooc_plan_footprint(M, N, K, beta, plan) <= budget
+    ops, arena = ooc.ooc_schedule(M, N, K, 1.0, beta, plan)
+    assert sched_ref.check_hazards(ops) == []
+    assert sched_ref.check_cover(ops, M, N, K) == []
+
+
+def test_model_planner_finds_a_plan_where_the_papers_rule_does():
+    rng = np.random.default_rng(12)
+    for _ in range(30):
+        M, N, K = (int(x) for x in rng.integers(1, 3000, 3))
+        budget = int(rng.integers(8, 4096)) * 1024
+        try:
+            ooc.ooc_plan(M, N, K, 0.5, budget, ooc.make_opts(planner=ooc.PLAN_PAPER))
+        except ooc.OOCError:
+            continue
+        plan = ooc.ooc_plan(M, N, K, 0.5, budget)
+        assert ooc.ooc_plan_footprint(M, N, K, 0.5, plan) <= budget

@@ -200,3 +200,33 @@ def test_full_size_sampled(wname):
         _say(f"  sampled {len(rows)} rows, normalised error {err:.2e}")
     finally:
         pp.free()
+
+
+# ---- degenerate shapes through tiny budgets (vectors, rank-one updates, skinny C) -----
+
+DEGENERATE = [
+    # M, N, K, alpha, beta, budget bytes, precision
+    (1, 1, 1, 1.5, 0.5, 64 << 10, ooc.FP64),
+    (1, 5000, 300, 1.0, 0.5, 256 << 10, ooc.FP64),
+    (5000, 1, 300, -2.0, 1.0, 256 << 10, ooc.FP64),
+    (3000, 3000, 1, 1.0, 0.5, 1 << 20, ooc.FP64),
+    (2000, 17, 2000, 0.5, 0.0, 512 << 10, ooc.FP64),
+    (1500, 1300, 1700, 1.0, 0.5, 3 << 20, ooc.SPLIT_BF16),
+    (257, 3001, 129, 1.0, 0.5, 2 << 20, ooc.SPLIT_BF16),
+]
+
+
+@pytest.mark.parametrize("case", range(len(DEGENERATE)))
+def test_degenerate_shapes_small_budgets(case):
+    M, N, K, alpha, beta, budget, prec = DEGENERATE[case]
+    _say(f"degenerate case {case}: M={M} N={N} K={K} budget={budget} precision={prec}")
+    w = W.Workload(f"degenerate{case}", M, N, K, alpha, beta, budget, seed=50 + case)
+    pp = PinnedProblem(w, nan_c=(beta == 0.0))
+    try:
+        st, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget,
+                                 ooc.make_opts(precision=prec, slices=5))
+        assert stats.arena_bytes <= budget and stats.plan.precision == prec
+        rows = np.arange(M) if M * N * K < 2e8 else sample_rows(M, stats.plan.mb)
+        check_rows(w, pp, rows)
+    finally:
+        pp.free()
