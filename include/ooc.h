@@ -52,9 +52,9 @@ typedef enum {
 
 /* FP64: tile products in FP64 on matrix cores.  SPLIT_BF16: each tile product
  * is formed from s BF16 slices per operand (error-free splitting, Ozaki et al.
- * 2012): slice products are exact with FP32 accumulation over chunks of 64,
- * chunk sums are added exactly in FP64, and the weighted slice sums are
- * combined in FP64; only the slices beyond s are dropped (truncation error
+ * 2012): slice products are exact with FP32 accumulation over windows of
+ * 64-256 k, window sums are added exactly in int32, and the weighted slice
+ * sums are combined in FP64; only the slices beyond s are dropped (truncation error
  * about (s+1) 2^(-8s) relative to (|A||B|)_ij times the row/column spread). */
 typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1 } ooc_precision;
 

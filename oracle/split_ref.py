@@ -26,7 +26,7 @@ units with FP32 accumulation.  Steps, for one K panel of A (m x k) and B (k x n)
     in panels of kb, steps 1-4 run per panel and C accumulates:
     C = alpha*S_0 + beta*C, then C = alpha*S_p + C.
 
-The grouping of equal weights in step 4 is this build's reading: the method
+The grouping of equal weights in step 4 is a reading of the method, which
 only requires the slice sum in FP64, and grouping keeps the result
 independent of how the equal-weight pairs are ordered.
 """

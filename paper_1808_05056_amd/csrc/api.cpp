@@ -194,7 +194,7 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
           break;
         default:
           status = OOC_ERR_ARG;
-          msg = "operation kind not supported by this build";
+          msg = "unknown operation kind";
           break;
       }
     }

@@ -12,10 +12,11 @@
 //     Each step is exact; |m_1| <= 256 and |m_p| <= 128 (p >= 2) are integers that
 //     BF16 holds exactly.  Same for B with f_j.
 //  3. For each weight t = p + q (2 <= t <= s+1), U_t = sum over p + q = t of
-//     sum_k mA_p[i,k] mB_q[k,j].  Inside a chunk of 64 k every partial sum is an
-//     integer below 2^24 (at most 64 * (2*2^15 + 6*2^14) for t <= 9, or
-//     64 * 2^16 for t = 2), so the FP32 MFMA accumulation is exact; chunk sums
-//     are added into U_t in FP64, also exactly.
+//     sum_k mA_p[i,k] mB_q[k,j].  A product of slices is at most 2^16 (t = 2),
+//     2^15 (t = 3) or 2^14 in magnitude, so inside a window of 256, 128 or 64 k
+//     of all pairs of the weight every partial sum is an integer below 2^24 and
+//     the FP32 MFMA accumulation is exact; window sums are added into an int32
+//     U_t, exact for K panels of at most 8192.
 //  4. S = sum over t from s+1 down to 2 of U_t * 2^(e_i + f_j - 8t), accumulated
 //     in FP64 from the smallest weight to the largest.
 //  5. C = alpha*S + beta*C + gamma*D with separate roundings (no fused
