@@ -564,10 +564,12 @@ static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes,
   ooc_status st = plan_candidates(pb, budget_bytes, opts, &plans, &times);
   if (st != OOC_OK) return st;
   size_t best = 0;
-  if (planner == OOC_PLAN_MLP) {
+  const bool fp64 = !opts || opts->precision == OOC_FP64;
+  if (planner == OOC_PLAN_MLP && fp64) {
     // the network ranks the cost model's shortlist: the plans it was trained
-    // on are the model's best candidates plus a few random others, so outside
-    // the shortlist its predictions are extrapolations
+    // on are FP64 plans among the model's best candidates plus a few random
+    // others, so outside the shortlist (and for split plans) its predictions
+    // would be extrapolations
     const size_t shortlist = std::min<size_t>(plans.size(), 8);
     std::vector<ooc_plan_t> top(plans.begin(), plans.begin() + shortlist);
     std::vector<double> pred;
