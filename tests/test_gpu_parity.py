@@ -198,6 +198,14 @@ def test_full_size_sampled(wname):
         rows = sample_rows(w.M, stats.plan.mb, count=8, seed=1)
         err = check_rows(w, pp, rows)
         _say(f"  sampled {len(rows)} rows, normalised error {err:.2e}")
+        if w.beta == 0.0:
+            # C is not read, so the same operands serve the split-BF16 path at full size
+            st, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget,
+                                     ooc.make_opts(precision=ooc.SPLIT_BF16, slices=6))
+            _say(f"  split-BF16 x6 plan {stats.plan} t={stats.t_total_s:.3f}s")
+            assert stats.arena_bytes <= w.budget and stats.plan.precision == ooc.SPLIT_BF16
+            err = check_rows(w, pp, sample_rows(w.M, stats.plan.mb, count=8, seed=2))
+            _say(f"  split-BF16 normalised error {err:.2e}")
     finally:
         pp.free()
 
