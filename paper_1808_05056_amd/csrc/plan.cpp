@@ -182,12 +182,14 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
   }
   if ((k & 1) || (n & 1)) t *= mc.kernel_scalar_factor;
   if (split) {
+    // the slice-product kernel computes whole 128 x 128 tiles
+    const double mp = std::ceil(m / 128.0) * 128.0, np = std::ceil(n / 128.0) * 128.0;
     const double products = slices * (slices + 1) / 2.0;
     const double rate = mc.split_tflops_per_product * 1e12 / products;
-    const double slice_s = (double)(m + n) * k * (8.0 + 2.0 * slices) / 4e12;
+    const double slice_s = (mp + np) * k * (8.0 + 2.0 * slices) / 4e12;
     // the FP64 slice-sum tile is read and written once per weight (s weights)
-    const double sum_s = (double)slices * 16.0 * m * n / mc.hbm_bytes_per_s;
-    return mc.kernel_launch_s * 3 + slice_s + sum_s + 2.0 * m * n * k / rate;
+    const double sum_s = (double)slices * 16.0 * mp * np / mc.hbm_bytes_per_s;
+    return mc.kernel_launch_s * 3 + slice_s + sum_s + 2.0 * mp * np * k / rate;
   }
   return mc.kernel_launch_s + t;
 }
@@ -564,12 +566,12 @@ static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes,
   ooc_status st = plan_candidates(pb, budget_bytes, opts, &plans, &times);
   if (st != OOC_OK) return st;
   size_t best = 0;
-  const bool fp64 = !opts || opts->precision == OOC_FP64;
-  if (planner == OOC_PLAN_MLP && fp64) {
+  if (planner == OOC_PLAN_MLP) {
     // the network ranks the cost model's shortlist: the plans it was trained
-    // on are FP64 plans among the model's best candidates plus a few random
-    // others, so outside the shortlist (and for split plans) its predictions
-    // would be extrapolations
+    // on are among the model's best candidates plus a few random others, so
+    // outside the shortlist its predictions would be extrapolations (and a
+    // network trained on FP64 timings only declines split plans: the model's
+    // choice stands)
     const size_t shortlist = std::min<size_t>(plans.size(), 8);
     std::vector<ooc_plan_t> top(plans.begin(), plans.begin() + shortlist);
     std::vector<double> pred;

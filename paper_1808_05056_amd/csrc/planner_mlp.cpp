@@ -181,6 +181,12 @@ bool mlp_predict(const Problem& pb, uint64_t budget_bytes, const std::vector<ooc
     if (!g_net.loaded) return false;
     net = g_net;
   }
+  // A network whose training set held FP64 plans only saw a constant slice
+  // count (stored as mean 0, deviation 1): it does not rank split plans.
+  constexpr int kSliceFeature = OOC_MLP_FEATURES - 1;
+  const bool knows_split = net.fmean[kSliceFeature] != 0.f || net.fstd[kSliceFeature] != 1.f;
+  for (const ooc_plan_t& p : plans)
+    if (p.precision == OOC_SPLIT_BF16 && !knows_split) return false;
   const int64_t n = (int64_t)plans.size();
   std::vector<float> X((size_t)n * OOC_MLP_FEATURES), y(n);
   if (features_for(pb, budget_bytes, plans.data(), n, X.data()) != OOC_OK) return false;

@@ -9,10 +9,15 @@ device, Section VI).  This tool
           log-uniform in [4096, 24576], budgets log-uniform 256 MiB - 8 GiB,
           seed 40), fits the network with the library's GPU kernels
           (ooc_mlp_fit: full-batch Adam, L2 weight decay) and writes the weights;
-  fit     refits the network from the timings a train run saved;
+          --precision split times split-BF16 plans (--slices) instead;
+  fit     refits the network from the timings one or more train runs saved
+          (--data a.npz,b.npz: FP64 and split timings fit one network, whose
+          slice-count feature tells the two apart);
   eval    times every candidate of the evaluation batch (seed 4) that the cost
           model, the network or the paper's rule would consider, and reports
-          the regret t(choice) / t(best measured) - 1 of each planner.
+          the regret t(choice) / t(best measured) - 1 of each planner;
+  sweep   times the cost model's best candidates for one named workload (and
+          the model's, the network's and the paper's choices): the swept plan.
 
     python -m paper_1808_05056_amd.planner_sweep train --out planner_mlp.txt
     python -m paper_1808_05056_amd.planner_sweep eval --weights planner_mlp.txt
@@ -75,10 +80,20 @@ def _key(p):
     return tuple(p.as_dict().values())
 
 
-def candidate_set(w, n_model, n_random, rng, extra=()):
-    plans, model_s = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget)
+def _opts(args, planner=ooc.PLAN_AUTO):
+    if args.precision == "split":
+        return ooc.make_opts(planner=planner, precision=ooc.SPLIT_BF16, slices=args.slices)
+    return ooc.make_opts(planner=planner)
+
+
+def candidate_set(w, n_model, n_random, rng, extra=(), opts=None, within=None):
+    """The model's n_model best candidates, n_random others (with a model time
+    at most `within` times the best, if given) and `extra`."""
+    plans, model_s = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget, opts)
     chosen = list(range(min(n_model, len(plans))))
     rest = list(range(len(chosen), len(plans)))
+    if within:
+        rest = [i for i in rest if model_s[i] <= within * model_s[0]]
     if rest and n_random:
         chosen += list(rng.choice(rest, size=min(n_random, len(rest)), replace=False))
     out = [plans[i] for i in chosen]
@@ -97,9 +112,17 @@ def train(args):
     rng = np.random.default_rng(1)
     X, y, meta = [], [], []
     t0 = time.time()
+    split = args.precision == "split"
     for idx, w in enumerate(problems):
-        paper = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, ooc.make_opts(planner=ooc.PLAN_PAPER))
-        plans, _, _ = candidate_set(w, args.n_model, args.n_random, rng, extra=[paper])
+        # FP64 runs also time the paper's plan; its split form (slivers of a
+        # few rows padded to whole tiles) is far outside what the network ranks
+        paper = [] if split else [ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, _opts(args, ooc.PLAN_PAPER))]
+        try:
+            plans, _, _ = candidate_set(w, args.n_model, args.n_random, rng, extra=paper, opts=_opts(args),
+                                        within=4.0 if split else None)
+        except ooc.OOCError as e:
+            _log(f"[train] problem {idx + 1}/{len(problems)}: no plan ({e})")
+            continue
         feats = ooc.ooc_mlp_features(w.M, w.N, w.K, w.beta, w.budget, plans)
         views = bufs.views(w)
         for p, f in zip(plans, feats):
@@ -108,15 +131,18 @@ def train(args):
             y.append(t)
             meta.append({"problem": idx, "M": w.M, "N": w.N, "K": w.K, "budget": w.budget, "plan": p.as_dict(),
                          "seconds": t})
+            _log(f"[train]   {p} {t:.3f}s")
         _log(f"[train] problem {idx + 1}/{len(problems)} M={w.M} N={w.N} K={w.K} budget={w.budget / GiB:.2f} GiB: "
              f"{len(plans)} plans, best {min(y[-len(plans):]):.3f}s ({time.time() - t0:.0f}s elapsed)")
+        _save(args.data, X, y, meta)  # after every problem, so a cut-short run keeps what it timed
     bufs.free()
-    X = np.array(X, dtype=np.float32)
-    y = np.array(y, dtype=np.float32)
-    np.savez(args.data, X=X, y=y)
-    with open(args.data + ".json", "w") as f:
+    fit_and_save(np.array(X, dtype=np.float32), np.array(y, dtype=np.float32), args)
+
+
+def _save(path, X, y, meta):
+    np.savez(path, X=np.array(X, dtype=np.float32), y=np.array(y, dtype=np.float32))
+    with open(path + ".json", "w") as f:
         json.dump(meta, f)
-    fit_and_save(X, y, args)
 
 
 def fit_and_save(X, y, args):
@@ -127,8 +153,10 @@ def fit_and_save(X, y, args):
 
 
 def fit(args):
-    d = np.load(args.data)
-    fit_and_save(d["X"], d["y"], args)
+    parts = [np.load(f) for f in args.data.split(",")]
+    X = np.concatenate([d["X"] for d in parts])
+    y = np.concatenate([d["y"] for d in parts])
+    fit_and_save(X, y, args)
 
 
 def evaluate(args):
@@ -137,37 +165,50 @@ def evaluate(args):
         ooc.ooc_mlp_load(args.weights)
     problems = W.problem_batch(4, count=args.count)
     bufs = Buffers(problems)
-    rng = np.random.default_rng(2)
+    split = args.precision == "split"
     rows = []
     t0 = time.time()
     for idx, w in enumerate(problems):
-        pm = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, ooc.make_opts(planner=ooc.PLAN_MODEL))
-        pl = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, ooc.make_opts(planner=ooc.PLAN_MLP))
-        pp = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, ooc.make_opts(planner=ooc.PLAN_PAPER))
-        all_plans, model_s = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget)
-        mlp_s = ooc.ooc_mlp_predict(w.M, w.N, w.K, w.beta, w.budget, all_plans)
+        try:
+            pm = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, _opts(args, ooc.PLAN_MODEL))
+            pl = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, _opts(args, ooc.PLAN_MLP))
+            # the paper's rule has no split form worth timing (slivers of a few
+            # rows padded to whole tiles)
+            pp = None if split else ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, _opts(args, ooc.PLAN_PAPER))
+        except ooc.OOCError as e:
+            _log(f"[eval] {idx + 1}/{len(problems)}: skipped, a planner finds no plan ({e})")
+            continue
+        all_plans, model_s = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget, _opts(args))
+        # the network's own favourites (split: among the model's 16 best only)
+        ranked = all_plans[:16] if split else all_plans
+        mlp_s = ooc.ooc_mlp_predict(w.M, w.N, w.K, w.beta, w.budget, ranked)
         by_mlp = list(np.argsort(mlp_s)[: args.n_mlp])
         sweep = [all_plans[i] for i in range(min(args.n_model, len(all_plans)))]
-        sweep += [all_plans[i] for i in by_mlp]
-        sweep += [pm, pl, pp]
+        sweep += [ranked[i] for i in by_mlp]
+        sweep += [pm, pl] + ([] if split else [pp])
         uniq, seen = [], set()
         for p in sweep:
             if _key(p) not in seen:
                 uniq.append(p)
                 seen.add(_key(p))
         views = bufs.views(w)
-        times = {(_key(p)): time_plan(w, views, p, args.reps) for p in uniq}
+        times = {}
+        for p in uniq:
+            times[_key(p)] = time_plan(w, views, p, args.reps)
+            _log(f"[eval]   {p} {times[_key(p)]:.3f}s")
         best = min(times.values())
         r = {"problem": idx, "M": w.M, "N": w.N, "K": w.K, "budget": w.budget, "swept": len(uniq),
-             "best_s": best, "model_s": times[_key(pm)], "mlp_s": times[_key(pl)], "paper_s": times[_key(pp)],
-             "flops": w.flops}
+             "best_s": best, "model_s": times[_key(pm)], "mlp_s": times[_key(pl)], "flops": w.flops}
+        if pp is not None:
+            r["paper_s"] = times[_key(pp)]
         rows.append(r)
+        paper_txt = f" paper {r['paper_s'] / best - 1:+.3f}" if pp is not None else ""
         _log(f"[eval] {idx + 1}/{len(problems)} M={w.M} N={w.N} K={w.K} budget={w.budget / GiB:.2f} GiB: best "
-             f"{best:.3f}s model {r['model_s'] / best - 1:+.3f} mlp {r['mlp_s'] / best - 1:+.3f} "
-             f"paper {r['paper_s'] / best - 1:+.3f} ({time.time() - t0:.0f}s elapsed)")
+             f"{best:.3f}s model {r['model_s'] / best - 1:+.3f} mlp {r['mlp_s'] / best - 1:+.3f}{paper_txt} "
+             f"({time.time() - t0:.0f}s elapsed)")
     bufs.free()
     summ = {}
-    for k in ("model", "mlp", "paper"):
+    for k in ("model", "mlp") + (() if split else ("paper",)):
         reg = np.array([r[f"{k}_s"] / r["best_s"] - 1 for r in rows])
         tf = np.array([r["flops"] / r[f"{k}_s"] / 1e12 for r in rows])
         summ[k] = {"mean_regret": float(reg.mean()), "median_regret": float(np.median(reg)),
@@ -180,6 +221,49 @@ def evaluate(args):
     _log(json.dumps(summ))
 
 
+def sweep(args):
+    import synth
+    from synth import workloads as W
+    w = W.BY_NAME[args.workload]
+    split = args.precision == "split"
+    if args.weights:
+        ooc.ooc_mlp_load(args.weights)
+    mats = [ooc.PinnedMatrix(w.M, w.K), ooc.PinnedMatrix(w.K, w.N), ooc.PinnedMatrix(w.M, w.N)]
+    try:
+        A, B, C = (m.array for m in mats)
+        synth.fill(A, w.spec_a())
+        synth.fill(B, w.spec_b())
+        synth.fill(C, w.spec_c())
+        plans, model_s = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget, _opts(args))
+        named = {"model": ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, _opts(args, ooc.PLAN_MODEL)),
+                 "mlp": ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, _opts(args, ooc.PLAN_MLP))}
+        if not split:
+            named["paper"] = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, _opts(args, ooc.PLAN_PAPER))
+        todo, seen = [], set()
+        for p in plans[: args.top] + list(named.values()):
+            if _key(p) not in seen:
+                todo.append(p)
+                seen.add(_key(p))
+        rows = []
+        for p in todo:
+            t = time_plan(w, (A, B, C), p, args.reps)
+            rows.append({"plan": p.as_dict(), "seconds": t, "tflops": w.flops / t / 1e12,
+                         "model_s": ooc.ooc_plan_predict(w.M, w.N, w.K, w.beta, p)})
+            _log(f"[sweep] {p} {t:.4f}s {w.flops / t / 1e12:.2f} TFLOP/s")
+        best = min(rows, key=lambda r: r["seconds"])
+        out = {"workload": w.name, "precision": args.precision, "slices": args.slices if split else 0,
+               "swept": len(rows), "best": best, "rows": rows}
+        for name, p in named.items():
+            r = next(r for r in rows if r["plan"] == p.as_dict())
+            out[name] = {"seconds": r["seconds"], "tflops": r["tflops"], "regret": r["seconds"] / best["seconds"] - 1}
+        with open(args.report, "w") as f:
+            json.dump(out, f, indent=1)
+        _log(json.dumps({k: v for k, v in out.items() if k != "rows"}))
+    finally:
+        for m in mats:
+            m.free()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -189,6 +273,10 @@ def main(argv=None):
     t.add_argument("--n-random", type=int, default=6)
     t.add_argument("--reps", type=int, default=1)
     f = sub.add_parser("fit")
+    e = sub.add_parser("eval")
+    for q in (t, e):
+        q.add_argument("--precision", choices=("fp64", "split"), default="fp64")
+        q.add_argument("--slices", type=int, default=5)
     for q in (t, f):
         q.add_argument("--hidden", type=int, default=64)
         q.add_argument("--epochs", type=int, default=1000)
@@ -197,15 +285,22 @@ def main(argv=None):
         q.add_argument("--seed", type=int, default=0)
         q.add_argument("--data", default="planner_sweep_train.npz")
         q.add_argument("--out", default="planner_mlp.txt")
-    e = sub.add_parser("eval")
     e.add_argument("--count", type=int, default=64)
     e.add_argument("--n-model", type=int, default=6)
     e.add_argument("--n-mlp", type=int, default=4)
     e.add_argument("--reps", type=int, default=1)
     e.add_argument("--weights", default=None)
     e.add_argument("--report", default="planner_eval.json")
+    sw = sub.add_parser("sweep")
+    sw.add_argument("--workload", default="tall-262144x8192x8192-budget-2GiB")
+    sw.add_argument("--precision", choices=("fp64", "split"), default="fp64")
+    sw.add_argument("--slices", type=int, default=5)
+    sw.add_argument("--top", type=int, default=12)
+    sw.add_argument("--reps", type=int, default=2)
+    sw.add_argument("--weights", default=None)
+    sw.add_argument("--report", default="planner_sweep_workload.json")
     args = ap.parse_args(argv)
-    {"train": train, "fit": fit, "eval": evaluate}[args.cmd](args)
+    {"train": train, "fit": fit, "eval": evaluate, "sweep": sweep}[args.cmd](args)
 
 
 if __name__ == "__main__":
