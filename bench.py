@@ -34,12 +34,13 @@ def log(msg):
 
 
 KERNEL_SOURCES = ["paper_1808_05056_amd/csrc/dgemm_f64_kernel.hpp", "paper_1808_05056_amd/csrc/dgemm_f64.hip"]
+SPLIT_SOURCES = ["paper_1808_05056_amd/csrc/split_bf16.hip"]
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
@@ -165,7 +166,8 @@ def main():
         achieved = work * args.steps / kbusy / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel_source": kernel_source_hash(), "plan_tag": plan_tag,
+                "kernel_source": kernel_source_hash(KERNEL_SOURCES if prec == ooc.FP64 else SPLIT_SOURCES),
+                "plan_tag": plan_tag,
                 "kernel": kname, "launches_per_step": nkern // args.steps,
                 "avg_launch_ms": round(kbusy / nkern * 1e3, 4)}
     link = None

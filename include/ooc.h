@@ -66,9 +66,10 @@ typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1 } ooc_precision;
  * cost model.  MLP: among the cost model's 8 best candidates, the one with the
  * smallest time predicted by the loaded network (the network shipped beside
  * the library is loaded on first use; falls back to MODEL when none is
- * loaded, and for split-BF16 plans when the loaded network was trained on
- * FP64 timings only, which it records as a constant slice-count feature).
- * AUTO = MODEL. */
+ * loaded, for split-BF16 plans when the loaded network was trained on FP64
+ * timings only, which it records as a constant slice-count feature, and for
+ * problems whose M, N, K or budget lies more than four standard deviations
+ * (log scale) from the training problems' mean).  AUTO = MODEL. */
 typedef enum { OOC_PLAN_AUTO = 0, OOC_PLAN_PAPER = 1, OOC_PLAN_MODEL = 2, OOC_PLAN_MLP = 3 } ooc_planner;
 
 /* Task orders over the grid of C blocks (i: block row, j: block column) and

@@ -62,7 +62,9 @@ struct Machine {
   double kernel_k0 = 30.0;         // per-tile fixed cost in units of k
   double kernel_scalar_factor = 1.15;  // odd leading dimensions (8-byte loads)
   double kernel_launch_s = 6e-6;
-  double split_tflops_per_product = 725.0;  // BF16 slice-product rate (TFLOP/s of BF16 work)
+  double split_tflops_per_product = 725.0;  // BF16 slice-product rate (TFLOP/s of BF16 work), two tiles per CU
+  double split_tflops_1wg_per_product = 350.0;  // same with one tile per CU
+  double split_k0 = 160.0;                   // per weight and tile: pipeline start in units of k
   double hbm_bytes_per_s = 5e12;            // streaming rate of the split kernel's slice-sum tile
   int cus = 256;
 };

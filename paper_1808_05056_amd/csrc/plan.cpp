@@ -182,14 +182,29 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
   }
   if ((k & 1) || (n & 1)) t *= mc.kernel_scalar_factor;
   if (split) {
-    // the slice-product kernel computes whole 128 x 128 tiles
+    // the slice-product kernel computes whole 128 x 128 tiles, two per CU at
+    // a time, in waves like the FP64 kernel; every weight's pass over a tile
+    // pays a pipeline start of split_k0 k
     const double mp = std::ceil(m / 128.0) * 128.0, np = std::ceil(n / 128.0) * 128.0;
     const double products = slices * (slices + 1) / 2.0;
-    const double rate = mc.split_tflops_per_product * 1e12 / products;
+    const double stile = 2.0 * 128.0 * 128.0 * (products * (double)k + slices * mc.split_k0);
+    const double s2 = mc.split_tflops_per_product * 1e12 / mc.cus;
+    const double s1 = mc.split_tflops_1wg_per_product * 1e12 / mc.cus;
+    double ts;
+    if (tiles <= mc.cus) {
+      ts = stile / s1;
+    } else {
+      const double per_wave = 2.0 * mc.cus;
+      const double full = std::floor(tiles / per_wave);
+      const double rest = tiles - full * per_wave;
+      ts = full * 2.0 * stile / s2;
+      if (rest > mc.cus) ts += 2.0 * stile / s2;
+      else if (rest > 0) ts += stile / s1;
+    }
     const double slice_s = (mp + np) * k * (8.0 + 2.0 * slices) / 4e12;
     // the FP64 slice-sum tile is read and written once per weight (s weights)
     const double sum_s = (double)slices * 16.0 * mp * np / mc.hbm_bytes_per_s;
-    return mc.kernel_launch_s * 3 + slice_s + sum_s + 2.0 * mp * np * k / rate;
+    return mc.kernel_launch_s * 6 + slice_s + sum_s + ts;
   }
   return mc.kernel_launch_s + t;
 }

@@ -192,6 +192,13 @@ bool mlp_predict(const Problem& pb, uint64_t budget_bytes, const std::vector<ooc
   if (features_for(pb, budget_bytes, plans.data(), n, X.data()) != OOC_OK) return false;
   for (int64_t c = 0; c < n; ++c)
     for (int j = 0; j < net.d; ++j) X[c * net.d + j] = (X[c * net.d + j] - net.fmean[j]) / net.fstd[j];
+  // M, N, K and the budget (the first four features, the same for every
+  // candidate) more than kMaxZ deviations from the training problems' mean:
+  // the prediction would be an extrapolation, so the network declines
+  constexpr float kMaxZ = 4.f;
+  if (n > 0)
+    for (int j = 0; j < 4; ++j)
+      if (std::fabs(X[j]) > kMaxZ) return false;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = 0;
   if (forward_impl(dev, net.d, net.H, net.params.data(), X.data(), n, y.data()) != OOC_OK) return false;

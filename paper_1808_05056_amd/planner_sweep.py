@@ -129,8 +129,8 @@ def train(args):
             t = time_plan(w, views, p, args.reps)
             X.append(f)
             y.append(t)
-            meta.append({"problem": idx, "M": w.M, "N": w.N, "K": w.K, "budget": w.budget, "plan": p.as_dict(),
-                         "seconds": t})
+            meta.append({"problem": idx, "M": w.M, "N": w.N, "K": w.K, "beta": w.beta, "budget": w.budget,
+                         "plan": p.as_dict(), "seconds": t})
             _log(f"[train]   {p} {t:.3f}s")
         _log(f"[train] problem {idx + 1}/{len(problems)} M={w.M} N={w.N} K={w.K} budget={w.budget / GiB:.2f} GiB: "
              f"{len(plans)} plans, best {min(y[-len(plans):]):.3f}s ({time.time() - t0:.0f}s elapsed)")
@@ -152,10 +152,22 @@ def fit_and_save(X, y, args):
     _log(f"[fit] {len(y)} samples; objective {hist[0]:.4f} -> {hist[-1]:.4f}; weights in {args.out}")
 
 
+def refeature(path):
+    """Features of the plans a train run saved, recomputed with the current
+    cost model (after it changes, the timings stay valid but the model's
+    prediction, one of the features, does not)."""
+    with open(path + ".json") as f:
+        meta = json.load(f)
+    X = np.concatenate([ooc.ooc_mlp_features(r["M"], r["N"], r["K"], r.get("beta", 0.0), r["budget"],
+                                             [ooc.ooc_plan_t(**r["plan"])]) for r in meta]).astype(np.float32)
+    return X, np.array([r["seconds"] for r in meta], dtype=np.float32)
+
+
 def fit(args):
-    parts = [np.load(f) for f in args.data.split(",")]
-    X = np.concatenate([d["X"] for d in parts])
-    y = np.concatenate([d["y"] for d in parts])
+    parts = [refeature(f) if args.refeature else (lambda d: (d["X"], d["y"]))(np.load(f))
+             for f in args.data.split(",")]
+    X = np.concatenate([x for x, _ in parts])
+    y = np.concatenate([t for _, t in parts])
     fit_and_save(X, y, args)
 
 
@@ -273,6 +285,7 @@ def main(argv=None):
     t.add_argument("--n-random", type=int, default=6)
     t.add_argument("--reps", type=int, default=1)
     f = sub.add_parser("fit")
+    f.add_argument("--refeature", action="store_true", help="recompute features with the current cost model")
     e = sub.add_parser("eval")
     for q in (t, e):
         q.add_argument("--precision", choices=("fp64", "split"), default="fp64")
