@@ -307,3 +307,39 @@ def test_model_planner_finds_a_plan_where_the_papers_rule_does():
             continue
         plan = ooc.ooc_plan(M, N, K, 0.5, budget)
         assert ooc.ooc_plan_footprint(M, N, K, 0.5, plan) <= budget
+
+
+def test_size_sweep_in_core_limit():
+    """The in-core limit of the size sweep is the largest N with 3 * 8 * N^2
+    bytes within the budget: 16384 exactly at 6 GiB (the paper's Xeon Phi
+    threshold, Section VI), 23170 at 12 GiB (the paper's largest in-core size
+    for its 12 GiB GPU is 22528, the last size of its sweep below the limit)."""
+    from paper_1808_05056_amd import size_sweep as S
+    GiB = 1 << 30
+    assert S.in_core_limit(6 * GiB) == 16384
+    assert S.in_core_limit(12 * GiB) == 23170
+    for b in (6 * GiB, 12 * GiB, 192 << 20, 1 << 20):
+        n = S.in_core_limit(b)
+        assert 24 * n * n <= b < 24 * (n + 1) ** 2
+    # the paper's partitioner is in core exactly up to the limit
+    for b in (192 << 20, 6 * GiB):
+        n = S.in_core_limit(b)
+        assert S.is_in_core(ooc.ooc_plan(n, n, n, 0.0, b, ooc.make_opts(planner=ooc.PLAN_PAPER)), n)
+        assert not S.is_in_core(ooc.ooc_plan(n + 1, n + 1, n + 1, 0.0, b, ooc.make_opts(planner=ooc.PLAN_PAPER)), n + 1)
+
+
+def test_planner_sweep_refeature(tmp_path):
+    """Saved timings are re-featured with the current cost model: the features
+    equal those the library computes for the same plans now."""
+    import json
+    from paper_1808_05056_amd import planner_sweep as ps
+    plans, _ = ooc.ooc_plan_candidates(9000, 7000, 5000, 0.0, 1 << 30, ooc.make_opts(precision=ooc.SPLIT_BF16, slices=5))
+    meta = [{"problem": 0, "M": 9000, "N": 7000, "K": 5000, "beta": 0.0, "budget": 1 << 30, "plan": p.as_dict(),
+             "seconds": 0.1 + 0.01 * i} for i, p in enumerate(plans[:5])]
+    path = str(tmp_path / "t.npz")
+    with open(path + ".json", "w") as f:
+        json.dump(meta, f)
+    X, y = ps.refeature(path)
+    assert np.array_equal(X, ooc.ooc_mlp_features(9000, 7000, 5000, 0.0, 1 << 30, plans[:5]))
+    assert np.allclose(y, [r["seconds"] for r in meta])
+    assert np.all(X[:, -1] == 5)  # the slice-count feature
