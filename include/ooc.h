@@ -75,12 +75,20 @@ typedef enum { OOC_PLAN_AUTO = 0, OOC_PLAN_PAPER = 1, OOC_PLAN_MODEL = 2, OOC_PL
 /* Task orders over the grid of C blocks (i: block row, j: block column) and
  * K panels p.  COLS is the paper's order (column by column, Fig. 2).
  * COLS_P keeps a whole block column of C resident and walks K panels outside
- * the block rows, so each B panel is loaded once; ROWS_P is its transpose. */
+ * the block rows, so each B panel is loaded once; ROWS_P is its transpose.
+ * With group g > 0 the _P orders walk groups of g blocks of the column (row)
+ * K panel by K panel.  The _PS orders are the _P orders with every other
+ * column (row) walked backwards: groups, K panels and blocks in reverse, so
+ * it starts with the panels the previous column (row) ended with, which are
+ * still resident (a C block then accumulates its K panels in descending
+ * order). */
 typedef enum {
-  OOC_ORDER_COLS = 0,   /* for j, for i, for p */
-  OOC_ORDER_ROWS = 1,   /* for i, for j, for p */
-  OOC_ORDER_COLS_P = 2, /* for j, for p, for i */
-  OOC_ORDER_ROWS_P = 3  /* for i, for p, for j */
+  OOC_ORDER_COLS = 0,    /* for j, for i, for p */
+  OOC_ORDER_ROWS = 1,    /* for i, for j, for p */
+  OOC_ORDER_COLS_P = 2,  /* for j, for p, for i */
+  OOC_ORDER_ROWS_P = 3,  /* for i, for p, for j */
+  OOC_ORDER_COLS_PS = 4, /* COLS_P, odd block columns backwards */
+  OOC_ORDER_ROWS_PS = 5  /* ROWS_P, odd block rows backwards */
 } ooc_order;
 
 /* A tiling and pipeline plan. */

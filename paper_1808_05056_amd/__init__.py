@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_BUDGET", 3: "ERR_DEVICE_MEM", 4: 
                 6: "ERR_NO_DEVICE", 7: "ERR_INJECTED", 8: "ERR_CAPACITY"}
 FP64, SPLIT_BF16 = 0, 1
 PLAN_AUTO, PLAN_PAPER, PLAN_MODEL, PLAN_MLP = 0, 1, 2, 3
-ORDER_COLS, ORDER_ROWS, ORDER_COLS_P, ORDER_ROWS_P = 0, 1, 2, 3
+ORDER_COLS, ORDER_ROWS, ORDER_COLS_P, ORDER_ROWS_P, ORDER_COLS_PS, ORDER_ROWS_PS = 0, 1, 2, 3, 4, 5
 OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM = range(4)
 OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_gemm"}
 MAX_WAITS = 6

@@ -30,7 +30,7 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
   if (plan.mb <= 0 || plan.nb <= 0) return fail(OOC_ERR_ARG, "plan: mb and nb must be positive");
   if (K > 0 && plan.kb <= 0) return fail(OOC_ERR_ARG, "plan: kb must be positive");
   if (plan.nstreams < 1 || plan.nstreams > 3) return fail(OOC_ERR_ARG, "plan: nstreams must be 1, 2 or 3");
-  if (plan.order < 0 || plan.order > 3) return fail(OOC_ERR_ARG, "plan: unknown order");
+  if (plan.order < 0 || plan.order > 5) return fail(OOC_ERR_ARG, "plan: unknown order");
   if (plan.nbuf_c < 1 || (K > 0 && (plan.nbuf_a < 1 || plan.nbuf_b < 1)))
     return fail(OOC_ERR_ARG, "plan: every operand needs at least one buffer");
   if (plan.precision != OOC_FP64 && plan.precision != OOC_SPLIT_BF16)
@@ -351,15 +351,20 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
     switch (p.order) {
       case OOC_ORDER_COLS: a_loads = (p.nbuf_a >= h * P) ? 1 : (double)w; b_loads = (P == 1 || p.nbuf_b >= P) ? 1 : (double)h; break;
       case OOC_ORDER_ROWS: b_loads = (p.nbuf_b >= w * P) ? 1 : (double)h; a_loads = (P == 1 || p.nbuf_a >= P) ? 1 : (double)w; break;
-      case OOC_ORDER_COLS_P: {
+      case OOC_ORDER_COLS_P:
+      case OOC_ORDER_COLS_PS: {
         const int64_t gs = p.group > 0 ? std::min<int64_t>(p.group, h) : h;
         a_loads = (double)w;
+        // a backwards column reuses at most a group's panels of one K panel
+        if (p.order == OOC_ORDER_COLS_PS) a_loads -= (double)(w - 1) * gs / ((double)P * h);
         b_loads = (P == 1 || p.nbuf_b >= P) ? 1 : (double)ceil_div(h, gs);
         break;
       }
-      case OOC_ORDER_ROWS_P: {
+      case OOC_ORDER_ROWS_P:
+      case OOC_ORDER_ROWS_PS: {
         const int64_t gs = p.group > 0 ? std::min<int64_t>(p.group, w) : w;
         b_loads = (double)h;
+        if (p.order == OOC_ORDER_ROWS_PS) b_loads -= (double)(h - 1) * gs / ((double)P * w);
         a_loads = (P == 1 || p.nbuf_a >= P) ? 1 : (double)ceil_div(w, gs);
         break;
       }
@@ -502,6 +507,25 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
     if (simt[c] >= 0) sim.push_back({simt[c], cands[c].p});
   if (sim.empty()) return fail(OOC_ERR_BUDGET, "no schedulable plan fits in the device budget");
   std::stable_sort(sim.begin(), sim.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  // the best _P plans walked backwards in every other row (column) as well:
+  // the next row starts with the panels the last one ended with
+  {
+    std::vector<std::pair<double, ooc_plan_t>> more;
+    size_t tried = 0;
+    for (size_t c = 0; c < sim.size() && tried < 16; ++c) {
+      ooc_plan_t q = sim[c].second;
+      if (q.order != OOC_ORDER_COLS_P && q.order != OOC_ORDER_ROWS_P) continue;
+      ++tried;
+      q.order = q.order == OOC_ORDER_COLS_P ? OOC_ORDER_COLS_PS : OOC_ORDER_ROWS_PS;
+      Layout lay;
+      if (plan_layout(pb, q, &lay) != OOC_OK) continue;
+      std::vector<ooc_op> ops;
+      if (build_schedule(pb, q, lay, &ops) != OOC_OK) continue;
+      more.push_back({simulate(pb, q, ops), q});
+    }
+    sim.insert(sim.end(), more.begin(), more.end());
+    std::stable_sort(sim.begin(), sim.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  }
   for (auto& s : sim) {
     plans->push_back(s.second);
     times->push_back(s.first);

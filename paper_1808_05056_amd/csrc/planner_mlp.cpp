@@ -125,7 +125,10 @@ void plan_features(const Problem& pb, uint64_t budget, const ooc_plan_t& p, doub
   f[x++] = (float)log2p((double)std::min<int64_t>(p.mb, pb.M));
   f[x++] = (float)log2p((double)std::min<int64_t>(p.nb, pb.N));
   f[x++] = (float)log2p((double)std::min<int64_t>(p.kb, pb.K) + 1);
-  for (int o = 0; o < 4; ++o) f[x++] = p.order == o ? 1.f : 0.f;
+  // the backwards-alternating orders share their base order's indicator (the
+  // cost model's prediction, also a feature, tells them apart)
+  const int base = p.order == OOC_ORDER_COLS_PS ? OOC_ORDER_COLS_P : (p.order == OOC_ORDER_ROWS_PS ? OOC_ORDER_ROWS_P : p.order);
+  for (int o = 0; o < 4; ++o) f[x++] = base == o ? 1.f : 0.f;
   f[x++] = (float)p.nbuf_a;
   f[x++] = (float)p.nbuf_b;
   f[x++] = (float)log2p((double)p.nbuf_c);

@@ -13,6 +13,7 @@
 // by columns, K not split, A and C double-buffered, B single-buffered, two
 // streams by block parity) this reproduces the paper's ordering.
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <map>
 #include <set>
@@ -34,14 +35,17 @@ struct Pool {
   int n = 0;
   std::vector<int64_t> key;       // content key per buffer (-1: empty)
   std::vector<int64_t> last_use;  // task index of the last use
-  std::vector<int> last_reader;   // op index of the last kernel that read the buffer
+  // op index of the last kernel on each stream that read the buffer's content
+  // (a load into the buffer waits for all of them: with kernels on two
+  // streams, the last reader's completion does not imply the other's)
+  std::vector<std::array<int, 3>> readers;
   std::vector<int> load_op;       // op index that loaded the current content
   std::vector<int64_t> next_use;  // task index of the content's next use (INT64_MAX: none)
   void init(int nb) {
     n = nb;
     key.assign(nb, -1);
     last_use.assign(nb, -1);
-    last_reader.assign(nb, -1);
+    readers.assign(nb, {-1, -1, -1});
     load_op.assign(nb, -1);
     next_use.assign(nb, INT64_MAX);
   }
@@ -73,7 +77,10 @@ struct Pool {
 
 // Tasks in walk order.  The _P orders walk groups of g C blocks of a block
 // column (row) K panel by K panel, the blocks of a group inside; g = 0 means
-// the whole column (row).
+// the whole column (row).  The _PS orders walk every other column (row)
+// backwards (groups, K panels and blocks in reverse), so a column (row) starts
+// with the group, the K panel and the block the previous one ended with, whose
+// B (A) panels are still resident.
 std::vector<Task> make_tasks(int order, int64_t h, int64_t w, int64_t P, int64_t g) {
   std::vector<Task> t;
   t.reserve((size_t)(h * w * P));
@@ -88,20 +95,29 @@ std::vector<Task> make_tasks(int order, int64_t h, int64_t w, int64_t P, int64_t
         for (int64_t j = 0; j < w; ++j)
           for (int64_t p = 0; p < P; ++p) t.push_back({i, j, p});
       break;
-    case OOC_ORDER_COLS_P: {
-      const int64_t gs = g > 0 ? std::min(g, h) : h;
-      for (int64_t j = 0; j < w; ++j)
-        for (int64_t i0 = 0; i0 < h; i0 += gs)
-          for (int64_t p = 0; p < P; ++p)
-            for (int64_t i = i0; i < std::min(h, i0 + gs); ++i) t.push_back({i, j, p});
-      break;
-    }
-    case OOC_ORDER_ROWS_P: {
-      const int64_t gs = g > 0 ? std::min(g, w) : w;
-      for (int64_t i = 0; i < h; ++i)
-        for (int64_t j0 = 0; j0 < w; j0 += gs)
-          for (int64_t p = 0; p < P; ++p)
-            for (int64_t j = j0; j < std::min(w, j0 + gs); ++j) t.push_back({i, j, p});
+    case OOC_ORDER_COLS_P:
+    case OOC_ORDER_COLS_PS:
+    case OOC_ORDER_ROWS_P:
+    case OOC_ORDER_ROWS_PS: {
+      // outer: block columns (COLS) or rows (ROWS); inner: the other index
+      const bool cols = order == OOC_ORDER_COLS_P || order == OOC_ORDER_COLS_PS;
+      const bool serp = order == OOC_ORDER_COLS_PS || order == OOC_ORDER_ROWS_PS;
+      const int64_t no = cols ? w : h, ni = cols ? h : w;
+      const int64_t gs = g > 0 ? std::min(g, ni) : ni;
+      const int64_t ng = ceil_div(ni, gs);
+      for (int64_t o = 0; o < no; ++o) {
+        const bool rev = serp && (o & 1);
+        for (int64_t gg = 0; gg < ng; ++gg) {
+          const int64_t g0 = (rev ? ng - 1 - gg : gg) * gs, g1 = std::min(ni, g0 + gs);
+          for (int64_t pp = 0; pp < P; ++pp) {
+            const int64_t p = rev ? P - 1 - pp : pp;
+            for (int64_t x = 0; x < g1 - g0; ++x) {
+              const int64_t in = rev ? g1 - 1 - x : g0 + x;
+              t.push_back(cols ? Task{in, o, p} : Task{o, in, p});
+            }
+          }
+        }
+      }
       break;
     }
   }
@@ -145,6 +161,21 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     kbk[t] = tasks[t].p * w + tasks[t].j;
   }
   std::vector<int64_t> nxa = next_uses(ka), nxb = next_uses(kbk);
+  // a C block opens at its first task and goes home after its last (the _PS
+  // orders walk K panels backwards in every other row or column)
+  std::vector<char> opens(T, 0), closes(T, 0);
+  {
+    std::vector<int64_t> first(h * w, -1), last(h * w, -1);
+    for (int64_t t = 0; t < T; ++t) {
+      const int64_t ck = tasks[t].i * w + tasks[t].j;
+      if (first[ck] < 0) first[ck] = t;
+      last[ck] = t;
+    }
+    for (int64_t c = 0; c < h * w; ++c) {
+      opens[first[c]] = 1;
+      closes[last[c]] = 1;
+    }
+  }
 
   Pool pa, pbf, pd;
   pa.init(K > 0 ? plan.nbuf_a : 0);
@@ -161,8 +192,8 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
   };
   auto fold_panel = [&](const Task& tk) -> int64_t {
     if (!staged || P == 1) return 0;
-    if (plan.order == OOC_ORDER_COLS_P) return spread(tk.i, h);
-    if (plan.order == OOC_ORDER_ROWS_P) return spread(tk.j, w);
+    if (plan.order == OOC_ORDER_COLS_P || plan.order == OOC_ORDER_COLS_PS) return spread(tk.i, h);
+    if (plan.order == OOC_ORDER_ROWS_P || plan.order == OOC_ORDER_ROWS_PS) return spread(tk.j, w);
     return P - 1;
   };
   // C bookkeeping: block key -> buffer, the op that last wrote it
@@ -206,7 +237,12 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     const int64_t k0 = tk.p * kb, k = K > 0 ? std::min(kb, K - k0) : 0;
     int sa = -1, sb = -1;
     // loads this task needs, issued in the order their buffers become free
-    struct Load { ooc_op op; int war; int* load_op_slot; };
+    struct Load {
+      ooc_op op;
+      std::array<int, 3> war;  // kernels that read the buffer's old content
+      int* load_op_slot;
+      int last() const { return std::max(war[0], std::max(war[1], war[2])); }
+    };
     std::vector<Load> loads;
     int c_load_placeholder = -1;
     if (K > 0) {
@@ -219,7 +255,8 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
         op.slot = sa;
         op.row0 = i0; op.col0 = k0; op.rows = m; op.cols = k;
         op.off_c = lay.offA + sa * lay.slotA; op.ld_c = k;
-        loads.push_back({op, pa.last_reader[sa], &pa.load_op[sa]});
+        loads.push_back({op, pa.readers[sa], &pa.load_op[sa]});
+        pa.readers[sa] = {-1, -1, -1};
         pa.key[sa] = ka[t];
       }
       pa.last_use[sa] = t;
@@ -233,7 +270,8 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
         op.slot = sb;
         op.row0 = k0; op.col0 = j0; op.rows = k; op.cols = n;
         op.off_c = lay.offB + sb * lay.slotB; op.ld_c = n;
-        loads.push_back({op, pbf.last_reader[sb], &pbf.load_op[sb]});
+        loads.push_back({op, pbf.readers[sb], &pbf.load_op[sb]});
+        pbf.readers[sb] = {-1, -1, -1};
         pbf.key[sb] = kbk[t];
       }
       pbf.last_use[sb] = t;
@@ -245,7 +283,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     for (int s = 0; s < plan.nbuf_c; ++s)
       if (c_block[s] == ckey) sc = s;
     int c_dep = -1;
-    if (tk.p == 0) {
+    if (opens[t]) {
       if (sc >= 0) return fail(OOC_ERR_ARG, "schedule: C block opened twice");
       for (int s = 0; s < plan.nbuf_c; ++s) {
         if (c_block[s] >= 0) continue;
@@ -262,7 +300,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
         op.slot = sc;
         op.row0 = i0; op.col0 = j0; op.rows = m; op.cols = n;
         op.off_c = lay.offC + sc * lay.slotC; op.ld_c = n;
-        loads.push_back({op, c_close[sc], &c_load_placeholder});
+        loads.push_back({op, {c_close[sc], -1, -1}, &c_load_placeholder});
       }
     } else {
       if (sc < 0) return fail(OOC_ERR_ARG, "schedule: C block not open");
@@ -278,13 +316,14 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
       op.slot = -1 - sd;
       op.row0 = i0; op.col0 = j0; op.rows = m; op.cols = n;
       op.off_c = lay.offD + sd * lay.slotD; op.ld_c = n;
-      loads.push_back({op, pd.last_reader[sd], &pd.load_op[sd]});
+      loads.push_back({op, pd.readers[sd], &pd.load_op[sd]});
+      pd.readers[sd] = {-1, -1, -1};
       pd.key[sd] = ckey;
       pd.last_use[sd] = t;
     }
-    std::stable_sort(loads.begin(), loads.end(), [](const Load& a, const Load& b) { return a.war < b.war; });
+    std::stable_sort(loads.begin(), loads.end(), [](const Load& a, const Load& b) { return a.last() < b.last(); });
     for (Load& L : loads) {
-      int x = push(L.op, {L.war});
+      int x = push(L.op, {L.war[0], L.war[1], L.war[2]});
       if (x < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
       *L.load_op_slot = x;
     }
@@ -301,7 +340,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     g.off_c = lay.offC + sc * lay.slotC; g.ld_c = n;
     g.off_w = lay.offW; g.len_w = lay.lenW;
     g.alpha = pb.alpha;
-    g.beta = tk.p == 0 ? (staged ? 0.0 : pb.beta) : 1.0;
+    g.beta = opens[t] ? (staged ? 0.0 : pb.beta) : 1.0;
     g.gamma = 0.0;
     if (fold_here) {
       g.off_d = lay.offD + sd * lay.slotD;
@@ -319,13 +358,13 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     if (split) last_ws = gx;
     if (gx < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
     if (K > 0) {
-      pa.last_reader[sa] = gx;
-      pbf.last_reader[sb] = gx;
+      pa.readers[sa][ops[gx].stream] = gx;
+      pbf.readers[sb][ops[gx].stream] = gx;
     }
-    if (fold_here) pd.last_reader[sd] = gx;
+    if (fold_here) pd.readers[sd][ops[gx].stream] = gx;
     c_last_writer[sc] = gx;
     // C block home after its last panel
-    if (tk.p == P - 1) {
+    if (closes[t]) {
       ooc_op op = blank(OOC_OP_D2H, t);
       op.mat = 2;
       op.slot = sc;

@@ -80,6 +80,12 @@ PLANS = [
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 5, 2, 3, 2, group=2)),
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 4, 3, 3, nbuf_d=1, group=2)),
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 3, 2, 3, nbuf_d=2, group=2)),
+    # every other row (column) walked backwards
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_PS, 4, 2, 4, 3, group=3)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_PS, 3, 2, 5, 3)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_PS, 2, 4, 3, 3, nbuf_d=1, group=2)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_PS, 2, 2, 5, 2, nbuf_d=1)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_PS, 5, 2, 3, 1, group=2)),
 ]
 
 
@@ -99,6 +105,33 @@ def test_group_walk_order():
         assert walk[:16] == [(0, j, p) for p in range(4) for j in range(4)]
     with pytest.raises(ooc.OOCError):
         ooc.ooc_schedule(41, 37, 29, 1.0, 0.0, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_P, 4, 2, 4, 3, group=-1))
+
+
+def test_backwards_alternating_walk_order():
+    # ROWS_PS: row 0 as ROWS_P; row 1 backwards (last group first, K panels and
+    # blocks in reverse), so it starts with the group, panel and block row 0 ended with
+    plan = ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_PS, 4, 2, 4, 3, group=3)
+    ops, _ = ooc.ooc_schedule(41, 37, 29, 1.0, 0.0, plan)
+    walk = [(op["i0"] // 9, op["j0"] // 10, op["k0"] // 8) for op in ops if op["kind"] == "gemm"]
+    row0 = [(0, j, p) for p in range(4) for j in range(3)] + [(0, 3, p) for p in range(4)]
+    row1 = [(1, 3, p) for p in (3, 2, 1, 0)] + [(1, j, p) for p in (3, 2, 1, 0) for j in (2, 1, 0)]
+    assert walk[:32] == row0 + row1
+    assert walk[32:48] == [(2, j, p) for p in range(4) for j in range(3)] + [(2, 3, p) for p in range(4)]
+    assert sorted(walk) == sorted((i, j, p) for i in range(5) for j in range(4) for p in range(4))
+    # COLS_PS is its transpose
+    plan = ooc.make_plan(10, 9, 8, ooc.ORDER_COLS_PS, 2, 4, 4, 3, group=3)
+    ops, _ = ooc.ooc_schedule(37, 41, 29, 1.0, 0.0, plan)
+    walk = [(op["i0"] // 10, op["j0"] // 9, op["k0"] // 8) for op in ops if op["kind"] == "gemm"]
+    assert walk[:32] == [(j, i, p) for (i, j, p) in row0 + row1]
+    # a C block that accumulates its K panels backwards reads C once, at its first panel
+    ops, _ = ooc.ooc_schedule(41, 37, 29, 1.0, 0.5, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_PS, 4, 2, 4, 3, group=3))
+    first = {}
+    for op in ops:
+        if op["kind"] == "gemm":
+            key = (op["i0"], op["j0"])
+            assert (op["beta"] == 0.5) == (key not in first)
+            first.setdefault(key, op["k0"])
+    assert first[(9, 30)] == 24  # row 1 starts block (1, 3) at the last K panel
 
 
 def test_copies_in_order_of_free_buffers():
@@ -211,6 +244,7 @@ SPLIT_PLANS = [
     (41, 37, 29, ooc.make_plan(9, 10, 29, ooc.ORDER_COLS, 2, 1, 2, 2, precision=ooc.SPLIT_BF16, slices=3)),
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_COLS_P, 2, 2, 5, 2, precision=ooc.SPLIT_BF16, slices=2, nbuf_d=1)),
     (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=1)),
+    (41, 37, 29, ooc.make_plan(9, 10, 8, ooc.ORDER_ROWS_PS, 4, 2, 4, 2, precision=ooc.SPLIT_BF16, slices=2, group=3)),
 ]
 
 

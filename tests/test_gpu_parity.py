@@ -87,6 +87,8 @@ SMALL_PLANS = [
     ("rows-ksplit-staged", ooc.make_plan(384, 256, 320, ooc.ORDER_ROWS, 2, 2, 2, 3, nbuf_d=1), None),
     ("rowsp-group2", ooc.make_plan(256, 256, 256, ooc.ORDER_ROWS_P, 4, 2, 3, 3, group=2), None),
     ("colsp-group3-staged", ooc.make_plan(256, 256, 256, ooc.ORDER_COLS_P, 2, 4, 3, 3, nbuf_d=1, group=3), None),
+    ("rowsps-group3", ooc.make_plan(256, 256, 256, ooc.ORDER_ROWS_PS, 4, 3, 4, 3, group=3), None),
+    ("colsps-staged", ooc.make_plan(256, 256, 256, ooc.ORDER_COLS_PS, 2, 2, 4, 3, nbuf_d=1), None),
 ]
 
 
