@@ -7,9 +7,9 @@
 // (kb) form a grid of tile tasks walked in a chosen order; each operand has a
 // pool of device buffers; a panel stays resident until its buffer is needed
 // again (a buffer whose content has no later use goes first, then the least
-// recently used), and every reuse of a buffer waits for the last operation
-// that read its old content.  A C block occupies a buffer from its first K
-// panel until it is back on the host.  With the paper's configuration (order
+// recently used), and every reuse of a buffer waits for the last operation on
+// each stream that read its old content.  A C block occupies a buffer from
+// its first task until it is back on the host.  With the paper's configuration (order
 // by columns, K not split, A and C double-buffered, B single-buffered, two
 // streams by block parity) this reproduces the paper's ordering.
 #include <algorithm>
