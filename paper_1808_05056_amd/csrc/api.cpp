@@ -10,6 +10,7 @@
 // for it.  The call returns after every stream has drained.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
@@ -130,7 +131,8 @@ struct HostMats {
 };
 
 ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>& ops, double* arena,
-                   const HostMats& hm, bool profile, double* timeline, int64_t timeline_cap, ooc_stats* st) {
+                   int64_t arena_elems, const HostMats& hm, bool profile, double* timeline, int64_t timeline_cap,
+                   ooc_stats* st) {
   const size_t n = ops.size();
   std::vector<int> evidx(n, -1);
   size_t nev = 0;
@@ -144,6 +146,24 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
     if (s0 != OOC_OK) return s0;
   }
   const int fail_at = env_int("OOC_FAIL_AT", -1);
+  // Race testing (OOC_STRESS_SEED >= 0): the arena starts as NaN, and before
+  // a third of the operations (chosen by the seed) a wait of up to
+  // OOC_STRESS_US microseconds is enqueued on the operation's stream, after
+  // its waits.  A correct operation list gives bit-identical results.
+  const int stress_seed = env_int("OOC_STRESS_SEED", -1);
+  const int stress_us = std::max(0, std::min(env_int("OOC_STRESS_US", 300), 5000));
+  uint64_t rng = 0x9E3779B97F4A7C15ull * (uint64_t)(stress_seed + 2);
+  auto next_rand = [&]() {
+    rng ^= rng << 13;
+    rng ^= rng >> 7;
+    rng ^= rng << 17;
+    return rng;
+  };
+  if (stress_seed >= 0) {
+    hipError_t e = launch_fill_nan(arena, arena_elems, c.st[0]);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.st[0]);
+    if (e != hipSuccess) return hip_fail(e, "poisoning the arena");
+  }
   ooc_status status = OOC_OK;
   std::string msg;
   int64_t d2h_issued = 0;
@@ -159,6 +179,8 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
     hipStream_t s = c.st[o.stream];
     hipError_t e = hipSuccess;
     for (int k = 0; k < o.nwait && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, c.ev[evidx[o.wait[k]]], 0);
+    if (e == hipSuccess && stress_seed >= 0 && next_rand() % 3 == 0)
+      e = launch_spin((uint32_t)(next_rand() % (uint64_t)(stress_us + 1)), s);
     if (e == hipSuccess && profile) e = hipEventRecord(c.tev[2 * x], s);
     if (e == hipSuccess) {
       switch (o.kind) {
@@ -332,8 +354,8 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
     arena = static_cast<double*>(c.arena);
   }
   HostMats hm{A, lda, B, ldb, C, ldc};
-  st = run_ops(c, plan, ops, arena, hm, opts && opts->profile, opts ? opts->timeline : nullptr,
-               opts ? opts->timeline_cap : 0, stats);
+  st = run_ops(c, plan, ops, arena, (int64_t)(lay.bytes / 8), hm, opts && opts->profile,
+               opts ? opts->timeline : nullptr, opts ? opts->timeline_cap : 0, stats);
   if (stats) {
     stats->plan = plan;
     stats->t_total_s = now_s() - t_enter;

@@ -38,4 +38,9 @@ hipError_t launch_adam(int64_t count, float* p, const float* g, float* m, float*
 // Device-to-device copy kernel (bytes and pointers multiples of 16).
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// Race testing (stress.hip): a wait of about `microseconds` (at most 5000) on
+// the stream, and a NaN fill of n doubles.
+hipError_t launch_spin(uint32_t microseconds, hipStream_t s);
+hipError_t launch_fill_nan(double* x, int64_t n, hipStream_t s);
+
 }  // namespace ooc

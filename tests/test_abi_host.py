@@ -305,6 +305,13 @@ def test_gpu_test_plans_fit_their_budgets():
                 assert ooc.ooc_plan_footprint(1024, 1024, 1024, beta, plan) <= 8 << 20, name
     split_plan = ooc.make_plan(256, 320, 320, ooc.ORDER_COLS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
     assert ooc.ooc_plan_footprint(1000, 900, 1100, 0.5, split_plan) <= 8 << 20
+    # the race-stress plans fit their 6 MiB budget and pass the CPU hazard checker
+    import test_gpu_race_stress
+    for name, plan, _ in test_gpu_race_stress.PLANS:
+        if plan is not None:
+            assert ooc.ooc_plan_footprint(1024, 768, 640, 0.5, plan) <= 6 << 20, name
+            ops, _ = ooc.ooc_schedule(1024, 768, 640, 1.5, 0.5, plan)
+            assert sched_ref.check_hazards(ops) == [], name
 
 
 DEGENERATE = [
