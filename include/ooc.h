@@ -150,7 +150,12 @@ typedef struct {
  * cached for the next call on the device until ooc_release().
  * Errors: OOC_ERR_ARG (negative sizes, ld too small, NULL operand with a
  * nonzero extent), OOC_ERR_BUDGET (nothing fits), OOC_ERR_DEVICE_MEM,
- * OOC_ERR_NOT_PINNED, OOC_ERR_NO_DEVICE, OOC_ERR_HIP. */
+ * OOC_ERR_NOT_PINNED, OOC_ERR_NO_DEVICE, OOC_ERR_HIP.
+ * Test hooks read from the environment at each call: OOC_FAIL_AT=n stops
+ * issuing at operation n (OOC_ERR_INJECTED after draining the streams);
+ * OOC_STRESS_SEED=s fills the device buffers with NaN first and, chosen by
+ * the seed, enqueues a wait of up to OOC_STRESS_US microseconds (default 300,
+ * at most 5000) before a third of the operations on their streams. */
 ooc_status ooc_gemm(int64_t M, int64_t N, int64_t K, double alpha,
                     const double* A, int64_t lda, const double* B, int64_t ldb,
                     double beta, double* C, int64_t ldc, size_t budget_bytes,
