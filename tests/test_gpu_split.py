@@ -126,3 +126,36 @@ def test_split_pipeline_model_planner_staged():
         assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
     finally:
         pp.free()
+
+
+@pytest.mark.parametrize("case", ["ld-padded", "alpha-zero", "k-zero", "beta-zero-nan-c"])
+def test_split_pipeline_edge_cases(case):
+    """The split path through the pipeline: host leading dimensions wider than
+    the rows, alpha = 0 and K = 0 (C = beta*C, A and B unread), and beta = 0
+    with C full of NaN (C unread)."""
+    alpha = 0.0 if case == "alpha-zero" else 1.25
+    beta = 0.0 if case == "beta-zero-nan-c" else 0.5
+    w = W.Workload("split-edge", 600, 500, 700, alpha, beta, 6 * MiB, seed=23, dist_a=synth.NORMAL,
+                   dist_b=synth.NORMAL, a_row_exp=(-10, 10), b_col_exp=(-10, 10))
+    pp = PinnedProblem(w, ld_pad=(5, 3, 7) if case == "ld-padded" else (0, 0, 0),
+                       nan_c=case == "beta-zero-nan-c")
+    try:
+        C0 = pp.C.copy()
+        if case == "alpha-zero":
+            synth.fill_nan(pp.A)  # A is not read
+        A, B = (pp.A[:, :0], pp.B[:0, :]) if case == "k-zero" else (pp.A, pp.B)
+        plan = ooc.make_plan(256, 192, 320, ooc.ORDER_ROWS, 2, 2, 2, 3, precision=ooc.SPLIT_BF16, slices=6)
+        _, stats = ooc.ooc_gemm_planned(w.alpha, A, B, w.beta, pp.C, w.budget, plan)
+        assert stats.arena_bytes <= w.budget
+        _say(f"split edge case {case}: plan {stats.plan}")
+        if case in ("alpha-zero", "k-zero"):
+            assert np.array_equal(pp.C, beta * C0)
+            return
+        Cin = None if beta == 0.0 else C0
+        want = split_ref.split_gemm(alpha, np.array(pp.A), np.array(pp.B), beta,
+                                    np.zeros_like(C0) if Cin is None else Cin, 6, kb=320)
+        assert np.array_equal(pp.C, want)
+        ref, D = oracle.gemm_rows(alpha, np.array(pp.A), np.array(pp.B), beta, Cin)
+        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(alpha, D, beta, Cin)) <= oracle.GATE
+    finally:
+        pp.free()
