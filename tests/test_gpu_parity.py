@@ -34,6 +34,9 @@ KERNEL_CASES = [
     (300, 200, 1000, 6, 2, 4, 0.75, -1.0, synth.NORMAL),  # padded leading dims
     (1024, 1024, 2048, 0, 0, 0, 1.0, 0.0, synth.NORMAL),
     (64, 64, 0, 0, 0, 0, 1.0, 0.5, synth.UNIFORM),        # k = 0: C = beta*C
+    # tile counts that leave remainders in the XCD bands and the row groups
+    (1100, 1500, 96, 0, 0, 0, 1.0, 0.0, synth.INT),       # 9 x 12 = 108 tiles
+    (2900, 2100, 300, 2, 0, 6, 0.5, 2.0, synth.INT),      # 23 x 17 = 391 tiles, more than two per CU
 ]
 
 
