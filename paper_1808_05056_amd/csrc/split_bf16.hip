@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -52,9 +53,28 @@ __device__ inline int32_t exponent_of(double mx) {
   return ex;
 }
 
-// One wave per row of A: exponent, then s slices of the row into the planes.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// The S slices of r (exponent e) as BF16 bit patterns: m_p = rint(r 2^(8p-e)),
+// r -= m_p 2^(e-8p), each step exact.
+template <int S>
+__device__ __forceinline__ void slices_of(double r, int32_t e, uint32_t (&bits)[S]) {
+#pragma unroll
+  for (int p = 1; p <= S; ++p) {
+    double mp = 0.0;
+    if (r != 0.0) {
+      mp = rint(ldexp(r, 8 * p - e));
+      r = r - ldexp(mp, e - 8 * p);
+    }
+    bits[p - 1] = bf16_bits_exact(mp);
+  }
+}
+
+// One wave per row of A: exponent, then the S slices of the row into the
+// planes, 8 consecutive k per lane and step (one 16-byte store per plane).
+template <int S>
 __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const double* __restrict__ A, int64_t lda,
-                                                  int s, int64_t mpad, int64_t kpad, uint16_t* __restrict__ planes,
+                                                  int64_t mpad, int64_t kpad, uint16_t* __restrict__ planes,
                                                   int32_t* __restrict__ ex_out) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -75,16 +95,25 @@ __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const do
   }
   const int32_t ex = bad ? kBad : exponent_of(mx);
   if (lane == 0) ex_out[row] = ex;
-  for (int64_t kk = lane; kk < kpad; kk += 64) {
-    double r = (live && !bad && kk < k) ? A[row * lda + kk] : 0.0;
-    for (int p = 1; p <= s; ++p) {
-      double mp = 0.0;
-      if (r != 0.0) {
-        mp = rint(ldexp(r, 8 * p - ex));
-        r = r - ldexp(mp, ex - 8 * p);
-      }
-      planes[((int64_t)(p - 1) * mpad + row) * kpad + kk] = bf16_bits_exact(mp);
+  // kpad is a multiple of 64, so a lane's 8 values never cross it
+  for (int64_t k8 = (int64_t)lane * 8; k8 < kpad; k8 += 512) {
+    uint32_t w[S][4];
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) w[p][x] = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t kk = k8 + q;
+      const double r = (live && !bad && kk < k) ? A[row * lda + kk] : 0.0;
+      uint32_t b[S];
+      slices_of<S>(r, ex, b);
+#pragma unroll
+      for (int p = 0; p < S; ++p) w[p][q >> 1] |= b[p] << (16 * (q & 1));
     }
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+      *reinterpret_cast<u32x4*>(planes + ((int64_t)p * mpad + row) * kpad + k8) = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
   }
 }
 
@@ -118,9 +147,12 @@ __global__ __launch_bounds__(256) void col_exponents(int64_t npad, const unsigne
   ex_out[j] = bits >= 0x7ff0000000000000ull ? kBad : exponent_of(__longlong_as_double((long long)bits));
 }
 
-// Slices of B into transposed planes [p][j][k]: a 64 (k) x 64 (j) tile per workgroup.
+// Slices of B into transposed planes [p][j][k]: a 64 (k) x 64 (j) tile per
+// workgroup; each thread slices 16 consecutive k of one column and stores them
+// as two 16-byte vectors per plane.
+template <int S>
 __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const double* __restrict__ B, int64_t ldb,
-                                                  int s, int64_t npad, int64_t kpad, const int32_t* __restrict__ ex,
+                                                  int64_t npad, int64_t kpad, const int32_t* __restrict__ ex,
                                                   uint16_t* __restrict__ planes) {
   __shared__ double tile[64][65];
   const int t = threadIdx.x;
@@ -135,17 +167,24 @@ __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const do
   const int jl = t >> 2, ks = (t & 3) * 16;
   const int64_t j = j0 + jl;
   const int32_t e = ex[j];
+  uint32_t w[S][8];
+#pragma unroll
+  for (int p = 0; p < S; ++p)
+#pragma unroll
+    for (int x = 0; x < 8; ++x) w[p][x] = 0;
+#pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const int kl = ks + q;
-    double r = (e == kBad) ? 0.0 : tile[jl][kl];
-    for (int p = 1; p <= s; ++p) {
-      double mp = 0.0;
-      if (r != 0.0) {
-        mp = rint(ldexp(r, 8 * p - e));
-        r = r - ldexp(mp, e - 8 * p);
-      }
-      planes[((int64_t)(p - 1) * npad + j) * kpad + k0 + kl] = bf16_bits_exact(mp);
-    }
+    const double r = (e == kBad) ? 0.0 : tile[jl][ks + q];
+    uint32_t b[S];
+    slices_of<S>(r, e, b);
+#pragma unroll
+    for (int p = 0; p < S; ++p) w[p][q >> 1] |= b[p] << (16 * (q & 1));
+  }
+#pragma unroll
+  for (int p = 0; p < S; ++p) {
+    u32x4* dst = reinterpret_cast<u32x4*>(planes + ((int64_t)p * npad + j) * kpad + k0 + ks);
+    dst[0] = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
+    dst[1] = u32x4{w[p][4], w[p][5], w[p][6], w[p][7]};
   }
 }
 
@@ -395,14 +434,32 @@ static hipError_t split_panel(int64_t m, int64_t n, int64_t k, int s, double alp
   unsigned long long* bmax = reinterpret_cast<unsigned long long*>(fb + np);  // 8-byte aligned: mp, np even
   double* Sws = reinterpret_cast<double*>(bmax + np);
   if (gamma == 0.0) D = nullptr;
-  hipLaunchKernelGGL(split_rows, dim3((unsigned)(mp / 4)), dim3(256), 0, stream, m, k, A, lda, s, mp, kp, Ap, ea);
+  const dim3 rows_grid((unsigned)(mp / 4)), cols_grid((unsigned)(kp / 64), (unsigned)(np / 64));
+  auto slice_a = [&](auto S) {
+    hipLaunchKernelGGL(split_rows<decltype(S)::value>, rows_grid, dim3(256), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
+  };
+  auto slice_b = [&](auto S) {
+    hipLaunchKernelGGL(split_cols<decltype(S)::value>, cols_grid, dim3(256), 0, stream, k, n, B, ldb, np, kp, fb, Bp);
+  };
+  auto with_s = [&](auto f) {
+    switch (s) {
+      case 1: f(std::integral_constant<int, 1>{}); break;
+      case 2: f(std::integral_constant<int, 2>{}); break;
+      case 3: f(std::integral_constant<int, 3>{}); break;
+      case 4: f(std::integral_constant<int, 4>{}); break;
+      case 5: f(std::integral_constant<int, 5>{}); break;
+      case 6: f(std::integral_constant<int, 6>{}); break;
+      case 7: f(std::integral_constant<int, 7>{}); break;
+      default: f(std::integral_constant<int, 8>{}); break;
+    }
+  };
+  with_s(slice_a);
   hipLaunchKernelGGL(zero_u64, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream,
                      reinterpret_cast<uint64_t*>(bmax), np);
   hipLaunchKernelGGL(col_absmax, dim3((unsigned)((n + 255) / 256), (unsigned)((k + 255) / 256)), dim3(256), 0, stream,
                      k, n, B, ldb, bmax);
   hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
-  hipLaunchKernelGGL(split_cols, dim3((unsigned)(kp / 64), (unsigned)(np / 64)), dim3(256), 0, stream, k, n, B, ldb, s,
-                     np, kp, fb, Bp);
+  with_s(slice_b);
   hipLaunchKernelGGL(split_gemm, dim3((unsigned)(np / SBN), (unsigned)(mp / SBM)), dim3(256), 0, stream, m, n, kp, s,
                      Ap, Bp, mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
   return hipGetLastError();
