@@ -284,7 +284,8 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
 #define OOC_MLP_FEATURES 19
 
 /* Features of candidate plans: X_out receives n x OOC_MLP_FEATURES floats
- * (log2 of M, N, K+1, budget, mb, nb, kb+1; order one-hot (4); nbuf_a, nbuf_b,
+ * (log2 of M, N, K+1, budget, mb, nb, kb+1; order one-hot (4; COLS_PS and
+ * ROWS_PS set the COLS_P and ROWS_P entries); nbuf_a, nbuf_b,
  * log2 nbuf_c, nbuf_d, nstreams; log2 of the cost model's time and of the H2D
  * bytes; split slices or 0).  Host only. */
 ooc_status ooc_mlp_features(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes,
