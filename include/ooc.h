@@ -151,6 +151,8 @@ typedef struct {
  * Errors: OOC_ERR_ARG (negative sizes, ld too small, NULL operand with a
  * nonzero extent), OOC_ERR_BUDGET (nothing fits), OOC_ERR_DEVICE_MEM,
  * OOC_ERR_NOT_PINNED, OOC_ERR_NO_DEVICE, OOC_ERR_HIP.
+ * OOC_LOG=1 in the environment prints one line per call on stderr (problem,
+ * plan, times, status).
  * Test hooks read from the environment at each call: OOC_FAIL_AT=n stops
  * issuing at operation n (OOC_ERR_INJECTED after draining the streams);
  * OOC_STRESS_SEED=s fills the device buffers with NaN first and, chosen by

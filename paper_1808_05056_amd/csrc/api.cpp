@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -375,6 +376,17 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
     stats->kernels = kern;
     stats->bytes_h2d = bh;
     stats->bytes_d2h = bd;
+  }
+  if (env_int("OOC_LOG", 0) > 0) {
+    // one line per call on stderr: problem, plan, times and outcome
+    std::fprintf(stderr,
+                 "[ooc] M=%lld N=%lld K=%lld budget=%llu plan mb=%lld nb=%lld kb=%lld order=%d bufs=%d/%d/%d/%d "
+                 "streams=%d group=%d %s%s ops=%zu arena=%llu t=%.6fs predicted=%.6fs status=%d\n",
+                 (long long)M, (long long)N, (long long)K, (unsigned long long)budget_bytes, (long long)plan.mb,
+                 (long long)plan.nb, (long long)plan.kb, plan.order, plan.nbuf_a, plan.nbuf_b, plan.nbuf_c,
+                 plan.nbuf_d, plan.nstreams, plan.group, plan.precision == OOC_SPLIT_BF16 ? "split-bf16 s=" : "fp64",
+                 plan.precision == OOC_SPLIT_BF16 ? std::to_string(plan.slices).c_str() : "", ops.size(),
+                 (unsigned long long)lay.bytes, now_s() - t_enter, predicted, (int)st);
   }
   return st;
 }
