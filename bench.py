@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "OOC DGEMM end-to-end TFLOP/s, FP64 vs split-BF16 at equal error; link GB/s"
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+PEAK_INT8_TOPS = 5000.0  # MI355X dense INT8 matrix peak (TOP/s)
 LINK_PEAK_GBPS = 63.0  # PCIe 5.0 x16, one direction (32 GT/s x 16 lanes, 128b/130b)
 PEAK_HBM_GBS = 8000.0
 
@@ -67,7 +68,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="square-32768-budget-4GiB")
     ap.add_argument("--planner", default="model", choices=["model", "paper", "mlp"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "split", "split-int8"])
     ap.add_argument("--slices", type=int, default=6)
     ap.add_argument("--cpu-rows", type=int, default=128, help="rows of C the CPU reference computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,7 +96,7 @@ def main():
         raise SystemExit("libooc.so is not built")
     w = W.BY_NAME[args.workload]
     planner = {"model": ooc.PLAN_MODEL, "paper": ooc.PLAN_PAPER, "mlp": ooc.PLAN_MLP}[args.planner]
-    prec = ooc.SPLIT_BF16 if args.precision == "split" else ooc.FP64
+    prec = {"fp64": ooc.FP64, "split": ooc.SPLIT_BF16, "split-int8": ooc.SPLIT_INT8}[args.precision]
     opts = ooc.make_opts(planner=planner, precision=prec, slices=args.slices if prec else 0)
     popts = ooc.make_opts(planner=planner, precision=prec, slices=args.slices if prec else 0,
                           profile=bool(args.profile))
@@ -160,11 +161,14 @@ def main():
         if prec == ooc.FP64:
             peak, work, kname = PEAK_FP64_TFLOPS, w.flops, "dgemm_f64_mfma"
             traffic = measured_traffic(w.name, plan_tag)
-        else:  # BF16 matrix work of the slice products (kernel time includes slicing)
-            peak, work, kname = PEAK_BF16_TFLOPS, w.flops * args.slices * (args.slices + 1) / 2, "split_gemm"
+        else:  # BF16 or INT8 matrix work of the slice products (kernel time includes slicing)
+            peak, kname = ((PEAK_BF16_TFLOPS, "split_gemm") if prec == ooc.SPLIT_BF16
+                           else (PEAK_INT8_TOPS, "split_gemm_i8"))
+            work = w.flops * args.slices * (args.slices + 1) / 2
             traffic = None
         achieved = work * args.steps / kbusy / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TOP/s" if prec == ooc.SPLIT_INT8 else "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel_source": kernel_source_hash(KERNEL_SOURCES if prec == ooc.FP64 else SPLIT_SOURCES),
                 "plan_tag": plan_tag,
@@ -179,15 +183,17 @@ def main():
                 "h2d_frac_of_link_peak": round(s1.bytes_h2d * args.steps / hbusy / 1e9 / LINK_PEAK_GBPS, 3)}
     # end-to-end roofline: min(matrix peak, link peak x the plan's flops per host-to-device byte)
     ai = w.flops / max(s1.bytes_h2d, 1)
-    compute_peak = (PEAK_FP64_TFLOPS if prec == ooc.FP64
-                    else PEAK_BF16_TFLOPS / (args.slices * (args.slices + 1) / 2))  # FP64-equivalent
+    compute_peak = (PEAK_FP64_TFLOPS if prec == ooc.FP64  # FP64-equivalent
+                    else (PEAK_BF16_TFLOPS if prec == ooc.SPLIT_BF16 else PEAK_INT8_TOPS)
+                    / (args.slices * (args.slices + 1) / 2))
     e2e_roof = min(compute_peak, ai * LINK_PEAK_GBPS * 1e9 / 1e12)
     e2e = {"tflops": round(e2e_roof, 3), "flop_per_h2d_byte": round(ai, 2), "link_peak_GBps": LINK_PEAK_GBPS,
            "frac": round(value / e2e_roof, 4)}
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == ooc.FP64 else f"split-bf16x{args.slices}",
+        "vs_baseline": None, "dtype": ("f64" if prec == ooc.FP64 else
+                                                 f"split-{'bf16' if prec == ooc.SPLIT_BF16 else 'int8'}x{args.slices}"),
         "data": "synthetic (seeded counter-based generator)",
         "config": {"workload": w.name, "M": w.M, "N": w.N, "K": w.K, "alpha": w.alpha, "beta": w.beta,
                    "budget_bytes": w.budget, "planner": args.planner, "plan": plan.as_dict(),

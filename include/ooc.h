@@ -55,8 +55,12 @@ typedef enum {
  * 2012): slice products are exact with FP32 accumulation over windows of
  * 64-256 k, window sums are added exactly in int32, and the weighted slice
  * sums are combined in FP64; only the slices beyond s are dropped (truncation error
- * about (s+1) 2^(-8s) relative to (|A||B|)_ij times the row/column spread). */
-typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1 } ooc_precision;
+ * about (s+1) 2^(-8s) relative to (|A||B|)_ij times the row/column spread).
+ * SPLIT_INT8: the same scheme with s INT8 slices of 7 bits each (digits
+ * truncated toward zero, |digit| <= 127) multiplied on INT8 matrix cores with
+ * exact INT32 sums; twice the BF16 rate per slice product, one bit less per
+ * slice (truncation error about (s+2) 2^(-7s) relative, as above). */
+typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1, OOC_SPLIT_INT8 = 2 } ooc_precision;
 
 /* How a plan is chosen.  PAPER: the paper's partitioner (Section V: fewest
  * vertical B slices, then fewest horizontal A slices, such that two C blocks of
@@ -67,7 +71,8 @@ typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1 } ooc_precision;
  * smallest time predicted by the loaded network (the network shipped beside
  * the library is loaded on first use; falls back to MODEL when none is
  * loaded, for split-BF16 plans when the loaded network was trained on FP64
- * timings only, which it records as a constant slice-count feature, and for
+ * timings only, which it records as a constant slice-count feature, for
+ * split-INT8 plans (the shipped network has not seen their timings), and for
  * problems whose M, N, K or budget lies more than four standard deviations
  * (log scale) from the training problems' mean).  AUTO = MODEL. */
 typedef enum { OOC_PLAN_AUTO = 0, OOC_PLAN_PAPER = 1, OOC_PLAN_MODEL = 2, OOC_PLAN_MLP = 3 } ooc_planner;
@@ -101,7 +106,7 @@ typedef struct {
   int32_t nstreams;     /* 1: one stream; 2: the paper's two streams used round robin by
                            block parity; 3: one stream each for H2D, kernels and D2H */
   int32_t precision;    /* ooc_precision */
-  int32_t slices;       /* split-BF16 slice count s (1..8); ignored for FP64 */
+  int32_t slices;       /* split slice count s (1..8); ignored for FP64 */
   int32_t nbuf_d;       /* 0: each C block is loaded into its own buffer before its first K panel.
                            >0 (beta != 0 only): C blocks start from zero and the initial C of a block
                            is staged in one of nbuf_d extra buffers (mb x nb) and added, scaled by
@@ -116,7 +121,7 @@ typedef struct {
   int32_t device;       /* HIP device ordinal (default 0) */
   int32_t planner;      /* ooc_planner (default AUTO) */
   int32_t precision;    /* ooc_precision (default FP64) */
-  int32_t slices;       /* split-BF16 slices (0: 6) */
+  int32_t slices;       /* split slices (0: 6) */
   int32_t nstreams;     /* restrict candidate plans to this stream count (0: any) */
   int32_t profile;      /* 1: time every operation with HIP events (fills the busy times) */
   void* arena;          /* optional caller-owned device memory used instead of allocating */
@@ -207,8 +212,9 @@ typedef enum {
   OOC_OP_H2D = 0,        /* host submatrix -> device buffer (2-D pitched copy) */
   OOC_OP_D2H = 1,        /* device buffer -> host submatrix */
   OOC_OP_GEMM = 2,       /* FP64 tile product c = alpha*a*b + beta*c + gamma*d on device buffers */
-  OOC_OP_SPLIT_GEMM = 3  /* the same product from BF16 slices: slices and exponents of the A and B
-                            panels are written to the workspace (off_w, len_w), then multiplied */
+  OOC_OP_SPLIT_GEMM = 3  /* the same product from BF16 or INT8 slices (the plan's precision): slices
+                            and exponents of the A and B panels are written to the workspace
+                            (off_w, len_w), then multiplied */
 } ooc_op_kind;
 
 #define OOC_MAX_WAITS 6
@@ -273,6 +279,12 @@ ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, dou
 ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
                                  const double* A, int64_t lda, const double* B, int64_t ldb,
                                  double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
+
+/* The same with s INT8 slices of 7 bits (OOC_SPLIT_INT8) on INT8 matrix cores
+ * with exact INT32 sums; arguments, rounding and errors as above. */
+ooc_status ooc_split_int8_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
+                                      const double* A, int64_t lda, const double* B, int64_t ldb,
+                                      double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
 
 /* ---- the learned planner ------------------------------------------------------ */
 /* A small regression network predicts the log run time of a candidate plan

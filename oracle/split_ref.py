@@ -29,8 +29,20 @@ units with FP32 accumulation.  Steps, for one K panel of A (m x k) and B (k x n)
 The grouping of equal weights in step 4 is a reading of the method, which
 only requires the slice sum in FP64, and grouping keeps the result
 independent of how the equal-weight pairs are ordered.
+
+Format "i8" is the same scheme with slices that INT8 matrix units multiply
+exactly into INT32 sums: in step 2, m_p = trunc(r * 2^(7p - e_i)) (rounded
+toward zero), r = r - m_p * 2^(e_i - 7p), so |m_p| <= 127 (|r| < 2^(e_i - 7(p-1))
+before step p); in steps 3-4 the weights are 2^(e_i + f_j - 7t).  A product
+of two slices is below 2^14 in magnitude, so an INT32 sum over every pair of
+one weight is exact for s * k * 2^14 < 2^31.  Seven bits per slice instead of
+eight: for the same truncation error the i8 form needs about 8/7 as many
+slices.
 """
 import numpy as np
+
+# slice format: (bits per slice, rounding of each slice)
+FORMATS = {"bf16": (8, np.rint), "i8": (7, np.trunc)}
 
 
 def exponents(X, axis):
@@ -42,21 +54,22 @@ def exponents(X, axis):
     return e
 
 
-def slices(X, e, s, axis):
+def slices(X, e, s, axis, fmt="bf16"):
     """s integer-valued slices of X and the final remainder (float64 arrays).
 
     axis=1: e holds one exponent per row; axis=0: one per column."""
+    bits, rnd = FORMATS[fmt]
     eb = e[:, None] if axis == 1 else e[None, :]
     r = np.array(X, dtype=np.float64, copy=True)
     out = []
     for p in range(1, s + 1):
-        m = np.rint(np.ldexp(r, (8 * p - eb).astype(np.int64)))
-        r = r - np.ldexp(m, (eb - 8 * p).astype(np.int64))
+        m = rnd(np.ldexp(r, (bits * p - eb).astype(np.int64)))
+        r = r - np.ldexp(m, (eb - bits * p).astype(np.int64))
         out.append(m)
     return out, r
 
 
-def slice_sum(A, B, s):
+def slice_sum(A, B, s, fmt="bf16"):
     """Steps 1-4 for one panel: the FP64 slice-sum S of A @ B."""
     m, k = A.shape
     n = B.shape[1]
@@ -64,19 +77,20 @@ def slice_sum(A, B, s):
         return np.zeros((m, n))
     e = exponents(A, 1)
     f = exponents(B, 0)
-    sa, _ = slices(A, e, s, 1)
-    sb, _ = slices(B, f, s, 0)
+    bits = FORMATS[fmt][0]
+    sa, _ = slices(A, e, s, 1, fmt)
+    sb, _ = slices(B, f, s, 0, fmt)
     S = np.zeros((m, n))
     for t in range(s + 1, 1, -1):
         U = np.zeros((m, n))
         for p in range(1, t):
             q = t - p
             U = U + sa[p - 1] @ sb[q - 1]
-        S = S + np.ldexp(U, (e[:, None] + f[None, :] - 8 * t).astype(np.int64))
+        S = S + np.ldexp(U, (e[:, None] + f[None, :] - bits * t).astype(np.int64))
     return S
 
 
-def split_gemm(alpha, A, B, beta, C, s, kb=None):
+def split_gemm(alpha, A, B, beta, C, s, kb=None, fmt="bf16"):
     """alpha*A@B + beta*C by the split scheme with s slices (K panels of kb)."""
     M, K = A.shape
     N = B.shape[1]
@@ -86,7 +100,7 @@ def split_gemm(alpha, A, B, beta, C, s, kb=None):
         return beta * Cout if beta != 0.0 else np.zeros((M, N))
     first = True
     for k0 in range(0, K, kb):
-        S = slice_sum(A[:, k0:k0 + kb], B[k0:k0 + kb, :], s)
+        S = slice_sum(A[:, k0:k0 + kb], B[k0:k0 + kb, :], s, fmt)
         if first:
             Cout = alpha * S + beta * Cout if beta != 0.0 else alpha * S
             first = False
@@ -95,11 +109,15 @@ def split_gemm(alpha, A, B, beta, C, s, kb=None):
     return Cout
 
 
-def truncation_bound(A, B, s):
+def truncation_bound(A, B, s, fmt="bf16"):
     """A bound on |S - A@B| per entry from the slice remainders:
     |A@B - sum_{p+q<=s+1} ...| <= sum over dropped pairs + remainder terms,
-    bounded here by (s+1) * 2^(-8s) * 2^(e_i+f_j) * k (crude, entrywise)."""
+    bounded here by (s+1) * 2^(-8s) * 2^(e_i+f_j) * k for BF16 slices and
+    (s+2) * 2^(-7s) * 2^(e_i+f_j) * k for INT8 slices (crude, entrywise: a
+    truncated INT8 slice keeps a remainder up to one unit of its last digit,
+    twice the rounded BF16 slice's half unit)."""
     e = exponents(A, 1)
     f = exponents(B, 0)
     k = A.shape[1]
-    return (s + 1) * 2.0 ** (-8 * s) * np.ldexp(np.ones((A.shape[0], B.shape[1])), (e[:, None] + f[None, :])) * k
+    lead = (s + 1) * 2.0 ** (-8 * s) if fmt == "bf16" else (s + 2) * 2.0 ** (-7 * s)
+    return lead * np.ldexp(np.ones((A.shape[0], B.shape[1])), (e[:, None] + f[None, :])) * k

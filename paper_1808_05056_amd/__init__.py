@@ -30,7 +30,7 @@ OOC_OK, OOC_ERR_ARG, OOC_ERR_BUDGET, OOC_ERR_DEVICE_MEM, OOC_ERR_NOT_PINNED, OOC
     OOC_ERR_NO_DEVICE, OOC_ERR_INJECTED, OOC_ERR_CAPACITY = range(9)
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_BUDGET", 3: "ERR_DEVICE_MEM", 4: "ERR_NOT_PINNED", 5: "ERR_HIP",
                 6: "ERR_NO_DEVICE", 7: "ERR_INJECTED", 8: "ERR_CAPACITY"}
-FP64, SPLIT_BF16 = 0, 1
+FP64, SPLIT_BF16, SPLIT_INT8 = 0, 1, 2
 PLAN_AUTO, PLAN_PAPER, PLAN_MODEL, PLAN_MLP = 0, 1, 2, 3
 ORDER_COLS, ORDER_ROWS, ORDER_COLS_P, ORDER_ROWS_P, ORDER_COLS_PS, ORDER_ROWS_PS = 0, 1, 2, 3, 4, 5
 OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM = range(4)
@@ -110,6 +110,7 @@ _sig("ooc_release", i32, [i32])
 _sig("ooc_device_copy", i32, [i32, vp, vp, sz])
 _sig("ooc_dgemm_device", i32, [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 _sig("ooc_split_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
+_sig("ooc_split_int8_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 P_flt = ctypes.POINTER(ctypes.c_float)
 _sig("ooc_mlp_features", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P_flt])
 _sig("ooc_mlp_forward", i32, [i32, i32, i32, P_flt, P_flt, i64, P_flt])
@@ -128,7 +129,8 @@ _sig("ooc_version", ctypes.c_char_p, [])
 EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_device_copy", "ooc_dgemm_device",
-           "ooc_split_gemm_device", "ooc_mlp_features", "ooc_mlp_forward", "ooc_mlp_grad", "ooc_mlp_adam",
+           "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_mlp_features", "ooc_mlp_forward",
+           "ooc_mlp_grad", "ooc_mlp_adam",
            "ooc_mlp_train", "ooc_mlp_fit", "ooc_mlp_save", "ooc_mlp_load", "ooc_mlp_loaded", "ooc_mlp_predict",
            "ooc_last_error", "ooc_version"]
 MLP_FEATURES = 19
@@ -307,6 +309,13 @@ def ooc_split_gemm_device(m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, re
     ms = dbl()
     _check(_lib.ooc_split_gemm_device(device, m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps,
                                       ctypes.byref(ms) if timed else None))
+    return ms.value if timed else None
+
+
+def ooc_split_int8_gemm_device(m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps=1, timed=False, device=0):
+    ms = dbl()
+    _check(_lib.ooc_split_int8_gemm_device(device, m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps,
+                                           ctypes.byref(ms) if timed else None))
     return ms.value if timed else None
 
 

@@ -211,9 +211,9 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
                                o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d, s);
           break;
         case OOC_OP_SPLIT_GEMM:
-          e = launch_split_gemm(o.rows, o.cols, o.k, plan.slices, o.alpha, arena + o.off_a, o.ld_a, arena + o.off_b,
-                                o.ld_b, o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d,
-                                arena + o.off_w, (size_t)o.len_w * 8, s);
+          e = launch_split_gemm(slice_format(plan.precision), o.rows, o.cols, o.k, plan.slices, o.alpha,
+                                arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b, o.beta, arena + o.off_c, o.ld_c,
+                                o.gamma, arena + o.off_d, o.ld_d, arena + o.off_w, (size_t)o.len_w * 8, s);
           break;
         default:
           status = OOC_ERR_ARG;
@@ -384,8 +384,9 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
                  "streams=%d group=%d %s%s ops=%zu arena=%llu t=%.6fs predicted=%.6fs status=%d\n",
                  (long long)M, (long long)N, (long long)K, (unsigned long long)budget_bytes, (long long)plan.mb,
                  (long long)plan.nb, (long long)plan.kb, plan.order, plan.nbuf_a, plan.nbuf_b, plan.nbuf_c,
-                 plan.nbuf_d, plan.nstreams, plan.group, plan.precision == OOC_SPLIT_BF16 ? "split-bf16 s=" : "fp64",
-                 plan.precision == OOC_SPLIT_BF16 ? std::to_string(plan.slices).c_str() : "", ops.size(),
+                 plan.nbuf_d, plan.nstreams, plan.group,
+                 plan.precision == OOC_SPLIT_BF16 ? "split-bf16 s=" : (plan.precision == OOC_SPLIT_INT8 ? "split-int8 s=" : "fp64"),
+                 plan.precision != OOC_FP64 ? std::to_string(plan.slices).c_str() : "", ops.size(),
                  (unsigned long long)lay.bytes, now_s() - t_enter, predicted, (int)st);
   }
   return st;
@@ -637,9 +638,9 @@ ooc_status ooc_dgemm_device(int32_t device, int64_t m, int64_t n, int64_t k, dou
   return OOC_OK;
 }
 
-ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
-                                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                                 int64_t ldc, int32_t reps, double* ms_out) {
+static ooc_status split_gemm_device(SliceFormat f, int32_t device, int64_t m, int64_t n, int64_t k, int32_t s,
+                                    double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                                    double beta, double* C, int64_t ldc, int32_t reps, double* ms_out) {
   if (m < 0 || n < 0 || k < 0) return fail(OOC_ERR_ARG, "negative size");
   if (s < 1 || s > 8) return fail(OOC_ERR_ARG, "slices must be 1..8");
   if (m == 0 || n == 0) return OOC_OK;
@@ -652,7 +653,7 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
   st = ensure_streams(c);
   if (st != OOC_OK) return st;
   hipStream_t strm = c.st[1];
-  const size_t wsb = split_workspace_bytes(m, n, k, s);
+  const size_t wsb = split_workspace_bytes(m, n, k, s, f);
   void* ws = nullptr;
   HIPCHK(hipMalloc(&ws, wsb), "hipMalloc workspace");
   const int r = reps > 0 ? reps : 1;
@@ -664,7 +665,7 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
     if (e == hipSuccess) e = hipEventRecord(e0, strm);
   }
   for (int x = 0; x < r && e == hipSuccess; ++x)
-    e = launch_split_gemm(m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, 0.0, nullptr, 0, ws, wsb, strm);
+    e = launch_split_gemm(f, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, 0.0, nullptr, 0, ws, wsb, strm);
   if (e == hipSuccess && ms_out) e = hipEventRecord(e1, strm);
   const hipError_t es = hipStreamSynchronize(strm);  // also after a failed launch, before the workspace is freed
   if (e == hipSuccess) e = es;
@@ -678,6 +679,18 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
   (void)hipFree(ws);
   if (e != hipSuccess) return hip_fail(e, "split gemm");
   return OOC_OK;
+}
+
+ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
+                                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                                 int64_t ldc, int32_t reps, double* ms_out) {
+  return split_gemm_device(kSliceBF16, device, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, reps, ms_out);
+}
+
+ooc_status ooc_split_int8_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
+                                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                                      double* C, int64_t ldc, int32_t reps, double* ms_out) {
+  return split_gemm_device(kSliceInt8, device, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, reps, ms_out);
 }
 
 ooc_status ooc_device_copy(int32_t device, void* dst, const void* src, size_t bytes) {

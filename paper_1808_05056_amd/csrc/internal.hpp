@@ -34,7 +34,7 @@ int64_t ceil_div(int64_t a, int64_t b);
 // Checks a plan's shape and fills the arena layout. Returns OOC_OK or OOC_ERR_ARG.
 ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay);
 
-// Split-BF16 workspace elements a plan needs (0 for FP64 plans).
+// Split workspace elements a plan needs (0 for FP64 plans).
 int64_t split_workspace_elems(const Problem& pb, const ooc_plan_t& plan);
 
 // The operation list of a plan (see ooc_op). Returns OOC_OK or OOC_ERR_ARG
@@ -65,6 +65,7 @@ struct Machine {
   double split_tflops_per_product = 725.0;  // BF16 slice-product rate (TFLOP/s of BF16 work), two tiles per CU
   double split_tflops_1wg_per_product = 350.0;  // same with one tile per CU
   double split_k0 = 160.0;                   // per weight and tile: pipeline start in units of k
+  double split_int8_speedup = 2.0;           // INT8 slice products per BF16 slice product in the same time
   double hbm_bytes_per_s = 5e12;            // streaming rate of the split kernel's slice-sum tile
   int cus = 256;
 };

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "ooc.h"
+
 namespace ooc {
 
 // C = alpha*A*B + beta*C + gamma*D, FP64 on matrix cores (row-major; k == 0
@@ -14,15 +16,19 @@ hipError_t launch_dgemm_f64(int64_t m, int64_t n, int64_t k, double alpha, const
                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                             double gamma, const double* D, int64_t ldd, hipStream_t stream);
 
-// Split-BF16 tile product (s slices): same result contract as launch_dgemm_f64
-// up to the split scheme's error; uses `workspace` (split_workspace_bytes).
-// K is processed in panels of at most kSplitMaxK (exact int32 slice sums):
+// Split tile product (s slices of BF16 or INT8, by bytes per slice element):
+// same result contract as launch_dgemm_f64 up to the split scheme's error;
+// uses `workspace` (split_workspace_bytes).  K is processed in panels of at
+// most kSplitMaxK (exact int32 slice sums):
 // C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C.
+enum SliceFormat { kSliceInt8 = 1, kSliceBF16 = 2 };
+inline SliceFormat slice_format(int precision) { return precision == OOC_SPLIT_INT8 ? kSliceInt8 : kSliceBF16; }
 constexpr int64_t kSplitMaxK = 8192;
-size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s);
-hipError_t launch_split_gemm(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
-                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
-                             const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream);
+size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat f);
+hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                             double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
+                             hipStream_t stream);
 
 // The planner network (see mlp.hip): parameter count, scratch size (floats)
 // for a batch of n, forward pass into y, loss and gradient, one Adam step.

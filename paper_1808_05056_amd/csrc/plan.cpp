@@ -20,9 +20,10 @@ const Machine& machine() {
 }
 
 int64_t split_workspace_elems(const Problem& pb, const ooc_plan_t& plan) {
-  if (plan.precision != OOC_SPLIT_BF16 || pb.keff() == 0) return 0;
-  // BF16 slice planes of one A panel and one B panel plus their exponents
-  return ceil_div((int64_t)split_workspace_bytes(plan.mb, plan.nb, plan.kb, plan.slices), 8);
+  if (plan.precision == OOC_FP64 || pb.keff() == 0) return 0;
+  // slice planes of one A panel and one B panel plus their exponents and the slice-sum tile
+  return ceil_div((int64_t)split_workspace_bytes(plan.mb, plan.nb, plan.kb, plan.slices, slice_format(plan.precision)),
+                  8);
 }
 
 ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
@@ -33,9 +34,9 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
   if (plan.order < 0 || plan.order > 5) return fail(OOC_ERR_ARG, "plan: unknown order");
   if (plan.nbuf_c < 1 || (K > 0 && (plan.nbuf_a < 1 || plan.nbuf_b < 1)))
     return fail(OOC_ERR_ARG, "plan: every operand needs at least one buffer");
-  if (plan.precision != OOC_FP64 && plan.precision != OOC_SPLIT_BF16)
+  if (plan.precision != OOC_FP64 && plan.precision != OOC_SPLIT_BF16 && plan.precision != OOC_SPLIT_INT8)
     return fail(OOC_ERR_ARG, "plan: unknown precision");
-  if (plan.precision == OOC_SPLIT_BF16 && (plan.slices < 1 || plan.slices > 8))
+  if (plan.precision != OOC_FP64 && (plan.slices < 1 || plan.slices > 8))
     return fail(OOC_ERR_ARG, "plan: slices must be 1..8");
   if (plan.nbuf_d < 0) return fail(OOC_ERR_ARG, "plan: nbuf_d must be >= 0");
   if (plan.group < 0) return fail(OOC_ERR_ARG, "plan: group must be >= 0");
@@ -127,7 +128,7 @@ bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan, int 
     p.nbuf_c = 2;
     p.nstreams = 2;
     p.precision = precision;
-    p.slices = precision == OOC_SPLIT_BF16 ? slices : 0;
+    p.slices = precision != OOC_FP64 ? slices : 0;
     p.nbuf_d = 0;
     return p;
   };
@@ -159,7 +160,7 @@ bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan, int 
 
 // ---- cost model --------------------------------------------------------------------
 
-static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k, bool split, int slices) {
+static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k, int precision, int slices) {
   if (m <= 0 || n <= 0) return mc.kernel_launch_s;
   const double tiles = (double)ceil_div(m, 128) * (double)ceil_div(n, 128);
   if (k <= 0) return mc.kernel_launch_s + (double)m * n * 16.0 / 4e12;
@@ -181,13 +182,15 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
     else if (rest > 0) t += tile_flops / r1;
   }
   if ((k & 1) || (n & 1)) t *= mc.kernel_scalar_factor;
-  if (split) {
+  if (precision != OOC_FP64) {
     // the slice-product kernel computes whole 128 x 128 tiles, two per CU at
     // a time, in waves like the FP64 kernel; every weight's pass over a tile
-    // pays a pipeline start of split_k0 k
+    // pays a pipeline start of split_k0 k (at the BF16 rate; INT8 products
+    // run split_int8_speedup times faster, the start costs the same time)
     const double mp = std::ceil(m / 128.0) * 128.0, np = std::ceil(n / 128.0) * 128.0;
     const double products = slices * (slices + 1) / 2.0;
-    const double stile = 2.0 * 128.0 * 128.0 * (products * (double)k + slices * mc.split_k0);
+    const double speed = precision == OOC_SPLIT_INT8 ? mc.split_int8_speedup : 1.0;
+    const double stile = 2.0 * 128.0 * 128.0 * (products * (double)k / speed + slices * mc.split_k0);
     const double s2 = mc.split_tflops_per_product * 1e12 / mc.cus;
     const double s1 = mc.split_tflops_1wg_per_product * 1e12 / mc.cus;
     double ts;
@@ -201,7 +204,7 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
       if (rest > mc.cus) ts += 2.0 * stile / s2;
       else if (rest > 0) ts += stile / s1;
     }
-    const double slice_s = (mp + np) * k * (8.0 + 2.0 * slices) / 4e12;
+    const double slice_s = (mp + np) * k * (8.0 + (double)slice_format(precision) * slices) / 4e12;
     // the FP64 slice-sum tile is read and written once per weight (s weights)
     const double sum_s = (double)slices * 16.0 * mp * np / mc.hbm_bytes_per_s;
     return mc.kernel_launch_s * 6 + slice_s + sum_s + ts;
@@ -225,7 +228,8 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
     else if (o.kind == OOC_OP_D2H) { cls[x] = 1; work[x] = (double)o.rows * o.cols * 8.0; }
     else {
       cls[x] = 2;
-      work[x] = kernel_seconds(mc, o.rows, o.cols, o.k, o.kind == OOC_OP_SPLIT_GEMM, plan.slices);
+      work[x] = kernel_seconds(mc, o.rows, o.cols, o.k, o.kind == OOC_OP_SPLIT_GEMM ? plan.precision : OOC_FP64,
+                               plan.slices);
     }
   }
   const int ns = plan.nstreams;
@@ -338,10 +342,10 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
   auto consider = [&](ooc_plan_t p) {
     Layout lay;
     p.precision = prec;
-    p.slices = prec == OOC_SPLIT_BF16 ? slices : 0;
+    p.slices = prec != OOC_FP64 ? slices : 0;
     // split tiles run K in panels of kSplitMaxK inside the kernel; plan panels
     // are kept to that size or below so both levels of panels coincide
-    if (prec == OOC_SPLIT_BF16 && K > kSplitMaxK && p.kb > kSplitMaxK) return;
+    if (prec != OOC_FP64 && K > kSplitMaxK && p.kb > kSplitMaxK) return;
     if (plan_layout(pb, p, &lay) != OOC_OK) return;
     if (lay.bytes > budget_bytes) return;
     // analytic lower bound: operand traffic vs link, flops vs kernel rate
@@ -392,8 +396,8 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
           const int64_t mr = M - (h - 1) * mb, nr = N - (w - 1) * nb;
           const int64_t kr = K > 0 ? K - (P - 1) * kb : 0;
           auto kt = [&](int64_t m, int64_t n) {
-            double t = (double)(P - 1) * kernel_seconds(mc, m, n, kb, prec == OOC_SPLIT_BF16, slices);
-            return t + kernel_seconds(mc, m, n, kr, prec == OOC_SPLIT_BF16, slices);
+            double t = (double)(P - 1) * kernel_seconds(mc, m, n, kb, prec, slices);
+            return t + kernel_seconds(mc, m, n, kr, prec, slices);
           };
           t_comp = (double)(h - 1) * (w - 1) * kt(mb, nb) + (double)(h - 1) * kt(mb, nr) +
                    (double)(w - 1) * kt(mr, nb) + kt(mr, nr);

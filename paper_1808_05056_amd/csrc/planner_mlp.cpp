@@ -136,7 +136,7 @@ void plan_features(const Problem& pb, uint64_t budget, const ooc_plan_t& p, doub
   f[x++] = (float)p.nstreams;
   f[x++] = (float)log2p(model_s);
   f[x++] = (float)log2p(h2d_bytes + 1);
-  f[x++] = (float)(p.precision == OOC_SPLIT_BF16 ? p.slices : 0);
+  f[x++] = (float)(p.precision != OOC_FP64 ? p.slices : 0);
 }
 
 ooc_status features_for(const Problem& pb, uint64_t budget, const ooc_plan_t* plans, int64_t n, float* X) {
@@ -188,8 +188,10 @@ bool mlp_predict(const Problem& pb, uint64_t budget_bytes, const std::vector<ooc
   // count (stored as mean 0, deviation 1): it does not rank split plans.
   constexpr int kSliceFeature = OOC_MLP_FEATURES - 1;
   const bool knows_split = net.fmean[kSliceFeature] != 0.f || net.fstd[kSliceFeature] != 1.f;
+  // Nor was it trained on INT8 slice timings, which run at twice the BF16 rate
+  // per product: it declines those plans too.
   for (const ooc_plan_t& p : plans)
-    if (p.precision == OOC_SPLIT_BF16 && !knows_split) return false;
+    if ((p.precision == OOC_SPLIT_BF16 && !knows_split) || p.precision == OOC_SPLIT_INT8) return false;
   const int64_t n = (int64_t)plans.size();
   std::vector<float> X((size_t)n * OOC_MLP_FEATURES), y(n);
   if (features_for(pb, budget_bytes, plans.data(), n, X.data()) != OOC_OK) return false;

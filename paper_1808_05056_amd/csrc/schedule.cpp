@@ -150,7 +150,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
   const int64_t kb = K > 0 ? plan.kb : 0;
   const int64_t h = ceil_div(M, mb), w = ceil_div(N, nb);
   const int64_t P = K > 0 ? ceil_div(K, kb) : 1;
-  const bool split = plan.precision == OOC_SPLIT_BF16 && K > 0;
+  const bool split = plan.precision != OOC_FP64 && K > 0;
   const int ns = plan.nstreams;
 
   std::vector<Task> tasks = make_tasks(plan.order, h, w, P, plan.group);

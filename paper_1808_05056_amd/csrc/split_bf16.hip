@@ -55,27 +55,46 @@ __device__ inline int32_t exponent_of(double mx) {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// The S slices of r (exponent e) as BF16 bit patterns: m_p = rint(r 2^(8p-e)),
-// r -= m_p 2^(e-8p), each step exact.
-template <int S>
+// Slice formats, by bytes per slice element EB: 2 = BF16 digits m_p =
+// rint(r 2^(8p-e)) (|m_1| <= 256, |m_p| <= 128), 1 = INT8 digits m_p =
+// trunc(r 2^(7p-e)) (|m_p| <= 127); in both r -= m_p 2^(e - bits p), exactly.
+template <int EB>
+struct SliceFmt;
+template <>
+struct SliceFmt<2> {
+  static constexpr int kBits = 8;
+  __device__ static double digit(double x) { return rint(x); }
+  __device__ static uint32_t pattern(double m) { return bf16_bits_exact(m); }
+};
+template <>
+struct SliceFmt<1> {
+  static constexpr int kBits = 7;
+  __device__ static double digit(double x) { return trunc(x); }
+  __device__ static uint32_t pattern(double m) { return (uint32_t)(uint8_t)(int8_t)(int)m; }
+};
+
+// The S slices of r (exponent e) as bit patterns of the format.
+template <int S, int EB>
 __device__ __forceinline__ void slices_of(double r, int32_t e, uint32_t (&bits)[S]) {
+  constexpr int b = SliceFmt<EB>::kBits;
 #pragma unroll
   for (int p = 1; p <= S; ++p) {
     double mp = 0.0;
     if (r != 0.0) {
-      mp = rint(ldexp(r, 8 * p - e));
-      r = r - ldexp(mp, e - 8 * p);
+      mp = SliceFmt<EB>::digit(ldexp(r, b * p - e));
+      r = r - ldexp(mp, e - b * p);
     }
-    bits[p - 1] = bf16_bits_exact(mp);
+    bits[p - 1] = SliceFmt<EB>::pattern(mp);
   }
 }
 
 // One wave per row of A: exponent, then the S slices of the row into the
-// planes, 8 consecutive k per lane and step (one 16-byte store per plane).
-template <int S>
+// planes, 16 bytes of consecutive k per lane and step (one store per plane).
+template <int S, int EB>
 __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const double* __restrict__ A, int64_t lda,
-                                                  int64_t mpad, int64_t kpad, uint16_t* __restrict__ planes,
+                                                  int64_t mpad, int64_t kpad, uint8_t* __restrict__ planes,
                                                   int32_t* __restrict__ ex_out) {
+  constexpr int E = 16 / EB, PER = 4 / EB;  // elements per lane and step, per 32-bit word
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= mpad) return;
@@ -95,25 +114,26 @@ __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const do
   }
   const int32_t ex = bad ? kBad : exponent_of(mx);
   if (lane == 0) ex_out[row] = ex;
-  // kpad is a multiple of 64, so a lane's 8 values never cross it
-  for (int64_t k8 = (int64_t)lane * 8; k8 < kpad; k8 += 512) {
+  // kpad is a multiple of 64 (BF16) or 128 (INT8), so a lane's E values never cross it
+  for (int64_t k0 = (int64_t)lane * E; k0 < kpad; k0 += 64 * E) {
     uint32_t w[S][4];
 #pragma unroll
     for (int p = 0; p < S; ++p)
 #pragma unroll
       for (int x = 0; x < 4; ++x) w[p][x] = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t kk = k8 + q;
+    for (int q = 0; q < E; ++q) {
+      const int64_t kk = k0 + q;
       const double r = (live && !bad && kk < k) ? A[row * lda + kk] : 0.0;
       uint32_t b[S];
-      slices_of<S>(r, ex, b);
+      slices_of<S, EB>(r, ex, b);
 #pragma unroll
-      for (int p = 0; p < S; ++p) w[p][q >> 1] |= b[p] << (16 * (q & 1));
+      for (int p = 0; p < S; ++p) w[p][q / PER] |= b[p] << (8 * EB * (q % PER));
     }
 #pragma unroll
     for (int p = 0; p < S; ++p)
-      *reinterpret_cast<u32x4*>(planes + ((int64_t)p * mpad + row) * kpad + k8) = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
+      *reinterpret_cast<u32x4*>(planes + (((int64_t)p * mpad + row) * kpad + k0) * EB) =
+          u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
   }
 }
 
@@ -149,11 +169,12 @@ __global__ __launch_bounds__(256) void col_exponents(int64_t npad, const unsigne
 
 // Slices of B into transposed planes [p][j][k]: a 64 (k) x 64 (j) tile per
 // workgroup; each thread slices 16 consecutive k of one column and stores them
-// as two 16-byte vectors per plane.
-template <int S>
+// as EB 16-byte vectors per plane.
+template <int S, int EB>
 __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const double* __restrict__ B, int64_t ldb,
                                                   int64_t npad, int64_t kpad, const int32_t* __restrict__ ex,
-                                                  uint16_t* __restrict__ planes) {
+                                                  uint8_t* __restrict__ planes) {
+  constexpr int PER = 4 / EB, NW = 16 / PER;  // elements per 32-bit word, words per thread and plane
   __shared__ double tile[64][65];
   const int t = threadIdx.x;
   const int64_t k0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
@@ -167,24 +188,24 @@ __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const do
   const int jl = t >> 2, ks = (t & 3) * 16;
   const int64_t j = j0 + jl;
   const int32_t e = ex[j];
-  uint32_t w[S][8];
+  uint32_t w[S][NW];
 #pragma unroll
   for (int p = 0; p < S; ++p)
 #pragma unroll
-    for (int x = 0; x < 8; ++x) w[p][x] = 0;
+    for (int x = 0; x < NW; ++x) w[p][x] = 0;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const double r = (e == kBad) ? 0.0 : tile[jl][ks + q];
     uint32_t b[S];
-    slices_of<S>(r, e, b);
+    slices_of<S, EB>(r, e, b);
 #pragma unroll
-    for (int p = 0; p < S; ++p) w[p][q >> 1] |= b[p] << (16 * (q & 1));
+    for (int p = 0; p < S; ++p) w[p][q / PER] |= b[p] << (8 * EB * (q % PER));
   }
 #pragma unroll
   for (int p = 0; p < S; ++p) {
-    u32x4* dst = reinterpret_cast<u32x4*>(planes + ((int64_t)p * npad + j) * kpad + k0 + ks);
-    dst[0] = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
-    dst[1] = u32x4{w[p][4], w[p][5], w[p][6], w[p][7]};
+    u32x4* dst = reinterpret_cast<u32x4*>(planes + (((int64_t)p * npad + j) * kpad + k0 + ks) * EB);
+#pragma unroll
+    for (int v = 0; v < EB; ++v) dst[v] = u32x4{w[p][4 * v], w[p][4 * v + 1], w[p][4 * v + 2], w[p][4 * v + 3]};
   }
 }
 
@@ -204,6 +225,43 @@ __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const do
 // and B[8*(l/32) .. +8][l%32]; accumulator element v of lane l is
 // D[8*(v/4) + 4*(l/32) + v%4][l%32].
 constexpr int SBM = 128, SBN = 128, SKC = 64, SPAD = 8;  // tile, k chunk, LDS row padding (bf16)
+
+// S = S + U_t 2^(e_i + f_j - bits t) for one 128 x 128 tile whose integer sums
+// U_t sit in LDS (row-major), walked row by row with consecutive threads on
+// consecutive columns; the last weight (t = 2) finishes S and writes
+// C = alpha*S + beta*C + gamma*D with separate roundings.
+__device__ __forceinline__ void slice_sum_update(const int32_t* Ul, int t, int s, int bits, int tid, int64_t m0,
+                                                 int64_t n0, int64_t m, int64_t n, int64_t npad,
+                                                 const int32_t* __restrict__ ea, const int32_t* __restrict__ fb,
+                                                 double* __restrict__ Sws, double alpha, double beta,
+                                                 double* __restrict__ C, int64_t ldc, double gamma,
+                                                 const double* __restrict__ D, int64_t ldd) {
+  const int c = tid & (SBN - 1);
+  const int64_t col = n0 + c;
+  const int32_t ff = fb[col];
+#pragma unroll 4
+  for (int r = tid / SBN; r < SBM; r += 256 / SBN) {
+    const int64_t row = m0 + r;
+    const int32_t ee = ea[row];
+    const bool bad = ee == kBad || ff == kBad;
+    double* ps = Sws + row * npad + col;
+    const double term = bad ? 0.0 : ldexp((double)Ul[r * SBN + c], ee + ff - bits * t);
+    const double S = (t == s + 1) ? term : (*ps + term);
+    if (t > 2) {
+      *ps = S;
+    } else if (row < m && col < n) {
+      double val;
+      if (bad) {
+        val = __builtin_nan("");
+      } else {
+        val = __dmul_rn(alpha, S);
+        if (beta != 0.0) val = __dadd_rn(val, __dmul_rn(beta, C[row * ldc + col]));
+        if (gamma != 0.0) val = __dadd_rn(val, __dmul_rn(gamma, D[row * ldd + col]));
+      }
+      C[row * ldc + col] = val;
+    }
+  }
+}
 
 __device__ inline int fold_window_chunks(int t) { return t <= 3 ? 4 : (t <= 7 ? 2 : 1); }
 
@@ -350,33 +408,132 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
           Ul[(wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4)) * SBN + wn * 64 + j * 32 + (lane & 31)] =
               U[i][j][v];
     __syncthreads();
-    {
-      const int c = tid & (SBN - 1);
-      const int64_t col = n0 + c;
-      const int32_t ff = fb[col];
-#pragma unroll 4
-      for (int r = tid / SBN; r < SBM; r += 256 / SBN) {
-        const int64_t row = m0 + r;
-        const int32_t ee = ea[row];
-        const bool bad = ee == kBad || ff == kBad;
-        double* ps = Sws + row * npad + col;
-        const double term = bad ? 0.0 : ldexp((double)Ul[r * SBN + c], ee + ff - 8 * t);
-        const double S = (t == s + 1) ? term : (*ps + term);
-        if (t > 2) {
-          *ps = S;
-        } else if (row < m && col < n) {
-          double val;
-          if (bad) {
-            val = __builtin_nan("");
-          } else {
-            val = __dmul_rn(alpha, S);
-            if (beta != 0.0) val = __dadd_rn(val, __dmul_rn(beta, C[row * ldc + col]));
-            if (gamma != 0.0) val = __dadd_rn(val, __dmul_rn(gamma, D[row * ldd + col]));
-          }
-          C[row * ldc + col] = val;
-        }
-      }
+    slice_sum_update(Ul, t, s, 8, tid, m0, n0, m, n, npad, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
+    __syncthreads();  // LDS is staging space again
+    if (t > 2) {
+      lstore(0);
+      __syncthreads();
     }
+  }
+}
+
+// INT8 slice products on V_MFMA_I32_32X32X32_I8 (lane l supplies A[l%32][16*(l/32) .. +16]
+// and B[16*(l/32) .. +16][l%32]; accumulator layout as for the BF16 form).  The
+// same tiling and staging as split_gemm, byte for byte: a 128-k chunk of INT8
+// planes is the 128 bytes of a 64-k BF16 chunk.  A product of two INT8 slices
+// is below 2^14 and the INT32 accumulation is exact, so no windows: one
+// weight's sum over every pair and the whole K panel (at most 8192 k:
+// |U_t| < 8 * 8192 * 2^14 = 2^30) stays in the accumulators.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+constexpr int SKC8 = 128;  // k per chunk (INT8)
+
+__global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, int64_t kpad, int s,
+                                                        const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
+                                                        int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
+                                                        const int32_t* __restrict__ fb, double* __restrict__ Sws,
+                                                        double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                                        double gamma, const double* __restrict__ D, int64_t ldd) {
+  constexpr int LD = SKC8 + 2 * SPAD;  // bytes per LDS row: the BF16 kernel's 64 + 8 elements
+  __shared__ __attribute__((aligned(16))) union {
+    struct {
+      uint8_t A[2][SBM][LD];
+      uint8_t B[2][SBN][LD];
+    } st;
+    int32_t U[SBM * SBN];
+  } sm;
+  static_assert(sizeof(int32_t) * SBM * SBN <= 2 * (SBM + SBN) * LD, "fold buffer");
+  auto& As = sm.st.A;
+  auto& Bs = sm.st.B;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * SBM, n0 = (int64_t)blockIdx.x * SBN;
+  // each thread moves 64 bytes of A and of B per chunk: a 32-byte quarter lq of rows lr and lr + 64
+  const int lr = tid >> 2, lq = (tid & 3) * 32;
+  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+  const int nchunks = (int)(kpad / SKC8);
+  auto gload = [&](int p, int q, int cc) {
+    const uint8_t* pa = Ap + ((int64_t)(p - 1) * mpad + m0) * kpad + (int64_t)cc * SKC8 + lq;
+    const uint8_t* pb = Bp + ((int64_t)(q - 1) * npad + n0) * kpad + (int64_t)cc * SKC8 + lq;
+    const uint4* a0 = reinterpret_cast<const uint4*>(pa + (int64_t)lr * kpad);
+    const uint4* a1 = reinterpret_cast<const uint4*>(pa + (int64_t)(lr + 64) * kpad);
+    const uint4* b0 = reinterpret_cast<const uint4*>(pb + (int64_t)lr * kpad);
+    const uint4* b1 = reinterpret_cast<const uint4*>(pb + (int64_t)(lr + 64) * kpad);
+    ra0 = a0[0]; ra1 = a0[1]; ra2 = a1[0]; ra3 = a1[1];
+    rb0 = b0[0]; rb1 = b0[1]; rb2 = b1[0]; rb3 = b1[1];
+  };
+  auto lstore = [&](int buf) {
+    *reinterpret_cast<uint4*>(&As[buf][lr][lq]) = ra0;
+    *reinterpret_cast<uint4*>(&As[buf][lr][lq + 16]) = ra1;
+    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq]) = ra2;
+    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq + 16]) = ra3;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq]) = rb0;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq + 16]) = rb1;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq]) = rb2;
+    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq + 16]) = rb3;
+  };
+  const int fr = lane & 31, fk = 16 * (lane >> 5);
+  auto plo_of = [&](int t) { return t - s > 1 ? t - s : 1; };
+  {
+    const int t0 = s + 1;
+    gload(plo_of(t0), t0 - plo_of(t0), 0);
+    lstore(0);
+    __syncthreads();
+  }
+  for (int t = s + 1; t >= 2; --t) {
+    const int plo = plo_of(t), phi = t - 1 < s ? t - 1 : s;
+    const int np = phi - plo + 1;
+    i32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
+    // steps: the pairs (p, t-p) in turn, each over every chunk; the next step
+    // is prefetched into registers while this one multiplies
+    const int nsteps = np * nchunks;
+    int pi = 0, ci = 0;
+    for (int st = 0; st < nsteps; ++st) {
+      const int buf = st & 1;
+      int npi = pi, nci = ci + 1;
+      if (nci == nchunks) {
+        nci = 0;
+        ++npi;
+      }
+      const bool more = st + 1 < nsteps;
+      if (more) gload(plo + npi, t - (plo + npi), nci);
+#pragma unroll
+      for (int kk = 0; kk < SKC8; kk += 32) {
+        i32x4 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const i32x4*>(&As[buf][wm * 64 + i * 32 + fr][kk + fk]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const i32x4*>(&Bs[buf][wn * 64 + j * 32 + fr][kk + fk]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) lstore(buf ^ 1);
+      __syncthreads();
+      pi = npi;
+      ci = nci;
+    }
+    // prefetch the next weight's first step while the slice sums are added
+    if (t > 2) gload(plo_of(t - 1), (t - 1) - plo_of(t - 1), 0);
+    int32_t* Ul = sm.U;  // [SBM][SBN]
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+          Ul[(wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4)) * SBN + wn * 64 + j * 32 + (lane & 31)] =
+              acc[i][j][v];
+    __syncthreads();
+    slice_sum_update(Ul, t, s, 7, tid, m0, n0, m, n, npad, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
     __syncthreads();  // LDS is staging space again
     if (t > 2) {
       lstore(0);
@@ -390,67 +547,83 @@ inline int64_t pad128(int64_t x) { return (x + 127) / 128 * 128; }
 
 }  // namespace
 
-// Workspace: A planes [s][mp][kp], B planes [s][np][kp] (bf16), row and column
-// exponents (int32), column maxima (uint64), slice-sum tile [mp][np] (FP64),
-// with mp, np = m, n rounded up to 128 and kp = k rounded up to 64.
-size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s) {
-  const int64_t mp = pad128(m), np = pad128(n), kp = pad64(k < kSplitMaxK ? k : kSplitMaxK);
-  return (size_t)(2 * s * (mp + np) * kp + 4 * (mp + np) + 8 * np + 8 * mp * np);
+// Workspace: A planes [s][mp][kp], B planes [s][np][kp] (BF16 or INT8),
+// row and column exponents (int32), column maxima (uint64), slice-sum tile
+// [mp][np] (FP64), with mp, np = m, n rounded up to 128 and kp = k rounded up
+// to a whole number of 128-byte chunks (64 BF16 or 128 INT8 elements).
+static int64_t pad_k(int64_t k, SliceFormat f) { return f == kSliceInt8 ? pad128(k) : pad64(k); }
+
+size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat f) {
+  const int64_t mp = pad128(m), np = pad128(n), kp = pad_k(k < kSplitMaxK ? k : kSplitMaxK, f);
+  return (size_t)((int64_t)f * s * (mp + np) * kp + 4 * (mp + np) + 8 * np + 8 * mp * np);
 }
 
-static hipError_t split_panel(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
-                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
-                              const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream);
+static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
+                              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                              double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
+                              hipStream_t stream);
 
-hipError_t launch_split_gemm(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
-                             const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
-                             const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream) {
+hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                             double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
+                             hipStream_t stream) {
   // K panels of at most kSplitMaxK: C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (f != kSliceBF16 && f != kSliceInt8) return hipErrorInvalidValue;
   if (k <= kSplitMaxK)
-    return split_panel(m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, workspace, ws_bytes, stream);
+    return split_panel(f, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, workspace, ws_bytes, stream);
   for (int64_t k0 = 0; k0 < k; k0 += kSplitMaxK) {
     const int64_t kk = (k - k0) < kSplitMaxK ? (k - k0) : kSplitMaxK;
     const bool first = k0 == 0;
-    hipError_t e = split_panel(m, n, kk, s, alpha, A + k0, lda, B + k0 * ldb, ldb, first ? beta : 1.0, C, ldc,
+    hipError_t e = split_panel(f, m, n, kk, s, alpha, A + k0, lda, B + k0 * ldb, ldb, first ? beta : 1.0, C, ldc,
                                first ? gamma : 0.0, D, ldd, workspace, ws_bytes, stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-static hipError_t split_panel(int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A, int64_t lda,
-                              const double* B, int64_t ldb, double beta, double* C, int64_t ldc, double gamma,
-                              const double* D, int64_t ldd, void* workspace, size_t ws_bytes, hipStream_t stream) {
+static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
+                              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                              double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
+                              hipStream_t stream) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (s < 1 || s > 8) return hipErrorInvalidValue;
   if (k <= 0) return launch_dgemm_f64(m, n, 0, alpha, nullptr, 1, nullptr, 1, beta, C, ldc, gamma, D, ldd, stream);
-  const int64_t mp = pad128(m), np = pad128(n), kp = pad64(k);
-  if (split_workspace_bytes(m, n, k, s) > ws_bytes) return hipErrorInvalidValue;
-  uint16_t* Ap = static_cast<uint16_t*>(workspace);
-  uint16_t* Bp = Ap + (size_t)s * mp * kp;
-  int32_t* ea = reinterpret_cast<int32_t*>(Bp + (size_t)s * np * kp);
+  const int64_t mp = pad128(m), np = pad128(n), kp = pad_k(k, f);
+  if (split_workspace_bytes(m, n, k, s, f) > ws_bytes) return hipErrorInvalidValue;
+  const int eb = (int)f;
+  uint8_t* Ap = static_cast<uint8_t*>(workspace);
+  uint8_t* Bp = Ap + (size_t)eb * s * mp * kp;
+  int32_t* ea = reinterpret_cast<int32_t*>(Bp + (size_t)eb * s * np * kp);
   int32_t* fb = ea + mp;
   unsigned long long* bmax = reinterpret_cast<unsigned long long*>(fb + np);  // 8-byte aligned: mp, np even
   double* Sws = reinterpret_cast<double*>(bmax + np);
   if (gamma == 0.0) D = nullptr;
   const dim3 rows_grid((unsigned)(mp / 4)), cols_grid((unsigned)(kp / 64), (unsigned)(np / 64));
   auto slice_a = [&](auto S) {
-    hipLaunchKernelGGL(split_rows<decltype(S)::value>, rows_grid, dim3(256), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
+    constexpr int sv = decltype(S)::value;
+    if (f == kSliceInt8)
+      hipLaunchKernelGGL((split_rows<sv, 1>), rows_grid, dim3(256), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
+    else
+      hipLaunchKernelGGL((split_rows<sv, 2>), rows_grid, dim3(256), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
   };
   auto slice_b = [&](auto S) {
-    hipLaunchKernelGGL(split_cols<decltype(S)::value>, cols_grid, dim3(256), 0, stream, k, n, B, ldb, np, kp, fb, Bp);
+    constexpr int sv = decltype(S)::value;
+    if (f == kSliceInt8)
+      hipLaunchKernelGGL((split_cols<sv, 1>), cols_grid, dim3(256), 0, stream, k, n, B, ldb, np, kp, fb, Bp);
+    else
+      hipLaunchKernelGGL((split_cols<sv, 2>), cols_grid, dim3(256), 0, stream, k, n, B, ldb, np, kp, fb, Bp);
   };
-  auto with_s = [&](auto f) {
+  auto with_s = [&](auto fn) {
     switch (s) {
-      case 1: f(std::integral_constant<int, 1>{}); break;
-      case 2: f(std::integral_constant<int, 2>{}); break;
-      case 3: f(std::integral_constant<int, 3>{}); break;
-      case 4: f(std::integral_constant<int, 4>{}); break;
-      case 5: f(std::integral_constant<int, 5>{}); break;
-      case 6: f(std::integral_constant<int, 6>{}); break;
-      case 7: f(std::integral_constant<int, 7>{}); break;
-      default: f(std::integral_constant<int, 8>{}); break;
+      case 1: fn(std::integral_constant<int, 1>{}); break;
+      case 2: fn(std::integral_constant<int, 2>{}); break;
+      case 3: fn(std::integral_constant<int, 3>{}); break;
+      case 4: fn(std::integral_constant<int, 4>{}); break;
+      case 5: fn(std::integral_constant<int, 5>{}); break;
+      case 6: fn(std::integral_constant<int, 6>{}); break;
+      case 7: fn(std::integral_constant<int, 7>{}); break;
+      default: fn(std::integral_constant<int, 8>{}); break;
     }
   };
   with_s(slice_a);
@@ -460,8 +633,13 @@ static hipError_t split_panel(int64_t m, int64_t n, int64_t k, int s, double alp
                      k, n, B, ldb, bmax);
   hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
   with_s(slice_b);
-  hipLaunchKernelGGL(split_gemm, dim3((unsigned)(np / SBN), (unsigned)(mp / SBM)), dim3(256), 0, stream, m, n, kp, s,
-                     Ap, Bp, mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
+  const dim3 grid((unsigned)(np / SBN), (unsigned)(mp / SBM));
+  if (f == kSliceInt8)
+    hipLaunchKernelGGL(split_gemm_i8, grid, dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
+                       beta, C, ldc, gamma, D, ldd);
+  else
+    hipLaunchKernelGGL(split_gemm, grid, dim3(256), 0, stream, m, n, kp, s, reinterpret_cast<const uint16_t*>(Ap),
+                       reinterpret_cast<const uint16_t*>(Bp), mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
   return hipGetLastError();
 }
 
