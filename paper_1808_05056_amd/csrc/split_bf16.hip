@@ -88,13 +88,15 @@ __device__ __forceinline__ void slices_of(double r, int32_t e, uint32_t (&bits)[
   }
 }
 
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
 // One wave per row of A: exponent, then the S slices of the row into the
-// planes, 16 bytes of consecutive k per lane and step (one store per plane).
+// planes, 8 consecutive k per lane and step (one 8 * EB-byte store per plane).
 template <int S, int EB>
 __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const double* __restrict__ A, int64_t lda,
                                                   int64_t mpad, int64_t kpad, uint8_t* __restrict__ planes,
                                                   int32_t* __restrict__ ex_out) {
-  constexpr int E = 16 / EB, PER = 4 / EB;  // elements per lane and step, per 32-bit word
+  constexpr int E = 8, PER = 4 / EB, NW = E / PER;  // elements per lane and step, per 32-bit word; words
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= mpad) return;
@@ -114,13 +116,13 @@ __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const do
   }
   const int32_t ex = bad ? kBad : exponent_of(mx);
   if (lane == 0) ex_out[row] = ex;
-  // kpad is a multiple of 64 (BF16) or 128 (INT8), so a lane's E values never cross it
+  // kpad is a multiple of 64, so a lane's E values never cross it
   for (int64_t k0 = (int64_t)lane * E; k0 < kpad; k0 += 64 * E) {
-    uint32_t w[S][4];
+    uint32_t w[S][NW];
 #pragma unroll
     for (int p = 0; p < S; ++p)
 #pragma unroll
-      for (int x = 0; x < 4; ++x) w[p][x] = 0;
+      for (int x = 0; x < NW; ++x) w[p][x] = 0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
       const int64_t kk = k0 + q;
@@ -131,9 +133,13 @@ __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const do
       for (int p = 0; p < S; ++p) w[p][q / PER] |= b[p] << (8 * EB * (q % PER));
     }
 #pragma unroll
-    for (int p = 0; p < S; ++p)
-      *reinterpret_cast<u32x4*>(planes + (((int64_t)p * mpad + row) * kpad + k0) * EB) =
-          u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
+    for (int p = 0; p < S; ++p) {
+      uint8_t* dst = planes + (((int64_t)p * mpad + row) * kpad + k0) * EB;
+      if constexpr (EB == 2)
+        *reinterpret_cast<u32x4*>(dst) = u32x4{w[p][0], w[p][1], w[p][2], w[p][3]};
+      else
+        *reinterpret_cast<u32x2*>(dst) = u32x2{w[p][0], w[p][1]};
+    }
   }
 }
 
