@@ -17,7 +17,8 @@ device, Section VI).  This tool
           model, the network or the paper's rule would consider, and reports
           the regret t(choice) / t(best measured) - 1 of each planner;
   sweep   times the cost model's best candidates for one named workload (and
-          the model's, the network's and the paper's choices): the swept plan.
+          the model's, the network's and the paper's choices): the swept plan;
+          --precision split or split-int8 sweeps BF16 or INT8 slice plans.
 
     python -m paper_1808_05056_amd.planner_sweep train --out planner_mlp.txt
     python -m paper_1808_05056_amd.planner_sweep eval --weights planner_mlp.txt
@@ -81,8 +82,9 @@ def _key(p):
 
 
 def _opts(args, planner=ooc.PLAN_AUTO):
-    if args.precision == "split":
-        return ooc.make_opts(planner=planner, precision=ooc.SPLIT_BF16, slices=args.slices)
+    if args.precision in ("split", "split-int8"):
+        prec = ooc.SPLIT_BF16 if args.precision == "split" else ooc.SPLIT_INT8
+        return ooc.make_opts(planner=planner, precision=prec, slices=args.slices)
     return ooc.make_opts(planner=planner)
 
 
@@ -237,7 +239,7 @@ def sweep(args):
     import synth
     from synth import workloads as W
     w = W.BY_NAME[args.workload]
-    split = args.precision == "split"
+    split = args.precision != "fp64"
     if args.weights:
         ooc.ooc_mlp_load(args.weights)
     mats = [ooc.PinnedMatrix(w.M, w.K), ooc.PinnedMatrix(w.K, w.N), ooc.PinnedMatrix(w.M, w.N)]
@@ -306,7 +308,7 @@ def main(argv=None):
     e.add_argument("--report", default="planner_eval.json")
     sw = sub.add_parser("sweep")
     sw.add_argument("--workload", default="tall-262144x8192x8192-budget-2GiB")
-    sw.add_argument("--precision", choices=("fp64", "split"), default="fp64")
+    sw.add_argument("--precision", choices=("fp64", "split", "split-int8"), default="fp64")
     sw.add_argument("--slices", type=int, default=5)
     sw.add_argument("--top", type=int, default=12)
     sw.add_argument("--reps", type=int, default=2)
