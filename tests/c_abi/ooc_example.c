@@ -1,7 +1,8 @@
 /* A plain C caller of the library: a tiled out-of-core product through a
  * small budget, checked exactly (integer-valued data, every sum exact) against
- * a naive triple loop; then the same product from the split-BF16 form, whose
- * slices are exact for these small integers.  Prints "ok" on success. */
+ * a naive triple loop; then the same product from the split-BF16 and the
+ * split-INT8 forms, whose slices are exact for these small integers.  Prints
+ * "ok" on success. */
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -38,11 +39,11 @@ int main(void) {
       R[i * N + j] = 2.0 * s + 0.5 * C0[i * N + j];
     }
   const size_t budget = (size_t)1 << 20; /* below the 1.48 MB of the three operands */
-  for (int form = 0; form < 2; ++form) {
+  for (int form = 0; form < 3; ++form) {
     for (int64_t x = 0; x < M * N; ++x) C[x] = C0[x];
     ooc_opts o = {0};
-    if (form == 1) {
-      o.precision = OOC_SPLIT_BF16;
+    if (form > 0) {
+      o.precision = form == 1 ? OOC_SPLIT_BF16 : OOC_SPLIT_INT8;
       o.slices = 2;
     }
     ooc_stats st;

@@ -23,6 +23,8 @@ PLANS = [
     ("cols-1-stream", ooc.make_plan(256, 384, 640, ooc.ORDER_COLS, 2, 1, 2, 1), None),
     ("split-rowsps", ooc.make_plan(256, 256, 320, ooc.ORDER_ROWS_PS, 2, 2, 3, 3, precision=ooc.SPLIT_BF16,
                                    slices=4, group=2), None),
+    ("int8-colsp-staged-2s", ooc.make_plan(256, 192, 384, ooc.ORDER_COLS_P, 2, 2, 3, 2, precision=ooc.SPLIT_INT8,
+                                           slices=4, nbuf_d=1, group=2), None),
 ]
 
 
