@@ -1,4 +1,4 @@
-// FP64-accurate tile product from BF16 slices on CDNA4 matrix cores.
+// FP64-accurate tile product from BF16 or INT8 slices on CDNA4 matrix cores.
 //
 // The paper's DGEMM stage computes each tile in FP64 (Section V).  This is an
 // alternative for the same stage: the error-free splitting of a matrix
@@ -23,6 +23,11 @@
 //     multiply-add), C not read when beta == 0, D not read when gamma == 0.
 // A row or column holding a non-finite value gives NaN in its output row or
 // column.
+//
+// The INT8 form runs the same steps with digits m_p = trunc(r * 2^(7p - e_i))
+// (|m_p| <= 127, a signed byte) and weights 2^(e_i + f_j - 7t); its slice
+// products run on INT8 matrix cores with exact INT32 sums and need no
+// accumulation windows (split_gemm_i8).
 //
 // Workspace layout: see split_workspace_bytes (B planes are stored transposed
 // so MFMA operands are contiguous in k; all padding is zero).
