@@ -431,13 +431,34 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
 // INT8 slice products on V_MFMA_I32_32X32X32_I8 (lane l supplies A[l%32][16*(l/32) .. +16]
 // and B[16*(l/32) .. +16][l%32]; accumulator layout as for the BF16 form).  The
 // same tiling and staging as split_gemm, byte for byte: a 128-k chunk of INT8
-// planes is the 128 bytes of a 64-k BF16 chunk.  A product of two INT8 slices
+// planes is the 128 bytes of a 64-k BF16 chunk.  Tiles are dealt to XCDs in
+// bands of groups of 4 tile rows (xcd_band_tile): at twice the BF16 rate the
+// plane re-reads from beyond L2 matter (1633 against 1530 TOP/s at 8192^3).  A product of two INT8 slices
 // is below 2^14 and the INT32 accumulation is exact, so no windows: one
 // weight's sum over every pair and the whole K panel (at most 8192 k:
 // |U_t| < 8 * 8192 * 2^14 = 2^30) stays in the accumulators.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 constexpr int SKC8 = 128;  // k per chunk (INT8)
+constexpr int GM8 = 4;     // tile rows per group in the XCD bands of split_gemm_i8
+
+// Tile of workgroup b in a 1-D grid of tiles_m x tiles_n tiles: workgroups are
+// dealt to the 8 XCDs round robin, so b & 7 names the XCD; each XCD takes a
+// contiguous band of the tiles, walked in groups of gm_rows tile rows
+// (column by column inside a group), so the tiles running together on one
+// XCD share A and B plane rows in its L2.
+__device__ inline void xcd_band_tile(int b, int tiles_m, int tiles_n, int gm_rows, int* tm, int* tn) {
+  const int ntiles = tiles_m * tiles_n;
+  const int xcd = b & 7, local = b >> 3;
+  const int q = ntiles >> 3, r = ntiles & 7;
+  const int lin = xcd * q + (xcd < r ? xcd : r) + local;
+  const int group = lin / (gm_rows * tiles_n);
+  const int first_m = group * gm_rows;
+  const int gm = (tiles_m - first_m) < gm_rows ? (tiles_m - first_m) : gm_rows;
+  const int in_group = lin - group * gm_rows * tiles_n;
+  *tm = first_m + in_group % gm;
+  *tn = in_group / gm;
+}
 
 __global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, int64_t kpad, int s,
                                                         const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
@@ -458,7 +479,9 @@ __global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, in
   auto& Bs = sm.st.B;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * SBM, n0 = (int64_t)blockIdx.x * SBN;
+  int tm, tn;
+  xcd_band_tile((int)blockIdx.x, (int)(mpad / SBM), (int)(npad / SBN), GM8, &tm, &tn);
+  const int64_t m0 = (int64_t)tm * SBM, n0 = (int64_t)tn * SBN;
   // each thread moves 64 bytes of A and of B per chunk: a 32-byte quarter lq of rows lr and lr + 64
   const int lr = tid >> 2, lq = (tid & 3) * 32;
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
@@ -645,9 +668,9 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
   hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
   with_s(slice_b);
   const dim3 grid((unsigned)(np / SBN), (unsigned)(mp / SBM));
-  if (f == kSliceInt8)
-    hipLaunchKernelGGL(split_gemm_i8, grid, dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
-                       beta, C, ldc, gamma, D, ldd);
+  if (f == kSliceInt8)  // one-dimensional grid: the kernel maps workgroups to tiles in XCD bands
+    hipLaunchKernelGGL(split_gemm_i8, dim3(grid.x * grid.y), dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea,
+                       fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
   else
     hipLaunchKernelGGL(split_gemm, grid, dim3(256), 0, stream, m, n, kp, s, reinterpret_cast<const uint16_t*>(Ap),
                        reinterpret_cast<const uint16_t*>(Bp), mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
