@@ -211,6 +211,12 @@ def test_full_size_sampled(wname):
             assert stats.arena_bytes <= w.budget and stats.plan.precision == ooc.SPLIT_BF16
             err = check_rows(w, pp, sample_rows(w.M, stats.plan.mb, count=8, seed=2))
             _say(f"  split-BF16 normalised error {err:.2e}")
+            st, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget,
+                                     ooc.make_opts(precision=ooc.SPLIT_INT8, slices=6))
+            _say(f"  split-INT8 x6 plan {stats.plan} t={stats.t_total_s:.3f}s")
+            assert stats.arena_bytes <= w.budget and stats.plan.precision == ooc.SPLIT_INT8
+            err = check_rows(w, pp, sample_rows(w.M, stats.plan.mb, count=8, seed=3))
+            _say(f"  split-INT8 normalised error {err:.2e}")
     finally:
         pp.free()
 
@@ -226,6 +232,8 @@ DEGENERATE = [
     (2000, 17, 2000, 0.5, 0.0, 512 << 10, ooc.FP64),
     (1500, 1300, 1700, 1.0, 0.5, 3 << 20, ooc.SPLIT_BF16),
     (257, 3001, 129, 1.0, 0.5, 2 << 20, ooc.SPLIT_BF16),
+    (1500, 1300, 1700, 1.0, 0.5, 3 << 20, ooc.SPLIT_INT8),
+    (3001, 257, 130, -1.0, 0.0, 2 << 20, ooc.SPLIT_INT8),
 ]
 
 
@@ -236,8 +244,10 @@ def test_degenerate_shapes_small_budgets(case):
     w = W.Workload(f"degenerate{case}", M, N, K, alpha, beta, budget, seed=50 + case)
     pp = PinnedProblem(w, nan_c=(beta == 0.0))
     try:
+        # INT8 digits carry 7 bits: 7 slices for the margin 5 BF16 slices give
+        slices = 7 if prec == ooc.SPLIT_INT8 else 5
         st, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget,
-                                 ooc.make_opts(precision=prec, slices=5))
+                                 ooc.make_opts(precision=prec, slices=slices))
         assert stats.arena_bytes <= budget and stats.plan.precision == prec
         rows = np.arange(M) if M * N * K < 2e8 else sample_rows(M, stats.plan.mb)
         check_rows(w, pp, rows)
