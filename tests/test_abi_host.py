@@ -238,6 +238,18 @@ def test_argument_errors_before_device_access():
     bad = ooc.make_plan(0, 4, 8)
     with pytest.raises(ooc.OOCError):
         ooc.ooc_plan_footprint(4, 4, 8, 0.0, bad)
+    # the split tile products check their arguments before touching a device
+    for fn in (ooc._lib.ooc_split_gemm_device, ooc._lib.ooc_split_int8_gemm_device):
+        for s_bad in (0, 9):
+            st = fn(0, 4, 4, 4, s_bad, 1.0, A.ctypes.data, 4, B.ctypes.data, 4, 0.0, C.ctypes.data, 4, 1, None)
+            assert st == ooc.OOC_ERR_ARG and "slices" in ooc.ooc_last_error()
+        st = fn(0, 4, 4, 4, 6, 1.0, A.ctypes.data, 3, B.ctypes.data, 4, 0.0, C.ctypes.data, 4, 1, None)
+        assert st == ooc.OOC_ERR_ARG
+        assert fn(0, 0, 4, 4, 6, 1.0, None, 4, None, 4, 0.0, None, 4, 1, None) == ooc.OOC_OK
+    # a split plan with a slice count outside 1..8 or an unknown precision is refused
+    for prec, sl in ((ooc.SPLIT_INT8, 0), (ooc.SPLIT_INT8, 9), (3, 6)):
+        with pytest.raises(ooc.OOCError):
+            ooc.ooc_plan_footprint(64, 64, 64, 0.0, ooc.make_plan(32, 32, 32, precision=prec, slices=sl))
 
 
 SPLIT_PLANS = [
