@@ -274,6 +274,26 @@ __device__ __forceinline__ void slice_sum_update(const int32_t* Ul, int t, int s
   }
 }
 
+constexpr int kBandRows = 4;  // tile rows per group in the XCD bands of the slice-product kernels
+
+// Tile of workgroup b in a 1-D grid of tiles_m x tiles_n tiles: workgroups are
+// dealt to the 8 XCDs round robin, so b & 7 names the XCD; each XCD takes a
+// contiguous band of the tiles, walked in groups of gm_rows tile rows
+// (column by column inside a group), so the tiles running together on one
+// XCD share A and B plane rows in its L2.
+__device__ inline void xcd_band_tile(int b, int tiles_m, int tiles_n, int gm_rows, int* tm, int* tn) {
+  const int ntiles = tiles_m * tiles_n;
+  const int xcd = b & 7, local = b >> 3;
+  const int q = ntiles >> 3, r = ntiles & 7;
+  const int lin = xcd * q + (xcd < r ? xcd : r) + local;
+  const int group = lin / (gm_rows * tiles_n);
+  const int first_m = group * gm_rows;
+  const int gm = (tiles_m - first_m) < gm_rows ? (tiles_m - first_m) : gm_rows;
+  const int in_group = lin - group * gm_rows * tiles_n;
+  *tm = first_m + in_group % gm;
+  *tn = in_group / gm;
+}
+
 __device__ inline int fold_window_chunks(int t) { return t <= 3 ? 4 : (t <= 7 ? 2 : 1); }
 
 __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64_t kpad, int s,
@@ -295,7 +315,9 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
   auto& Bs = sm.st.B;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * SBM, n0 = (int64_t)blockIdx.x * SBN;
+  int tm, tn;
+  xcd_band_tile((int)blockIdx.x, (int)(mpad / SBM), (int)(npad / SBN), kBandRows, &tm, &tn);
+  const int64_t m0 = (int64_t)tm * SBM, n0 = (int64_t)tn * SBN;
   // global -> register staging: each thread moves 4 x 16 bytes of A and of B per
   // chunk: a 16-element quarter lq of rows lr and lr + 64 of the 64-k chunk
   const int lr = tid >> 2, lq = (tid & 3) * 16;
@@ -440,26 +462,6 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 constexpr int SKC8 = 128;  // k per chunk (INT8)
-constexpr int GM8 = 4;     // tile rows per group in the XCD bands of split_gemm_i8
-
-// Tile of workgroup b in a 1-D grid of tiles_m x tiles_n tiles: workgroups are
-// dealt to the 8 XCDs round robin, so b & 7 names the XCD; each XCD takes a
-// contiguous band of the tiles, walked in groups of gm_rows tile rows
-// (column by column inside a group), so the tiles running together on one
-// XCD share A and B plane rows in its L2.
-__device__ inline void xcd_band_tile(int b, int tiles_m, int tiles_n, int gm_rows, int* tm, int* tn) {
-  const int ntiles = tiles_m * tiles_n;
-  const int xcd = b & 7, local = b >> 3;
-  const int q = ntiles >> 3, r = ntiles & 7;
-  const int lin = xcd * q + (xcd < r ? xcd : r) + local;
-  const int group = lin / (gm_rows * tiles_n);
-  const int first_m = group * gm_rows;
-  const int gm = (tiles_m - first_m) < gm_rows ? (tiles_m - first_m) : gm_rows;
-  const int in_group = lin - group * gm_rows * tiles_n;
-  *tm = first_m + in_group % gm;
-  *tn = in_group / gm;
-}
-
 __global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, int64_t kpad, int s,
                                                         const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
                                                         int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
@@ -480,7 +482,7 @@ __global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, in
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   int tm, tn;
-  xcd_band_tile((int)blockIdx.x, (int)(mpad / SBM), (int)(npad / SBN), GM8, &tm, &tn);
+  xcd_band_tile((int)blockIdx.x, (int)(mpad / SBM), (int)(npad / SBN), kBandRows, &tm, &tn);
   const int64_t m0 = (int64_t)tm * SBM, n0 = (int64_t)tn * SBN;
   // each thread moves 64 bytes of A and of B per chunk: a 32-byte quarter lq of rows lr and lr + 64
   const int lr = tid >> 2, lq = (tid & 3) * 32;
@@ -667,10 +669,11 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
                      k, n, B, ldb, bmax);
   hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
   with_s(slice_b);
-  const dim3 grid((unsigned)(np / SBN), (unsigned)(mp / SBM));
-  if (f == kSliceInt8)  // one-dimensional grid: the kernel maps workgroups to tiles in XCD bands
-    hipLaunchKernelGGL(split_gemm_i8, dim3(grid.x * grid.y), dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea,
-                       fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
+  // one-dimensional grids: the kernels map workgroups to tiles in XCD bands
+  const dim3 grid((unsigned)((np / SBN) * (mp / SBM)));
+  if (f == kSliceInt8)
+    hipLaunchKernelGGL(split_gemm_i8, grid, dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
+                       beta, C, ldc, gamma, D, ldd);
   else
     hipLaunchKernelGGL(split_gemm, grid, dim3(256), 0, stream, m, n, kp, s, reinterpret_cast<const uint16_t*>(Ap),
                        reinterpret_cast<const uint16_t*>(Bp), mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
