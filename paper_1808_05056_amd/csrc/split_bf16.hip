@@ -280,7 +280,9 @@ constexpr int kBandRows = 4;  // tile rows per group in the XCD bands of the sli
 // dealt to the 8 XCDs round robin, so b & 7 names the XCD; each XCD takes a
 // contiguous band of the tiles, walked in groups of gm_rows tile rows
 // (column by column inside a group), so the tiles running together on one
-// XCD share A and B plane rows in its L2.
+// XCD share A and B plane rows in its L2.  The slice planes are re-read once
+// per pair and tile; groups of 4 rows measured best (INT8 kernel at 8192^3:
+// 1633 TOP/s against 1530 with the plain 2-D grid; groups of 8 gain nothing).
 __device__ inline void xcd_band_tile(int b, int tiles_m, int tiles_n, int gm_rows, int* tm, int* tn) {
   const int ntiles = tiles_m * tiles_n;
   const int xcd = b & 7, local = b >> 3;
@@ -453,15 +455,15 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
 // INT8 slice products on V_MFMA_I32_32X32X32_I8 (lane l supplies A[l%32][16*(l/32) .. +16]
 // and B[16*(l/32) .. +16][l%32]; accumulator layout as for the BF16 form).  The
 // same tiling and staging as split_gemm, byte for byte: a 128-k chunk of INT8
-// planes is the 128 bytes of a 64-k BF16 chunk.  Tiles are dealt to XCDs in
-// bands of groups of 4 tile rows (xcd_band_tile): at twice the BF16 rate the
-// plane re-reads from beyond L2 matter (1633 against 1530 TOP/s at 8192^3).  A product of two INT8 slices
-// is below 2^14 and the INT32 accumulation is exact, so no windows: one
-// weight's sum over every pair and the whole K panel (at most 8192 k:
+// planes is the 128 bytes of a 64-k BF16 chunk, and tiles are dealt to the
+// XCDs in the same bands (xcd_band_tile).  A product of two INT8 slices is
+// below 2^14 and the INT32 accumulation is exact, so no windows: one weight's
+// sum over every pair and the whole K panel (at most 8192 k:
 // |U_t| < 8 * 8192 * 2^14 = 2^30) stays in the accumulators.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 constexpr int SKC8 = 128;  // k per chunk (INT8)
+
 __global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, int64_t kpad, int s,
                                                         const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
                                                         int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
