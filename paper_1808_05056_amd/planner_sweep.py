@@ -15,7 +15,8 @@ device, Section VI).  This tool
           slice-count feature tells the two apart);
   eval    times every candidate of the evaluation batch (seed 4) that the cost
           model, the network or the paper's rule would consider, and reports
-          the regret t(choice) / t(best measured) - 1 of each planner;
+          the regret t(choice) / t(best measured) - 1 of each planner
+          (--precision split or split-int8: slice plans);
   sweep   times the cost model's best candidates for one named workload (and
           the model's, the network's and the paper's choices): the swept plan;
           --precision split or split-int8 sweeps BF16 or INT8 slice plans.
@@ -179,7 +180,7 @@ def evaluate(args):
         ooc.ooc_mlp_load(args.weights)
     problems = W.problem_batch(4, count=args.count)
     bufs = Buffers(problems)
-    split = args.precision == "split"
+    split = args.precision != "fp64"
     rows = []
     t0 = time.time()
     for idx, w in enumerate(problems):
@@ -289,8 +290,9 @@ def main(argv=None):
     f = sub.add_parser("fit")
     f.add_argument("--refeature", action="store_true", help="recompute features with the current cost model")
     e = sub.add_parser("eval")
+    t.add_argument("--precision", choices=("fp64", "split"), default="fp64")
+    e.add_argument("--precision", choices=("fp64", "split", "split-int8"), default="fp64")
     for q in (t, e):
-        q.add_argument("--precision", choices=("fp64", "split"), default="fp64")
         q.add_argument("--slices", type=int, default=5)
     for q in (t, f):
         q.add_argument("--hidden", type=int, default=64)
