@@ -196,8 +196,11 @@ def evaluate(args):
         all_plans, model_s = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget, _opts(args))
         # the network's own favourites (split: among the model's 16 best only)
         ranked = all_plans[:16] if split else all_plans
-        mlp_s = ooc.ooc_mlp_predict(w.M, w.N, w.K, w.beta, w.budget, ranked)
-        by_mlp = list(np.argsort(mlp_s)[: args.n_mlp])
+        if args.precision == "split-int8":  # the network declines INT8 plans (its choice is the model's)
+            by_mlp = []
+        else:
+            mlp_s = ooc.ooc_mlp_predict(w.M, w.N, w.K, w.beta, w.budget, ranked)
+            by_mlp = list(np.argsort(mlp_s)[: args.n_mlp])
         sweep = [all_plans[i] for i in range(min(args.n_model, len(all_plans)))]
         sweep += [ranked[i] for i in by_mlp]
         sweep += [pm, pl] + ([] if split else [pp])
