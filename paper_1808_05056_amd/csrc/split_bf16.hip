@@ -247,6 +247,10 @@ __device__ __forceinline__ void slice_sum_update(const int32_t* Ul, int t, int s
                                                  double* __restrict__ Sws, double alpha, double beta,
                                                  double* __restrict__ C, int64_t ldc, double gamma,
                                                  const double* __restrict__ D, int64_t ldd) {
+  // separate roundings: the products and sums below are not fused (the pragma
+  // covers operations written in this function; HIP's __dmul_rn / __dadd_rn
+  // inline plain operations from a header compiled with contraction on)
+#pragma clang fp contract(off)
   const int c = tid & (SBN - 1);
   const int64_t col = n0 + c;
   const int32_t ff = fb[col];
@@ -265,9 +269,9 @@ __device__ __forceinline__ void slice_sum_update(const int32_t* Ul, int t, int s
       if (bad) {
         val = __builtin_nan("");
       } else {
-        val = __dmul_rn(alpha, S);
-        if (beta != 0.0) val = __dadd_rn(val, __dmul_rn(beta, C[row * ldc + col]));
-        if (gamma != 0.0) val = __dadd_rn(val, __dmul_rn(gamma, D[row * ldd + col]));
+        val = alpha * S;
+        if (beta != 0.0) val = val + beta * C[row * ldc + col];
+        if (gamma != 0.0) val = val + gamma * D[row * ldd + col];
       }
       C[row * ldc + col] = val;
     }

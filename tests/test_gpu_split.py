@@ -44,6 +44,7 @@ CASES = [
     (33, 17, 5, 7, 1.0, 1.0, synth.UNIFORM, 0),
     (200, 150, 9000, 6, 1.0, 0.5, synth.NORMAL, 10),   # more than one 8192-k panel
     (300, 260, 2048, 2, 1.0, 0.0, synth.UNIFORM, 0),   # long exactness windows (t <= 3)
+    (131, 67, 257, 5, 0.75, -1.25, synth.NORMAL, 8),   # beta*C inexact: the final sums must not be fused
 ]
 
 

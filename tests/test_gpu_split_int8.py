@@ -140,3 +140,27 @@ def test_int8_pipeline_model_planner():
         assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
     finally:
         pp.free()
+
+
+@pytest.mark.parametrize("s", range(1, 9))
+def test_int8_every_slice_count_ragged(s):
+    # every slice count on a shape ragged in m, n and k (one partial tile and chunk each)
+    m, n, k = 131, 67, 257
+    A = np.ascontiguousarray(synth.matrix(m, k, synth.spec(400 + s, 0, synth.NORMAL, row_exp=(-8, 8))))
+    B = np.ascontiguousarray(synth.matrix(k, n, synth.spec(400 + s, 1, synth.NORMAL, col_exp=(-8, 8))))
+    C0 = np.ascontiguousarray(synth.matrix(m, n, synth.spec(400 + s, 2, synth.UNIFORM)))
+    _say(f"split-int8 s={s} ragged")
+    got = _device_split_i8(A, B, C0, 0.75, -1.25, s)
+    assert np.array_equal(got, split_ref.split_gemm(0.75, A, B, -1.25, C0, s, fmt="i8"))
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 300, 2), (300, 1, 3), (2, 2, 8192), (129, 1, 8193)])
+def test_int8_tiny_and_long_shapes(shape):
+    m, n, k = shape
+    A = np.ascontiguousarray(synth.matrix(m, k, synth.spec(500 + k, 0, synth.UNIFORM)))
+    B = np.ascontiguousarray(synth.matrix(k, n, synth.spec(500 + k, 1, synth.UNIFORM)))
+    C0 = np.zeros((m, n))
+    _say(f"split-int8 shape {shape}")
+    got = _device_split_i8(A, B, C0, 1.0, 0.0, 7)
+    want = split_ref.split_gemm(1.0, A, B, 0.0, None, 7, kb=8192 if k > 8192 else None, fmt="i8")
+    assert np.array_equal(got, want)
