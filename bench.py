@@ -73,6 +73,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=128, help="rows of C the CPU reference computes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile", type=int, default=1, help="time every op with HIP events in the timed steps")
+    ap.add_argument("--split-leg", type=int, default=1, help="1: also time the split-BF16 form (FP64 runs only)")
+    ap.add_argument("--split-slices", default="4,5,6",
+                    help="slice counts tried for the split leg, smallest first; the first to meet the gate is timed")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
                     help="only run the library's device copy kernel once on BYTES (traffic-counter reference)")
     args = ap.parse_args()
@@ -116,82 +119,40 @@ def main():
     # first call: checked against the CPU reference on sampled rows
     st, s1 = ooc.ooc_gemm(w.alpha, A, B, w.beta, C, w.budget, opts)
     plan = s1.plan
-    log(f"[bench] plan {plan}; first call {s1.t_total_s:.3f}s")
+    log(f"[bench] plan {plan}; first call {s1.t_total_s:.3f}s (planning {s1.t_plan_s * 1e3:.1f} ms)")
     cpu = None
-    err = None
+    ref = rows = D = Cin = None
+    err = (None, None)
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(0)
         rows = np.unique(np.concatenate([[0, w.M - 1], rng.integers(0, w.M, args.cpu_rows)]))[: args.cpu_rows]
-        Cin = None
         if w.beta != 0.0:
             Cin = np.empty((len(rows), w.N))
             synth.fill_rows(Cin, rows, w.spec_c())
         tc = time.time()
         ref, D = oracle.gemm_rows(w.alpha, A, B, w.beta, Cin, rows=rows)
         tcpu = time.time() - tc
-        err = oracle.normalized_error(C[rows], ref, oracle.gate_denominator(w.alpha, D, w.beta, Cin))
+        err = oracle.errors(C[rows], ref, w.alpha, D, w.beta, Cin)
         flops = 2.0 * len(rows) * w.N * w.K
         cpu = {"value": flops / tcpu / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(), "kind": "oracle",
                "sample": f"{len(rows)} of {w.M} rows of C ({flops:.3e} flop) in {tcpu:.1f}s; "
                          f"the same plain triple loop extrapolates to {tcpu * w.M / len(rows):.0f}s for the whole product"}
-        log(f"[bench] CPU reference: {len(rows)} rows in {tcpu:.1f}s, max normalised error {err:.3e}")
+        log(f"[bench] CPU reference: {len(rows)} rows in {tcpu:.1f}s, error literal {err[0]:.3e} "
+            f"generalised {err[1]:.3e}")
 
-    for i in range(args.warmup):
-        ooc.ooc_gemm_planned(w.alpha, A, B, w.beta, C, w.budget, plan, opts)
-        log(f"[bench] warmup {i + 1}/{args.warmup} done")
-    times, kbusy, hbusy, dbusy = [], 0.0, 0.0, 0.0
-    nkern = 0
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        _, s = ooc.ooc_gemm_planned(w.alpha, A, B, w.beta, C, w.budget, plan, popts)
-        times.append(s.t_total_s)
-        kbusy += s.t_kernel_busy_s
-        hbusy += s.t_h2d_busy_s
-        dbusy += s.t_d2h_busy_s
-        nkern += s.kernels
-        log(f"[bench] step {i + 1}/{args.steps}: {s.t_total_s:.3f}s {w.flops / s.t_total_s / 1e12:.2f} TFLOP/s")
-    elapsed = time.perf_counter() - t_start
-    ms = elapsed / args.steps * 1e3
-    value = w.flops * args.steps / elapsed / 1e12
+    leg = run_leg(ooc, w, A, B, C, opts, popts, args, prec, args.slices)
+    leg["first_call_plan_s"] = round(s1.t_plan_s, 6)
+    roof, link = leg.pop("roofline"), leg.pop("link")
+    e2e = leg.pop("end_to_end_roofline")
 
-    roof = None
-    if args.profile and kbusy > 0:
-        plan_tag = "{mb}x{nb}x{kb}/o{order}".format(**plan.as_dict())
-        if prec == ooc.FP64:
-            peak, work, kname = PEAK_FP64_TFLOPS, w.flops, "dgemm_f64_mfma"
-            traffic = measured_traffic(w.name, plan_tag)
-        else:  # BF16 or INT8 matrix work of the slice products (kernel time includes slicing)
-            peak, kname = ((PEAK_BF16_TFLOPS, "split_gemm") if prec == ooc.SPLIT_BF16
-                           else (PEAK_INT8_TOPS, "split_gemm_i8"))
-            work = w.flops * args.slices * (args.slices + 1) / 2
-            traffic = None
-        achieved = work * args.steps / kbusy / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TOP/s" if prec == ooc.SPLIT_INT8 else "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel_source": kernel_source_hash(KERNEL_SOURCES if prec == ooc.FP64 else SPLIT_SOURCES),
-                "plan_tag": plan_tag,
-                "kernel": kname, "launches_per_step": nkern // args.steps,
-                "avg_launch_ms": round(kbusy / nkern * 1e3, 4)}
-    link = None
-    if args.profile and hbusy > 0:
-        link = {"h2d_GBps": round(s1.bytes_h2d * args.steps / hbusy / 1e9, 2),
-                "d2h_GBps": round(s1.bytes_d2h * args.steps / dbusy / 1e9, 2) if dbusy > 0 else None,
-                "h2d_bytes_per_step": int(s1.bytes_h2d), "d2h_bytes_per_step": int(s1.bytes_d2h),
-                "h2d_busy_frac": round(hbusy / elapsed, 3), "kernel_busy_frac": round(kbusy / elapsed, 3),
-                "h2d_frac_of_link_peak": round(s1.bytes_h2d * args.steps / hbusy / 1e9 / LINK_PEAK_GBPS, 3)}
-    # end-to-end roofline: min(matrix peak, link peak x the plan's flops per host-to-device byte)
-    ai = w.flops / max(s1.bytes_h2d, 1)
-    compute_peak = (PEAK_FP64_TFLOPS if prec == ooc.FP64  # FP64-equivalent
-                    else (PEAK_BF16_TFLOPS if prec == ooc.SPLIT_BF16 else PEAK_INT8_TOPS)
-                    / (args.slices * (args.slices + 1) / 2))
-    e2e_roof = min(compute_peak, ai * LINK_PEAK_GBPS * 1e9 / 1e12)
-    e2e = {"tflops": round(e2e_roof, 3), "flop_per_h2d_byte": round(ai, 2), "link_peak_GBps": LINK_PEAK_GBPS,
-           "frac": round(value / e2e_roof, 4)}
+    split = None
+    if args.split_leg and prec == ooc.FP64:
+        split = split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin)
+
     out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 2), "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": leg["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": ("f64" if prec == ooc.FP64 else
                                                  f"split-{'bf16' if prec == ooc.SPLIT_BF16 else 'int8'}x{args.slices}"),
         "data": "synthetic (seeded counter-based generator)",
@@ -199,12 +160,128 @@ def main():
                    "budget_bytes": w.budget, "planner": args.planner, "plan": plan.as_dict(),
                    "arena_bytes": int(s1.arena_bytes), "parallelism": "single GPU"},
         "roofline": roof, "cpu_baseline": cpu, "link": link, "end_to_end_roofline": e2e,
-        "max_normalized_error": err, "predicted_s": round(s1.t_predicted_s, 4),
+        "max_error_literal": err[0], "max_normalized_error": err[1],
+        "timing": {"ci95_rel": leg["ci95_rel"], "planning_first_call_s": leg["first_call_plan_s"],
+                   "planning_per_step_s": leg["plan_s"], "overlap": leg["overlap"]},
+        "predicted_s": round(s1.t_predicted_s, 4),
+        "split_bf16": split,
     }
+    if split and split.get("value"):
+        out["split_vs_fp64"] = round(split["value"] / leg["value"], 4)
     print(json.dumps(out), flush=True)
     for m in (Am, Bm, Cm):
         m.free()
     ooc.ooc_release(-1)
+
+
+def ci95_rel(times):
+    """Half-width of the 95 % confidence interval of the mean step time (Student's t),
+    relative to the mean: the paper repeats until this is at most 2.5 % (Section VI)."""
+    n = len(times)
+    if n < 2:
+        return None
+    from scipy import stats as sst
+    m = float(np.mean(times))
+    sd = float(np.std(times, ddof=1))
+    return round(float(sst.t.ppf(0.975, n - 1)) * sd / np.sqrt(n) / m, 5)
+
+
+def run_leg(ooc, w, A, B, C, opts, popts, args, prec, slices):
+    """Warmup and timed steps of one form through ooc_gemm (planning included in
+    every step's time; the plan choice is cached after the first call)."""
+    for i in range(args.warmup):
+        ooc.ooc_gemm(w.alpha, A, B, w.beta, C, w.budget, opts)
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    times, kbusy, hbusy, dbusy, mbusy, tplan, ovl = [], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0
+    nkern = nmma = 0
+    s = None
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        _, s = ooc.ooc_gemm(w.alpha, A, B, w.beta, C, w.budget, popts)
+        times.append(time.perf_counter() - t0)
+        kbusy += s.t_kernel_busy_s
+        hbusy += s.t_h2d_busy_s
+        dbusy += s.t_d2h_busy_s
+        mbusy += s.t_mma_busy_s
+        nmma += s.mma_launches
+        tplan += s.t_plan_s
+        ovl += s.overlap
+        nkern += s.kernels
+        log(f"[bench] step {i + 1}/{args.steps}: {times[-1]:.3f}s {w.flops / times[-1] / 1e12:.2f} TFLOP/s")
+    elapsed = time.perf_counter() - t_start
+    value = w.flops * args.steps / elapsed / 1e12
+    plan = s.plan
+    roof = None
+    if args.profile and mbusy > 0:
+        plan_tag = "{mb}x{nb}x{kb}/o{order}".format(**plan.as_dict())
+        if prec == ooc.FP64:
+            peak, work, kname = PEAK_FP64_TFLOPS, w.flops, "dgemm_f64_mfma"
+            traffic = measured_traffic(w.name, plan_tag)
+        else:  # BF16 or INT8 matrix work of the slice products, slicing kernels excluded
+            peak, kname = ((PEAK_BF16_TFLOPS, "split_gemm") if prec == ooc.SPLIT_BF16
+                           else (PEAK_INT8_TOPS, "split_gemm_i8"))
+            work = w.flops * slices * (slices + 1) / 2
+            traffic = None
+        achieved = work * args.steps / mbusy / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TOP/s" if prec == ooc.SPLIT_INT8 else "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": traffic,
+                "kernel_source": kernel_source_hash(KERNEL_SOURCES if prec == ooc.FP64 else SPLIT_SOURCES),
+                "plan_tag": plan_tag, "kernel": kname, "launches_per_step": nmma // args.steps,
+                "avg_launch_ms": round(mbusy / nmma * 1e3, 4),
+                "op_busy_frac": round(kbusy / elapsed, 3)}
+    link = None
+    if args.profile and hbusy > 0:
+        link = {"h2d_GBps": round(s.bytes_h2d * args.steps / hbusy / 1e9, 2),
+                "d2h_GBps": round(s.bytes_d2h * args.steps / dbusy / 1e9, 2) if dbusy > 0 else None,
+                "h2d_bytes_per_step": int(s.bytes_h2d), "d2h_bytes_per_step": int(s.bytes_d2h),
+                "h2d_busy_frac": round(hbusy / elapsed, 3), "kernel_busy_frac": round(kbusy / elapsed, 3),
+                "h2d_frac_of_link_peak": round(s.bytes_h2d * args.steps / hbusy / 1e9 / LINK_PEAK_GBPS, 3)}
+    # end-to-end roofline: min(matrix peak, link peak x the plan's flops per host-to-device byte)
+    ai = w.flops / max(s.bytes_h2d, 1)
+    compute_peak = (PEAK_FP64_TFLOPS if prec == ooc.FP64  # FP64-equivalent
+                    else (PEAK_BF16_TFLOPS if prec == ooc.SPLIT_BF16 else PEAK_INT8_TOPS)
+                    / (slices * (slices + 1) / 2))
+    e2e_roof = min(compute_peak, ai * LINK_PEAK_GBPS * 1e9 / 1e12)
+    e2e = {"tflops": round(e2e_roof, 3), "flop_per_h2d_byte": round(ai, 2), "link_peak_GBps": LINK_PEAK_GBPS,
+           "frac": round(value / e2e_roof, 4)}
+    return {"value": round(value, 3), "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+            "ci95_rel": ci95_rel(times), "plan_s": round(tplan / args.steps, 6),
+            "overlap": round(ovl / args.steps, 4) if args.profile else None,
+            "plan": plan.as_dict(), "roofline": roof, "link": link, "end_to_end_roofline": e2e}
+
+
+def split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin):
+    """The split-BF16 form on the same workload and operands: the smallest slice
+    count (from --split-slices) whose result meets the gate on the oracle's
+    sampled rows (literal metric when beta == 0, generalised otherwise), timed
+    like the FP64 leg."""
+    import oracle
+    chosen, tried = None, []
+    for sl in (int(x) for x in args.split_slices.split(",")):
+        if w.beta != 0.0:
+            synth.fill(C, w.spec_c())
+        o = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=sl)
+        _, st = ooc.ooc_gemm(w.alpha, A, B, w.beta, C, w.budget, o)
+        lit, gen = oracle.errors(C[rows], ref, w.alpha, D, w.beta, Cin) if ref is not None else (None, None)
+        gated = lit if w.beta == 0.0 else gen
+        tried.append({"slices": sl, "error_literal": lit, "error_generalised": gen,
+                      "first_call_s": round(st.t_total_s, 4)})
+        log(f"[bench] split-BF16 s={sl}: plan {st.plan} {st.t_total_s:.3f}s error literal "
+            f"{lit if lit is None else f'{lit:.3e}'} generalised {gen if gen is None else f'{gen:.3e}'}")
+        if gated is not None and gated <= oracle.GATE:
+            chosen = (sl, lit, gen)
+            break
+    if chosen is None:
+        return {"value": None, "tried": tried, "note": "no slice count met the gate"}
+    sl = chosen[0]
+    o = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=sl)
+    po = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=sl, profile=bool(args.profile))
+    leg = run_leg(ooc, w, A, B, C, o, po, args, ooc.SPLIT_BF16, sl)
+    leg.update({"dtype": f"split-bf16x{sl}", "slices": sl, "error_literal": chosen[1],
+                "error_generalised": chosen[2], "tried": tried})
+    return leg
 
 
 if __name__ == "__main__":

@@ -129,6 +129,14 @@ typedef struct {
   double* timeline;     /* optional (profile == 1): receives start and end of op x, in seconds
                            from the first op's start, at timeline[2x] and timeline[2x+1] */
   int64_t timeline_cap; /* number of ops timeline can hold */
+  void* streams[3];     /* optional caller-owned hipStream_t (borrowed, never destroyed): pipeline
+                           stream x runs on streams[x] when it is not NULL, else on a stream the
+                           library owns.  The call still returns only after every stream it used
+                           has drained; work the caller queued on a borrowed stream before the call
+                           runs before the pipeline's first operation on that stream */
+  int32_t release_arena;/* 1: free the device arena before returning (every call allocates anew);
+                           0 (default): keep it cached for the next call on the device until
+                           ooc_release() -- saves the allocation on repeated calls */
 } ooc_opts;
 
 /* Outcome of a call. */
@@ -145,6 +153,15 @@ typedef struct {
   uint64_t arena_bytes;  /* device bytes used by the call (<= budget) */
   int64_t ops, tasks, kernels;
   int64_t blocks_done;   /* C blocks completely written back to the host */
+  double t_plan_s;       /* host time from entry until the operation list was ready: choosing the plan
+                            (unless given), its layout, the schedule and the cost model's prediction */
+  double overlap;        /* (profile == 1) fraction of the time some host-device copy was in flight
+                            during which a tile kernel ran too: the share of the transfers hidden
+                            behind computation (0 without profiling) */
+  double t_mma_busy_s;   /* (profile == 1) sum of the durations of the matrix-core kernels alone: the
+                            FP64 tile kernels, or the slice-product kernels of split plans without
+                            their slicing kernels */
+  int64_t mma_launches;  /* (profile == 1) number of those kernel launches */
 } ooc_stats;
 
 /* ---- the out-of-core product ---------------------------------------------------- */
@@ -152,7 +169,8 @@ typedef struct {
 /* C = alpha*A*B + beta*C through a device budget of budget_bytes.
  * All device memory the call uses (tile buffers and split workspace) is at most
  * budget_bytes; it is allocated for the call (or taken from opts->arena) and
- * cached for the next call on the device until ooc_release().
+ * cached for the next call on the device until ooc_release(), or freed before
+ * returning with opts->release_arena = 1.
  * Errors: OOC_ERR_ARG (negative sizes, ld too small, NULL operand with a
  * nonzero extent), OOC_ERR_BUDGET (nothing fits), OOC_ERR_DEVICE_MEM,
  * OOC_ERR_NOT_PINNED, OOC_ERR_NO_DEVICE, OOC_ERR_HIP.

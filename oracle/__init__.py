@@ -125,4 +125,16 @@ def normalized_error(C, Cref, D):
     return float(r.max()) if r.size else 0.0
 
 
+def errors(C, Cref, alpha, D_ab, beta, Cin):
+    """Both error figures of a result: (literal, generalised).
+
+    literal     max |C - Cref| / (|A||B|)_ij, the metric as the acceptance
+                criterion states it;
+    generalised max |C - Cref| / (|alpha| (|A||B|)_ij + |beta| |C_in|_ij)
+                (gate_denominator), which also accounts for the rounding of the
+                final addition alpha*S + beta*C."""
+    return (normalized_error(C, Cref, D_ab),
+            normalized_error(C, Cref, gate_denominator(alpha, D_ab, beta, Cin)))
+
+
 GATE = 1e-12  # normalised error bound every result must meet (denominator: gate_denominator)

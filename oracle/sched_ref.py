@@ -183,24 +183,74 @@ def check_hazards(ops):
     return bad
 
 
-def check_cover(ops, M, N, K):
-    """Every C element goes home exactly once and every (i, j, k) product term
-    is computed exactly once.  Returns a list of problems (empty = fine)."""
-    problems = []
-    home = np.zeros((M, N), dtype=np.int32)
+def _cells(ops, M, N):
+    """Row and column boundaries of every rectangle the ops touch in C: the
+    grid they form has cells that each op covers entirely or not at all."""
+    rb, cb = {0, M}, {0, N}
     for op in ops:
-        if op["kind"] == "d2h":
-            home[op["row0"]:op["row0"] + op["rows"], op["col0"]:op["col0"] + op["cols"]] += 1
-    if M * N and not np.all(home == 1):
-        problems.append(f"C elements returned {home.min()}..{home.max()} times")
-    if K > 0:
-        # count coverage of the k range for each C element by GEMM tasks
-        cov = np.zeros((M, N), dtype=np.int64)
-        for op in ops:
-            if op["kind"] in ("gemm", "split_gemm"):
-                cov[op["i0"]:op["i0"] + op["m"], op["j0"]:op["j0"] + op["n"]] += op["k"]
-        if M * N and not np.all(cov == K):
-            problems.append(f"k-coverage per C element ranges {cov.min()}..{cov.max()}, expected {K}")
+        if op["kind"] == "d2h" or op["kind"] in ("gemm", "split_gemm"):
+            r0, c0, r, c = _host_rect(op)
+            rb.update((r0, r0 + r))
+            cb.update((c0, c0 + c))
+    return sorted(x for x in rb if 0 <= x <= M), sorted(x for x in cb if 0 <= x <= N)
+
+
+def _host_rect(op):
+    """(row0, col0, rows, cols) of C that an op returns (d2h) or updates (GEMM)."""
+    if op["kind"] == "d2h":
+        return op["row0"], op["col0"], op["rows"], op["cols"]
+    return op["i0"], op["j0"], op["m"], op["n"]
+
+
+def check_cover(ops, M, N, K):
+    """Coverage of the result by an operation list.  Returns a list of
+    problems (empty = fine):
+      * every C element is returned to the host (d2h of mat 'C') exactly once;
+      * for every C element, the K ranges [k0, k0 + k) of the GEMM ops that
+        update it tile [0, K) exactly: no gap, no overlap, no repeat (so every
+        product term A_ik B_kj is added exactly once); with K == 0 every GEMM
+        op of the element has k == 0;
+      * the element's d2h is ordered after every GEMM op that updates it
+        (stream order and waits), so the host receives the finished value.
+    """
+    problems = []
+    rows, cols = _cells(ops, M, N)
+    reach = happens_before(ops)
+    gemms = [x for x, op in enumerate(ops) if op["kind"] in ("gemm", "split_gemm")]
+    homes = [x for x, op in enumerate(ops) if op["kind"] == "d2h" and op.get("mat", "C") == "C"]
+
+    def covers(op, r0, c0):
+        a, b, r, c = _host_rect(op)
+        return a <= r0 < a + r and b <= c0 < b + c
+
+    for ri in range(len(rows) - 1):
+        for ci in range(len(cols) - 1):
+            r0, c0 = rows[ri], cols[ci]
+            if rows[ri + 1] <= r0 or cols[ci + 1] <= c0:
+                continue
+            cell = f"C[{r0}:{rows[ri + 1]}, {c0}:{cols[ci + 1]}]"
+            home = [x for x in homes if covers(ops[x], r0, c0)]
+            if len(home) != 1:
+                problems.append(f"{cell} returned {len(home)} times")
+            ivs = sorted((ops[x]["k0"], ops[x]["k"], x) for x in gemms if covers(ops[x], r0, c0))
+            if K > 0:
+                at = 0
+                for k0, k, x in ivs:
+                    if k0 > at:
+                        problems.append(f"{cell}: k range [{at}, {k0}) not computed")
+                    elif k0 < at:
+                        problems.append(f"{cell}: k range [{k0}, {min(at, k0 + k)}) computed twice (op {x})")
+                    at = max(at, k0 + k)
+                if at < K:
+                    problems.append(f"{cell}: k range [{at}, {K}) not computed")
+                elif at > K:
+                    problems.append(f"{cell}: k range reaches {at} > K = {K}")
+            elif any(k != 0 for _, k, _ in ivs):
+                problems.append(f"{cell}: K = 0 but a GEMM op has k > 0")
+            for h in home:
+                for _, _, x in ivs:
+                    if not (reach[h] >> x) & 1:
+                        problems.append(f"{cell}: d2h op {h} is not ordered after GEMM op {x}")
     return problems
 
 

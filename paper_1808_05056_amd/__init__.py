@@ -57,14 +57,16 @@ P_dbl = ctypes.POINTER(ctypes.c_double)
 
 class ooc_opts(ctypes.Structure):
     _fields_ = [("device", i32), ("planner", i32), ("precision", i32), ("slices", i32), ("nstreams", i32),
-                ("profile", i32), ("arena", vp), ("arena_bytes", sz), ("timeline", P_dbl), ("timeline_cap", i64)]
+                ("profile", i32), ("arena", vp), ("arena_bytes", sz), ("timeline", P_dbl), ("timeline_cap", i64),
+                ("streams", vp * 3), ("release_arena", i32)]
 
 
 class ooc_stats(ctypes.Structure):
     _fields_ = [("plan", ooc_plan_t), ("t_total_s", dbl), ("t_pipeline_s", dbl), ("t_h2d_busy_s", dbl),
                 ("t_d2h_busy_s", dbl), ("t_kernel_busy_s", dbl), ("t_predicted_s", dbl), ("flops", dbl),
                 ("bytes_h2d", u64), ("bytes_d2h", u64), ("arena_bytes", u64), ("ops", i64), ("tasks", i64),
-                ("kernels", i64), ("blocks_done", i64)]
+                ("kernels", i64), ("blocks_done", i64), ("t_plan_s", dbl), ("overlap", dbl),
+                ("t_mma_busy_s", dbl), ("mma_launches", i64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "plan"}
@@ -166,9 +168,14 @@ def _mat_arg(X, name):
 
 
 def make_opts(device=0, planner=PLAN_AUTO, precision=FP64, slices=0, nstreams=0, profile=False, arena=None,
-              arena_bytes=0, timeline=None):
-    """timeline: a float64 numpy array of 2*nops entries to receive per-op start/end (profile mode)."""
+              arena_bytes=0, timeline=None, streams=None, release_arena=False):
+    """timeline: a float64 numpy array of 2*nops entries to receive per-op start/end (profile mode).
+    streams: up to three raw hipStream_t handles (ints) the pipeline borrows (None entries: the library's)."""
     o = ooc_opts(device, planner, precision, slices, nstreams, 1 if profile else 0, arena, arena_bytes, None, 0)
+    if streams is not None:
+        for x, h in enumerate(streams):
+            o.streams[x] = h
+    o.release_arena = 1 if release_arena else 0
     if timeline is not None:
         assert timeline.dtype == np.float64 and timeline.flags.c_contiguous
         o.timeline = timeline.ctypes.data_as(P_dbl)

@@ -44,6 +44,7 @@ struct DevCtx {
   hipStream_t st[3] = {nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> ev;   // dependency events (no timing)
   std::vector<hipEvent_t> tev;  // timing events (profile mode)
+  std::vector<hipEvent_t> kev;  // timing events around slice-product kernels alone (profile mode)
   void* arena = nullptr;
   size_t arena_bytes = 0;
 };
@@ -131,9 +132,38 @@ struct HostMats {
   double* C; int64_t ldc;
 };
 
-ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>& ops, double* arena,
-                   int64_t arena_elems, const HostMats& hm, bool profile, double* timeline, int64_t timeline_cap,
-                   ooc_stats* st) {
+// Length of the union of intervals [a, b).
+double union_length(std::vector<std::pair<double, double>> iv) {
+  std::sort(iv.begin(), iv.end());
+  double total = 0.0, lo = 0.0, hi = -1.0;
+  for (const auto& x : iv) {
+    if (x.first > hi) {
+      if (hi > lo) total += hi - lo;
+      lo = x.first;
+      hi = x.second;
+    } else {
+      hi = std::max(hi, x.second);
+    }
+  }
+  if (hi > lo) total += hi - lo;
+  return total;
+}
+
+// Fraction of the copy-busy time (union of copy intervals) during which a
+// kernel also ran: |U_copy ∩ U_kernel| / |U_copy| = (|U_c| + |U_k| - |U_c ∪ U_k|) / |U_c|.
+double overlap_fraction(const std::vector<std::pair<double, double>>& copies,
+                        const std::vector<std::pair<double, double>>& kernels) {
+  const double uc = union_length(copies);
+  if (uc <= 0.0) return 0.0;
+  std::vector<std::pair<double, double>> all(copies);
+  all.insert(all.end(), kernels.begin(), kernels.end());
+  const double both = uc + union_length(kernels) - union_length(all);
+  return std::max(0.0, std::min(1.0, both / uc));
+}
+
+ooc_status run_ops(DevCtx& c, hipStream_t* streams, const ooc_plan_t& plan, const std::vector<ooc_op>& ops,
+                   double* arena, int64_t arena_elems, const HostMats& hm, bool profile, double* timeline,
+                   int64_t timeline_cap, ooc_stats* st) {
   const size_t n = ops.size();
   std::vector<int> evidx(n, -1);
   size_t nev = 0;
@@ -142,8 +172,13 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
       if (evidx[o.wait[k]] < 0) evidx[o.wait[k]] = (int)nev++;
   ooc_status s0 = ensure_events(c.ev, nev, hipEventDisableTiming);
   if (s0 != OOC_OK) return s0;
+  // slice-product launches of each split op, for their kernel-only timing events
+  std::vector<int64_t> kfirst(n + 1, 0);
+  for (size_t x = 0; x < n; ++x)
+    kfirst[x + 1] = kfirst[x] + (ops[x].kind == OOC_OP_SPLIT_GEMM ? split_launches(ops[x].k) : 0);
   if (profile) {
     s0 = ensure_events(c.tev, 2 * n, hipEventDefault);
+    if (s0 == OOC_OK) s0 = ensure_events(c.kev, (size_t)(2 * kfirst[n]), hipEventDefault);
     if (s0 != OOC_OK) return s0;
   }
   const int fail_at = env_int("OOC_FAIL_AT", -1);
@@ -161,8 +196,8 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
     return rng;
   };
   if (stress_seed >= 0) {
-    hipError_t e = launch_fill_nan(arena, arena_elems, c.st[0]);
-    if (e == hipSuccess) e = hipStreamSynchronize(c.st[0]);
+    hipError_t e = launch_fill_nan(arena, arena_elems, streams[0]);
+    if (e == hipSuccess) e = hipStreamSynchronize(streams[0]);
     if (e != hipSuccess) return hip_fail(e, "poisoning the arena");
   }
   ooc_status status = OOC_OK;
@@ -177,7 +212,7 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
       msg = "failure injected at op " + std::to_string(x);
       break;
     }
-    hipStream_t s = c.st[o.stream];
+    hipStream_t s = streams[o.stream];
     hipError_t e = hipSuccess;
     for (int k = 0; k < o.nwait && e == hipSuccess; ++k) e = hipStreamWaitEvent(s, c.ev[evidx[o.wait[k]]], 0);
     if (e == hipSuccess && stress_seed >= 0 && next_rand() % 3 == 0)
@@ -210,11 +245,18 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
           e = launch_dgemm_f64(o.rows, o.cols, o.k, o.alpha, arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b,
                                o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d, s);
           break;
-        case OOC_OP_SPLIT_GEMM:
+        case OOC_OP_SPLIT_GEMM: {
+          KernelTimer kt;
+          if (profile) {
+            kt.events = c.kev.data() + 2 * kfirst[x];
+            kt.count = (int)(kfirst[x + 1] - kfirst[x]);
+          }
           e = launch_split_gemm(slice_format(plan.precision), o.rows, o.cols, o.k, plan.slices, o.alpha,
                                 arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b, o.beta, arena + o.off_c, o.ld_c,
-                                o.gamma, arena + o.off_d, o.ld_d, arena + o.off_w, (size_t)o.len_w * 8, s);
+                                o.gamma, arena + o.off_d, o.ld_d, arena + o.off_w, (size_t)o.len_w * 8, s,
+                                profile ? &kt : nullptr);
           break;
+        }
         default:
           status = OOC_ERR_ARG;
           msg = "unknown operation kind";
@@ -233,7 +275,7 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
   }
   // drain every stream, also after a failure, so no work outlives the call
   for (int k = 0; k < plan.nstreams; ++k) {
-    hipError_t e = hipStreamSynchronize(c.st[k]);
+    hipError_t e = hipStreamSynchronize(streams[k]);
     if (e != hipSuccess && status == OOC_OK) {
       status = OOC_ERR_HIP;
       msg = std::string("stream synchronise: ") + hipGetErrorString(e);
@@ -245,16 +287,45 @@ ooc_status run_ops(DevCtx& c, const ooc_plan_t& plan, const std::vector<ooc_op>&
     st->blocks_done = (status == OOC_OK || status == OOC_ERR_INJECTED) ? d2h_issued : 0;
     if (profile && status == OOC_OK) {
       double th = 0, td = 0, tk = 0;
+      std::vector<std::pair<double, double>> copies, kernels;
       for (size_t x = 0; x < issued; ++x) {
-        float ms = 0.f;
+        float ms = 0.f, a = 0.f, b = 0.f;
         if (hipEventElapsedTime(&ms, c.tev[2 * x], c.tev[2 * x + 1]) != hipSuccess) continue;
+        const bool copy = ops[x].kind == OOC_OP_H2D || ops[x].kind == OOC_OP_D2H;
         if (ops[x].kind == OOC_OP_H2D) th += ms * 1e-3;
         else if (ops[x].kind == OOC_OP_D2H) td += ms * 1e-3;
         else tk += ms * 1e-3;
+        if (hipEventElapsedTime(&a, c.tev[0], c.tev[2 * x]) == hipSuccess &&
+            hipEventElapsedTime(&b, c.tev[0], c.tev[2 * x + 1]) == hipSuccess)
+          (copy ? copies : kernels).emplace_back(a * 1e-3, b * 1e-3);
       }
       st->t_h2d_busy_s = th;
       st->t_d2h_busy_s = td;
       st->t_kernel_busy_s = tk;
+      st->overlap = overlap_fraction(copies, kernels);
+      // matrix-core kernels alone: FP64 tile kernels are whole ops; split ops
+      // count their slice-product launches without the slicing kernels
+      double tm = 0.0;
+      int64_t nm = 0;
+      for (size_t x = 0; x < issued; ++x) {
+        if (ops[x].kind == OOC_OP_GEMM) {
+          float ms = 0.f;
+          if (ops[x].k > 0 && hipEventElapsedTime(&ms, c.tev[2 * x], c.tev[2 * x + 1]) == hipSuccess) {
+            tm += ms * 1e-3;
+            ++nm;
+          }
+        } else if (ops[x].kind == OOC_OP_SPLIT_GEMM) {
+          for (int64_t y = kfirst[x]; y < kfirst[x + 1]; ++y) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c.kev[2 * y], c.kev[2 * y + 1]) == hipSuccess) {
+              tm += ms * 1e-3;
+              ++nm;
+            }
+          }
+        }
+      }
+      st->t_mma_busy_s = tm;
+      st->mma_launches = nm;
       if (timeline) {
         for (size_t x = 0; x < issued && (int64_t)x < timeline_cap; ++x) {
           float a = 0.f, b = 0.f;
@@ -315,6 +386,7 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
   st = build_schedule(pb, plan, lay, &ops);
   if (st != OOC_OK) return st;
   if (given) predicted = simulate(pb, plan, ops);
+  const double t_plan = now_s() - t_enter;
 
   const int dev = opts ? opts->device : 0;
   st = ensure_device(dev);
@@ -354,10 +426,22 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
     }
     arena = static_cast<double*>(c.arena);
   }
+  // pipeline streams: the caller's where given (borrowed), else the device's own
+  hipStream_t streams[3];
+  for (int x = 0; x < 3; ++x)
+    streams[x] = (opts && opts->streams[x]) ? static_cast<hipStream_t>(opts->streams[x]) : c.st[x];
   HostMats hm{A, lda, B, ldb, C, ldc};
-  st = run_ops(c, plan, ops, arena, (int64_t)(lay.bytes / 8), hm, opts && opts->profile,
+  st = run_ops(c, streams, plan, ops, arena, (int64_t)(lay.bytes / 8), hm, opts && opts->profile,
                opts ? opts->timeline : nullptr, opts ? opts->timeline_cap : 0, stats);
+  if (opts && opts->release_arena && !opts->arena && c.arena) {
+    // run_ops drained every stream it used, so nothing reads the arena any more
+    const hipError_t e = hipFree(c.arena);
+    c.arena = nullptr;
+    c.arena_bytes = 0;
+    if (e != hipSuccess && st == OOC_OK) st = hip_fail(e, "hipFree of the arena");
+  }
   if (stats) {
+    stats->t_plan_s = t_plan;
     stats->plan = plan;
     stats->t_total_s = now_s() - t_enter;
     stats->t_predicted_s = predicted;
@@ -592,8 +676,10 @@ ooc_status ooc_release(int32_t device) {
     c.arena_bytes = 0;
     for (hipEvent_t e : c.ev) (void)hipEventDestroy(e);
     for (hipEvent_t e : c.tev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c.kev) (void)hipEventDestroy(e);
     c.ev.clear();
     c.tev.clear();
+    c.kev.clear();
     for (int s = 0; s < 3; ++s) (void)hipStreamDestroy(c.st[s]);
     c.init = false;
   }

@@ -25,10 +25,20 @@ enum SliceFormat { kSliceInt8 = 1, kSliceBF16 = 2 };
 inline SliceFormat slice_format(int precision) { return precision == OOC_SPLIT_INT8 ? kSliceInt8 : kSliceBF16; }
 constexpr int64_t kSplitMaxK = 8192;
 size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat f);
+// Optional timing of the slice-product kernels alone (slicing kernels
+// excluded): events[2x] and events[2x+1] are recorded around the x-th
+// slice-product launch, for x < count; `used` counts the launches made.
+struct KernelTimer {
+  hipEvent_t* events = nullptr;
+  int count = 0;
+  int used = 0;
+};
+// Number of slice-product launches a split product over k makes.
+inline int64_t split_launches(int64_t k) { return k <= 0 ? 0 : (k + kSplitMaxK - 1) / kSplitMaxK; }
 hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                              double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                             hipStream_t stream);
+                             hipStream_t stream, KernelTimer* timer = nullptr);
 
 // The planner network (see mlp.hip): parameter count, scratch size (floats)
 // for a batch of n, forward pass into y, loss and gradient, one Adam step.

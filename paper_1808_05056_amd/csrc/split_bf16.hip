@@ -603,22 +603,23 @@ size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat
 static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                               double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                              hipStream_t stream);
+                              hipStream_t stream, KernelTimer* timer);
 
 hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                              double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                             hipStream_t stream) {
+                             hipStream_t stream, KernelTimer* timer) {
   // K panels of at most kSplitMaxK: C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C
   if (m <= 0 || n <= 0) return hipSuccess;
   if (f != kSliceBF16 && f != kSliceInt8) return hipErrorInvalidValue;
   if (k <= kSplitMaxK)
-    return split_panel(f, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, workspace, ws_bytes, stream);
+    return split_panel(f, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, workspace, ws_bytes, stream,
+                       timer);
   for (int64_t k0 = 0; k0 < k; k0 += kSplitMaxK) {
     const int64_t kk = (k - k0) < kSplitMaxK ? (k - k0) : kSplitMaxK;
     const bool first = k0 == 0;
     hipError_t e = split_panel(f, m, n, kk, s, alpha, A + k0, lda, B + k0 * ldb, ldb, first ? beta : 1.0, C, ldc,
-                               first ? gamma : 0.0, D, ldd, workspace, ws_bytes, stream);
+                               first ? gamma : 0.0, D, ldd, workspace, ws_bytes, stream, timer);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -627,7 +628,7 @@ hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int
 static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                               double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                              hipStream_t stream) {
+                              hipStream_t stream, KernelTimer* timer) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (s < 1 || s > 8) return hipErrorInvalidValue;
   if (k <= 0) return launch_dgemm_f64(m, n, 0, alpha, nullptr, 1, nullptr, 1, beta, C, ldc, gamma, D, ldd, stream);
@@ -677,13 +678,25 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
   with_s(slice_b);
   // one-dimensional grids: the kernels map workgroups to tiles in XCD bands
   const dim3 grid((unsigned)((np / SBN) * (mp / SBM)));
+  const bool timed = timer && timer->used < timer->count;
+  if (timed) {
+    const hipError_t e = hipEventRecord(timer->events[2 * timer->used], stream);
+    if (e != hipSuccess) return e;
+  }
   if (f == kSliceInt8)
     hipLaunchKernelGGL(split_gemm_i8, grid, dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
                        beta, C, ldc, gamma, D, ldd);
   else
     hipLaunchKernelGGL(split_gemm, grid, dim3(256), 0, stream, m, n, kp, s, reinterpret_cast<const uint16_t*>(Ap),
                        reinterpret_cast<const uint16_t*>(Bp), mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (timed) {
+    const hipError_t er = hipEventRecord(timer->events[2 * timer->used + 1], stream);
+    if (er != hipSuccess) return er;
+    ++timer->used;
+  }
+  return hipSuccess;
 }
 
 }  // namespace ooc

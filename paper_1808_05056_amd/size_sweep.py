@@ -35,8 +35,12 @@ def in_core_limit(budget_bytes):
     return n
 
 
-def measure(n, budget, reps=2, seed=7, planners=(("paper", ooc.PLAN_PAPER), ("model", ooc.PLAN_MODEL))):
-    """{planner name: (plan, best seconds, TFLOP/s)} for one square product of size n."""
+def measure(n, budget, reps=2, seed=7, planners=(("paper", ooc.PLAN_PAPER), ("model", ooc.PLAN_MODEL)),
+            check=None):
+    """{planner name: (plan, best seconds, TFLOP/s)} for one square product of size n.
+
+    check, if given, is called as check(planner_name, workload, A, B, C, plan)
+    after each planner's timed calls, with C holding that planner's result."""
     import synth
     from synth import workloads as W
     w = W.Workload(f"square-{n}", n, n, n, 1.0, 0.0, budget, seed=seed)
@@ -51,6 +55,8 @@ def measure(n, budget, reps=2, seed=7, planners=(("paper", ooc.PLAN_PAPER), ("mo
             _, s = ooc.ooc_gemm(1.0, A, B, 0.0, C, budget, opts)
             best = min(ooc.ooc_gemm(1.0, A, B, 0.0, C, budget, opts)[1].t_total_s for _ in range(reps))
             out[name] = (s.plan, best, w.flops / best / 1e12)
+            if check is not None:
+                check(name, w, A, B, C, s.plan)
         return out
     finally:
         for m in mats:

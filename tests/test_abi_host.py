@@ -420,3 +420,46 @@ def test_planner_sweep_refeature(tmp_path):
     assert np.array_equal(X, ooc.ooc_mlp_features(9000, 7000, 5000, 0.0, 1 << 30, plans[:5]))
     assert np.allclose(y, [r["seconds"] for r in meta])
     assert np.all(X[:, -1] == 5)  # the slice-count feature
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every field of the ABI structs sits at the same offset, and every struct
+    has the same size, in the ctypes binding as in include/ooc.h (compiled with
+    gcc): the binding marshals the new fields (borrowed streams, arena release,
+    planning time, overlap) where the library reads and writes them."""
+    import subprocess
+    structs = {"ooc_plan_t": ooc.ooc_plan_t, "ooc_opts": ooc.ooc_opts, "ooc_stats": ooc.ooc_stats,
+               "ooc_op": ooc.ooc_op}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ooc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", exe])
+    out = subprocess.check_output([exe], text=True).split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            s, f, v = ln.split()
+            got[(s, f)] = int(v)
+    import ctypes
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
+    for f in ("streams", "release_arena"):
+        assert f in dict(ooc.ooc_opts._fields_)
+    for f in ("t_plan_s", "overlap"):
+        assert f in dict(ooc.ooc_stats._fields_)
+
+
+def test_make_opts_borrowed_streams_and_release():
+    o = ooc.make_opts(streams=[0x1234, None, 0x5678], release_arena=True)
+    assert o.streams[0] == 0x1234 and not o.streams[1] and o.streams[2] == 0x5678
+    assert o.release_arena == 1
+    d = ooc.make_opts()
+    assert not any(d.streams) and d.release_arena == 0

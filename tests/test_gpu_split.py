@@ -12,7 +12,7 @@ import synth
 from oracle import split_ref
 from synth import workloads as W
 import paper_1808_05056_amd as ooc
-from gpu_helpers import PinnedProblem
+from gpu_helpers import PinnedProblem, gate_errors
 
 pytestmark = pytest.mark.gpu
 MiB = 1 << 20
@@ -60,7 +60,7 @@ def test_split_kernel_bit_exact_vs_split_reference(case):
     assert np.array_equal(got, want), np.max(np.abs(got - want))
     if s >= 6:
         ref, D = oracle.gemm_rows(alpha, A, B, beta, C0)
-        assert oracle.normalized_error(got, ref, oracle.gate_denominator(alpha, D, beta, C0)) <= oracle.GATE
+        gate_errors(got, ref, alpha, D, beta, C0)
 
 
 def test_split_chunk_sums_exact_at_largest_slices():
@@ -88,7 +88,7 @@ def test_split_nonfinite_rows_and_columns_give_nan():
     assert np.all(np.isnan(got[3])) and np.all(np.isnan(got[:, 9]))
     mask = np.ones((m, n), bool); mask[3] = False; mask[:, 9] = False
     ref, D = oracle.gemm_rows(1.0, A, B, 0.0, None)
-    assert oracle.normalized_error(got[mask], ref[mask], D[mask]) <= oracle.GATE
+    gate_errors(got[mask], ref[mask], 1.0, D[mask], 0.0, None)
 
 
 @pytest.mark.parametrize("planner", ["paper", "ksplit"])
@@ -110,7 +110,7 @@ def test_split_pipeline_bit_exact(planner):
         want = split_ref.split_gemm(w.alpha, pp.A, pp.B, w.beta, C0, 6, kb=kb)
         assert np.array_equal(pp.C, want)
         ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
-        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
+        gate_errors(pp.C, ref, w.alpha, D, w.beta, C0)
     finally:
         pp.free()
 
@@ -124,7 +124,7 @@ def test_split_pipeline_model_planner_staged():
                                  ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=7))
         assert stats.arena_bytes <= w.budget
         ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
-        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
+        gate_errors(pp.C, ref, w.alpha, D, w.beta, C0)
     finally:
         pp.free()
 
@@ -157,6 +157,6 @@ def test_split_pipeline_edge_cases(case):
                                     np.zeros_like(C0) if Cin is None else Cin, 6, kb=320)
         assert np.array_equal(pp.C, want)
         ref, D = oracle.gemm_rows(alpha, np.array(pp.A), np.array(pp.B), beta, Cin)
-        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(alpha, D, beta, Cin)) <= oracle.GATE
+        gate_errors(pp.C, ref, alpha, D, beta, Cin)
     finally:
         pp.free()

@@ -13,7 +13,7 @@ import synth
 from oracle import split_ref
 from synth import workloads as W
 import paper_1808_05056_amd as ooc
-from gpu_helpers import PinnedProblem
+from gpu_helpers import PinnedProblem, gate_errors
 
 pytestmark = pytest.mark.gpu
 MiB = 1 << 20
@@ -60,7 +60,7 @@ def test_int8_kernel_bit_exact_vs_split_reference(case):
     assert np.array_equal(got, want), np.max(np.abs(got - want))
     if s >= (6 if dist == synth.UNIFORM else 7):
         ref, D = oracle.gemm_rows(alpha, A, B, beta, C0)
-        assert oracle.normalized_error(got, ref, oracle.gate_denominator(alpha, D, beta, C0)) <= oracle.GATE
+        gate_errors(got, ref, alpha, D, beta, C0)
 
 
 def test_int8_largest_digits_and_weight_sums():
@@ -88,7 +88,7 @@ def test_int8_nonfinite_rows_and_columns_give_nan():
     assert np.all(np.isnan(got[3])) and np.all(np.isnan(got[:, 9]))
     mask = np.ones((m, n), bool); mask[3] = False; mask[:, 9] = False
     ref, D = oracle.gemm_rows(1.0, A, B, 0.0, None)
-    assert oracle.normalized_error(got[mask], ref[mask], D[mask]) <= oracle.GATE
+    gate_errors(got[mask], ref[mask], 1.0, D[mask], 0.0, None)
 
 
 def test_int8_k_zero_and_alpha_zero():
@@ -122,7 +122,7 @@ def test_int8_pipeline_bit_exact(planner):
         want = split_ref.split_gemm(w.alpha, pp.A, pp.B, w.beta, C0, 7, kb=kb, fmt="i8")
         assert np.array_equal(pp.C, want)
         ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
-        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
+        gate_errors(pp.C, ref, w.alpha, D, w.beta, C0)
     finally:
         pp.free()
 
@@ -137,7 +137,7 @@ def test_int8_pipeline_model_planner():
                                  ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_INT8, slices=7))
         assert stats.arena_bytes <= w.budget and stats.plan.precision == ooc.SPLIT_INT8
         ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
-        assert oracle.normalized_error(pp.C, ref, oracle.gate_denominator(w.alpha, D, w.beta, C0)) <= oracle.GATE
+        gate_errors(pp.C, ref, w.alpha, D, w.beta, C0)
     finally:
         pp.free()
 

@@ -157,3 +157,84 @@ def test_cycle_or_forward_wait_rejected():
            dict(kind="h2d", mat="C", stream=1, task=0, waits=[], row0=0, col0=0, rows=1, cols=1, dev_off=0, dev_ld=1)]
     with pytest.raises(ValueError):
         sched_ref.happens_before(ops)
+
+
+# ---- check_cover must reject lists that lose, repeat or misorder work ------------------
+
+def _ksplit_pipeline():
+    """One stream, a 2 x 2 grid of C blocks, K split into three panels of 4, 3
+    and 5: every C block gets three GEMM ops and one d2h."""
+    M, N, K = 6, 4, 12
+    mb, nb = 3, 2
+    panels = [(0, 4), (4, 3), (7, 5)]
+    offA, offB, offC = 0, mb * K, mb * K + K * nb
+    ops = []
+    for i in range(2):
+        for j in range(2):
+            ops.append(dict(kind="h2d", mat="C", stream=0, task=0, waits=[], row0=i * mb, col0=j * nb, rows=mb,
+                            cols=nb, dev_off=offC, dev_ld=nb))
+            for k0, k in panels:
+                ops.append(dict(kind="h2d", mat="A", stream=0, task=0, waits=[], row0=i * mb, col0=k0, rows=mb,
+                                cols=k, dev_off=offA, dev_ld=k))
+                ops.append(dict(kind="h2d", mat="B", stream=0, task=0, waits=[], row0=k0, col0=j * nb, rows=k,
+                                cols=nb, dev_off=offB, dev_ld=nb))
+                ops.append(dict(kind="gemm", stream=0, task=0, waits=[], m=mb, n=nb, k=k, i0=i * mb, j0=j * nb,
+                                k0=k0, off_a=offA, lda=k, off_b=offB, ldb=nb, off_c=offC, ldc=nb, alpha=1.0,
+                                beta=1.0))
+            ops.append(dict(kind="d2h", mat="C", stream=0, task=0, waits=[], row0=i * mb, col0=j * nb, rows=mb,
+                            cols=nb, dev_off=offC, dev_ld=nb))
+    return ops, M, N, K, offC + mb * nb
+
+
+def test_cover_accepts_a_k_split_pipeline():
+    ops, M, N, K, arena = _ksplit_pipeline()
+    assert sched_ref.check_cover(ops, M, N, K) == []
+    A, B, C = _problem(M, N, K, 6)
+    want, _ = oracle.gemm_rows(1.0, A, B, 1.0, C)
+    Cw = C.copy()
+    sched_ref.execute(ops, A, B, Cw, arena)
+    assert np.array_equal(Cw, want)
+
+
+def test_cover_catches_a_dropped_d2h():
+    ops, M, N, K, _ = _ksplit_pipeline()
+    last = max(x for x, o in enumerate(ops) if o["kind"] == "d2h")
+    bad = sched_ref.check_cover(ops[:last] + ops[last + 1:], M, N, K)
+    assert any("returned 0 times" in p for p in bad), bad
+
+
+def test_cover_catches_a_duplicated_d2h():
+    ops, M, N, K, _ = _ksplit_pipeline()
+    first = min(x for x, o in enumerate(ops) if o["kind"] == "d2h")
+    bad = sched_ref.check_cover(ops + [dict(ops[first])], M, N, K)
+    assert any("returned 2 times" in p for p in bad), bad
+
+
+def test_cover_catches_a_missing_k_panel():
+    ops, M, N, K, _ = _ksplit_pipeline()
+    x = [x for x, o in enumerate(ops) if o["kind"] == "gemm"][4]  # block (0, 1), panel [4, 7)
+    bad = sched_ref.check_cover(ops[:x] + ops[x + 1:], M, N, K)
+    assert any("[4, 7) not computed" in p for p in bad), bad
+
+
+def test_cover_catches_a_repeated_panel_that_keeps_the_k_total():
+    # the middle panel of block (0, 0) is moved from [4, 7) to [0, 3): every C element still
+    # sums k = 12, but [0, 3) is added twice and [4, 7) never
+    ops, M, N, K, _ = _ksplit_pipeline()
+    gx = [x for x, o in enumerate(ops) if o["kind"] == "gemm"][:3]  # block (0, 0)
+    ops = [dict(o) for o in ops]
+    ops[gx[1]]["k0"] = 0
+    total = sum(ops[x]["k"] for x in gx)
+    assert total == K  # a check that only sums k per element would pass this list
+    bad = sched_ref.check_cover(ops, M, N, K)
+    assert any("computed twice" in p for p in bad) and any("[4, 7) not computed" in p for p in bad), bad
+
+
+def test_cover_catches_a_d2h_before_the_last_panel():
+    ops, M, N, K, _ = _ksplit_pipeline()
+    # move block (1, 1)'s d2h in front of its last GEMM on the same stream
+    d = max(x for x, o in enumerate(ops) if o["kind"] == "d2h")
+    g = max(x for x, o in enumerate(ops) if o["kind"] == "gemm")
+    moved = ops[:g] + [ops[d]] + ops[g:d] + ops[d + 1:]
+    bad = sched_ref.check_cover(moved, M, N, K)
+    assert any("not ordered after GEMM" in p for p in bad), bad

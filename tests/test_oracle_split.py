@@ -222,3 +222,30 @@ def test_int8_panels_and_alpha_beta():
     for kb in (None, 32, 7):
         got = split_ref.split_gemm(1.5, A, B, 0.5, C, s=8, kb=kb, fmt="i8")
         assert oracle.normalized_error(got, ref, D) < 1e-14
+
+
+def test_bf16_truncation_bound_is_not_vacuous():
+    # random data: at s = 2 the error reaches more than a thousandth of the bound somewhere
+    M, N, K = 3, 4, 24
+    A = _mat(M, K, 5, 0, row_exp=(-5, 5))
+    B = _mat(K, N, 5, 1, col_exp=(-5, 5))
+    exact = [[sum(Fraction(A[i, k]) * Fraction(B[k, j]) for k in range(K)) for j in range(N)] for i in range(M)]
+    got = split_ref.split_gemm(1.0, A, B, 0.0, None, s=2)
+    bound = split_ref.truncation_bound(A, B, 2)
+    worst = max(abs(Fraction(got[i, j]) - exact[i][j]) / Fraction(bound[i, j]) for i in range(M) for j in range(N))
+    assert Fraction(1, 1000) < worst <= 1
+
+
+@pytest.mark.parametrize("K", [1, 16])
+def test_bf16_truncation_bound_is_tight_on_adversarial_digits(K):
+    # v = 2^-1 + 2^-9 + ... + 2^-49 slices into 129, -127, -127, ...: the dropped pairs of one
+    # weight all carry the same sign and add up, so the error reaches a quarter of the bound
+    # at s = 1 and s = 6.  A bound with 2^(-7s) for BF16 slices, or without the factor k or
+    # (s + 1), fails this test.
+    v = sum(2.0 ** (-1 - 8 * p) for p in range(7))
+    A, B = np.full((1, K), v), np.full((K, 1), v)
+    exact = Fraction(v) * Fraction(v) * K
+    for s in (1, 6):
+        got = split_ref.split_gemm(1.0, A, B, 0.0, None, s=s)
+        ratio = abs(Fraction(got[0, 0]) - exact) / Fraction(split_ref.truncation_bound(A, B, s)[0, 0])
+        assert Fraction(1, 8) < ratio <= 1, (s, float(ratio))
