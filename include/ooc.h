@@ -263,6 +263,56 @@ ooc_status ooc_schedule(int64_t M, int64_t N, int64_t K, double alpha, double be
                         const ooc_plan_t* plan, ooc_op* ops, int64_t cap, int64_t* nops,
                         uint64_t* arena_bytes);
 
+/* ---- accumulation sessions: repeated invocation ----------------------------------
+ * The paper's MMOOC can serve as the local step of an outer algorithm (SUMMA or
+ * HSUMMA, Section V: the step/nsteps logic of Fig. 2): over steps s = 0..S-1
+ * it adds alpha_s * A_s * B_s to C, reading C at the first step only and
+ * writing back the blocks still on the device after the last step.  A session
+ * computes
+ *     C = beta * C_in + sum over steps of alpha_s * A_s * B_s
+ * (A_s M x K_s, B_s K_s x N, row-major, page-locked; K_s may differ per
+ * step), each step rounded as C = alpha_s * A_s B_s + C.  The first R rows of
+ * C (ooc_accum_resident_rows: all of C when it takes at most half the budget,
+ * else as many rows as fit in half, a multiple of 128 from 128 on) stay on the
+ * device for the whole session: loaded once at ooc_accum_begin (if beta != 0),
+ * updated in place by every step and written back once by ooc_accum_end.
+ * The remaining rows are streamed through the rest of the budget by the
+ * ordinary pipeline at every step (read and written back).  The session
+ * allocates budget_bytes of device memory at begin and frees it at end.
+ * Host C must stay valid and untouched by the caller until ooc_accum_end;
+ * A_s and B_s only during their step.  Rows >= R of C hold the running sum
+ * after each step; rows < R only after ooc_accum_end.  Steps and end are
+ * synchronous.  On an error inside a step C is unspecified; the session must
+ * still be ended (which frees it). */
+typedef struct ooc_accum_s* ooc_accum;
+
+/* Open a session for C (M x N, page-locked, leading dimension ldc >= N).
+ * Errors as ooc_gemm (OOC_ERR_DEVICE_MEM if budget_bytes exceeds the free
+ * device memory).  opts as for ooc_gemm (the timeline and arena are ignored). */
+ooc_status ooc_accum_begin(int64_t M, int64_t N, double beta, double* C, int64_t ldc, size_t budget_bytes,
+                           const ooc_opts* opts, ooc_accum* out);
+
+/* One step: C += alpha * A * B with A (M x K, lda >= K) and B (K x N, ldb >= N).
+ * alpha == 0 or K == 0 leave C unchanged (beta is applied at the first step). */
+ooc_status ooc_accum_step(ooc_accum acc, int64_t K, double alpha, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, ooc_stats* stats);
+
+/* Write the resident rows back and free the session (also after an error).
+ * A session without steps returns C = beta * C_in. */
+ooc_status ooc_accum_end(ooc_accum acc, ooc_stats* stats);
+
+/* Rows of C a session of this size keeps on the device (host only). */
+ooc_status ooc_accum_resident_rows(int64_t M, int64_t N, size_t budget_bytes, int64_t* rows);
+
+/* The operation lists of one session step (host only): part 0 updates the
+ * resident rows [0, R) in place (C at arena element 0, leading dimension N;
+ * no C copies), part 1 streams rows [R, M) through buffers placed after
+ * them (its host rows count from row R).  beta_eff is beta at the first
+ * step and 1 afterwards.  A part with no rows returns *nops = 0. */
+ooc_status ooc_accum_schedule(int64_t M, int64_t N, int64_t K, double alpha, double beta_eff, size_t budget_bytes,
+                              const ooc_opts* opts, int32_t part, ooc_op* ops, int64_t cap, int64_t* nops,
+                              uint64_t* arena_bytes);
+
 /* ---- memory helpers ----------------------------------------------------------- */
 
 ooc_status ooc_host_alloc(void** ptr, size_t bytes);  /* page-locked host memory */

@@ -202,10 +202,12 @@ def _host_rect(op):
     return op["i0"], op["j0"], op["m"], op["n"]
 
 
-def check_cover(ops, M, N, K):
+def check_cover(ops, M, N, K, returns_home=True):
     """Coverage of the result by an operation list.  Returns a list of
     problems (empty = fine):
-      * every C element is returned to the host (d2h of mat 'C') exactly once;
+      * every C element is returned to the host (d2h of mat 'C') exactly once
+        (with returns_home=False, for C that stays on the device between the
+        steps of an accumulation session: never);
       * for every C element, the K ranges [k0, k0 + k) of the GEMM ops that
         update it tile [0, K) exactly: no gap, no overlap, no repeat (so every
         product term A_ik B_kj is added exactly once); with K == 0 every GEMM
@@ -230,7 +232,7 @@ def check_cover(ops, M, N, K):
                 continue
             cell = f"C[{r0}:{rows[ri + 1]}, {c0}:{cols[ci + 1]}]"
             home = [x for x in homes if covers(ops[x], r0, c0)]
-            if len(home) != 1:
+            if len(home) != (1 if returns_home else 0):
                 problems.append(f"{cell} returned {len(home)} times")
             ivs = sorted((ops[x]["k0"], ops[x]["k"], x) for x in gemms if covers(ops[x], r0, c0))
             if K > 0:
@@ -254,16 +256,22 @@ def check_cover(ops, M, N, K):
     return problems
 
 
-def execute(ops, A, B, C, arena_elems, seed=0, poison=np.nan, kernels=None):
+def execute(ops, A, B, C, arena_elems, seed=0, poison=np.nan, kernels=None, arena=None):
     """Run the operation list on the CPU.
 
     Ops are taken in a random order that respects stream order and waits.  The
-    device arena starts filled with `poison`.  GEMM ops compute
+    device arena starts filled with `poison`, unless an existing arena (a
+    float64 array of at least arena_elems entries) is passed, which is then
+    used and updated in place (device memory that outlives one operation
+    list, as in an accumulation session).  GEMM ops compute
     alpha*a@b + beta*c on the arena views (beta == 0: c is not read).  Other
     kernel kinds are run by kernels[kind](op, arena) when given.
     C (host) is updated in place by the d2h ops.
     """
-    arena = np.full(arena_elems, poison, dtype=np.float64)
+    if arena is None:
+        arena = np.full(arena_elems, poison, dtype=np.float64)
+    elif arena.shape[0] < arena_elems:
+        raise ValueError("arena smaller than the operation list needs")
     host = {"A": A, "B": B, "C": C}
     preds = predecessors(ops)
     n = len(ops)

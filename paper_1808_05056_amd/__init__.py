@@ -102,6 +102,11 @@ _sig("ooc_plan_candidates", i32, [i64, i64, i64, dbl, sz, P(ooc_opts), P(ooc_pla
 _sig("ooc_plan_predict", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(dbl)])
 _sig("ooc_plan_simulate", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(dbl), i64, P(i64)])
 _sig("ooc_schedule", i32, [i64, i64, i64, dbl, dbl, P(ooc_plan_t), P(ooc_op), i64, P(i64), P(u64)])
+_sig("ooc_accum_begin", i32, [i64, i64, dbl, vp, i64, sz, P(ooc_opts), P(vp)])
+_sig("ooc_accum_step", i32, [vp, i64, dbl, vp, i64, vp, i64, P(ooc_stats)])
+_sig("ooc_accum_end", i32, [vp, P(ooc_stats)])
+_sig("ooc_accum_resident_rows", i32, [i64, i64, sz, P(i64)])
+_sig("ooc_accum_schedule", i32, [i64, i64, i64, dbl, dbl, sz, P(ooc_opts), i32, P(ooc_op), i64, P(i64), P(u64)])
 _sig("ooc_host_alloc", i32, [P(vp), sz])
 _sig("ooc_host_free", i32, [vp])
 _sig("ooc_device_alloc", i32, [i32, P(vp), sz])
@@ -134,6 +139,7 @@ EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "oo
            "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_mlp_features", "ooc_mlp_forward",
            "ooc_mlp_grad", "ooc_mlp_adam",
            "ooc_mlp_train", "ooc_mlp_fit", "ooc_mlp_save", "ooc_mlp_load", "ooc_mlp_loaded", "ooc_mlp_predict",
+           "ooc_accum_begin", "ooc_accum_step", "ooc_accum_end", "ooc_accum_resident_rows", "ooc_accum_schedule",
            "ooc_last_error", "ooc_version"]
 MLP_FEATURES = 19
 
@@ -288,8 +294,12 @@ def ooc_schedule(M, N, K, alpha, beta, plan):
     cap = max(n.value, 1)
     arr = (ooc_op * cap)()
     _check(_lib.ooc_schedule(M, N, K, alpha, beta, ctypes.byref(plan), arr, cap, ctypes.byref(n), ctypes.byref(ab)))
+    return _ops_as_dicts(arr, n.value), ab.value // 8
+
+
+def _ops_as_dicts(arr, count):
     ops = []
-    for x in range(n.value):
+    for x in range(count):
         o = arr[x]
         kind = OP_NAMES[o.kind]
         d = dict(kind=kind, stream=o.stream, task=o.task, waits=[o.wait[k] for k in range(o.nwait)], slot=o.slot)
@@ -301,7 +311,59 @@ def ooc_schedule(M, N, K, alpha, beta, plan):
                      off_b=o.off_b, ldb=o.ld_b, off_c=o.off_c, ldc=o.ld_c, off_d=o.off_d, ldd=o.ld_d,
                      off_w=o.off_w, len_w=o.len_w, alpha=o.alpha, beta=o.beta, gamma=o.gamma)
         ops.append(d)
-    return ops, ab.value // 8
+    return ops
+
+
+# ---- accumulation sessions ----------------------------------------------------------
+
+class AccumSession:
+    """C = beta*C_in + sum of alpha_s * A_s @ B_s over steps (ooc_accum_begin/step/end).
+    C must be a page-locked float64 view that stays alive until end()."""
+
+    def __init__(self, beta, C, budget_bytes, opts=None):
+        pc, ldc = _mat_arg(C, "C")
+        self.C = C
+        h = vp()
+        _check(_lib.ooc_accum_begin(C.shape[0], C.shape[1], beta, pc, ldc, budget_bytes,
+                                    ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)))
+        self.handle = h.value
+
+    def step(self, alpha, A, B, raise_on_error=True):
+        pa, lda = _mat_arg(A, "A")
+        pb, ldb = _mat_arg(B, "B")
+        st = ooc_stats()
+        s = _lib.ooc_accum_step(self.handle, A.shape[1], alpha, pa, lda, pb, ldb, ctypes.byref(st))
+        if raise_on_error:
+            _check(s)
+        return s, st
+
+    def end(self):
+        st = ooc_stats()
+        h, self.handle = self.handle, None
+        _check(_lib.ooc_accum_end(h, ctypes.byref(st)))
+        return st
+
+
+def ooc_accum_resident_rows(M, N, budget_bytes):
+    r = i64()
+    _check(_lib.ooc_accum_resident_rows(M, N, budget_bytes, ctypes.byref(r)))
+    return r.value
+
+
+def ooc_accum_schedule(M, N, K, alpha, beta_eff, budget_bytes, part, opts=None):
+    """One session step's operation list for part 0 (resident rows) or 1 (streamed rows),
+    as dicts, and the arena size in elements."""
+    n, ab = i64(), u64()
+    o = ctypes.byref(opts) if opts is not None else None
+    st = _lib.ooc_accum_schedule(M, N, K, alpha, beta_eff, budget_bytes, o, part, None, 0, ctypes.byref(n),
+                                 ctypes.byref(ab))
+    if st not in (OOC_OK, OOC_ERR_CAPACITY):
+        _check(st)
+    cap = max(n.value, 1)
+    arr = (ooc_op * cap)()
+    _check(_lib.ooc_accum_schedule(M, N, K, alpha, beta_eff, budget_bytes, o, part, arr, cap, ctypes.byref(n),
+                                   ctypes.byref(ab)))
+    return _ops_as_dicts(arr, n.value), ab.value // 8
 
 
 def ooc_device_copy(dst, src, nbytes, device=0):

@@ -476,8 +476,132 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
   return st;
 }
 
+// ---- accumulation sessions: C += alpha_s * A_s * B_s over several calls ---------------
+//
+// The paper's MMOOC can be called once per step of an outer algorithm (SUMMA
+// or HSUMMA, Section V, the step/nsteps logic of Fig. 2): C is read at the
+// first step only, and the C blocks still on the device at the end of a step
+// are written back only after the last one.  A session generalises this: the
+// first R rows of C (as many as fit in half the budget) stay on the device for
+// the whole session, are loaded once (when beta != 0) and written back once at
+// the end; the remaining rows are streamed through the other half by the
+// ordinary pipeline at every step (read and written back each time).
+
+// Rows of C a session keeps on the device: all of C when it takes at most
+// half the budget, else as many rows as fit in half the budget, a multiple of
+// 128 (the tile height) when there are at least 128.
+int64_t accum_resident_rows(int64_t M, int64_t N, uint64_t budget) {
+  if (M <= 0 || N <= 0) return 0;
+  const uint64_t half = budget / 2;
+  if ((uint64_t)M * (uint64_t)N * 8u <= half) return M;
+  int64_t r = (int64_t)(half / (8u * (uint64_t)N));
+  if (r >= 128) r = r / 128 * 128;
+  return std::min(r, M);
+}
+
+// One part of a session step: rows [0, R) with C resident (part 0) or rows
+// [R, M) streamed through buffers placed after the resident rows (part 1).
+// Host rows of part 1 count from row R.
+ooc_status accum_part(int part, int64_t M, int64_t N, int64_t K, double alpha, double beta_eff, int64_t R,
+                      uint64_t budget, const ooc_opts* opts, Problem* pb_out, ooc_plan_t* plan, Layout* lay,
+                      std::vector<ooc_op>* ops, double* predicted) {
+  Problem pb;
+  pb.N = N; pb.K = K; pb.alpha = alpha; pb.beta = beta_eff;
+  pb.base = R > 0 ? ceil_div(R * N, 32) * 32 : 0;
+  if (part == 0) {
+    pb.M = R;
+    pb.c_resident = true;
+    pb.c_ld = N;
+  } else {
+    pb.M = M - R;
+  }
+  *pb_out = pb;
+  ops->clear();
+  if (pb.M <= 0 || N <= 0) return OOC_OK;
+  ooc_status st = choose_plan(pb, budget, opts, plan, predicted);
+  if (st != OOC_OK) return st;
+  st = plan_layout(pb, *plan, lay);
+  if (st != OOC_OK) return st;
+  if (lay->bytes > budget) return fail(OOC_ERR_BUDGET, "session step plan exceeds the budget");
+  return build_schedule(pb, *plan, *lay, ops);
+}
+
 }  // namespace
 
+}  // namespace ooc
+
+struct ooc_accum_s {
+  int dev = 0;
+  int64_t M = 0, N = 0;
+  double beta = 0.0;
+  double* C = nullptr;
+  int64_t ldc = 0;
+  uint64_t budget = 0;
+  ooc_opts opts{};
+  int64_t R = 0;         // resident rows
+  void* mem = nullptr;   // session arena: resident C rows, then the step plans' buffers
+  int64_t steps = 0;
+};
+
+namespace ooc {
+namespace {
+
+// Step of a session (the device lease is held by the caller).
+ooc_status accum_step_locked(DevCtx& c, ooc_accum_s* a, int64_t K, double alpha, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, ooc_stats* stats) {
+  const double t_enter = now_s();
+  const double beta_eff = a->steps == 0 ? a->beta : 1.0;
+  hipStream_t streams[3];
+  for (int x = 0; x < 3; ++x)
+    streams[x] = a->opts.streams[x] ? static_cast<hipStream_t>(a->opts.streams[x]) : c.st[x];
+  ooc_stats total{};
+  for (int part = 0; part < 2; ++part) {
+    Problem pb;
+    ooc_plan_t plan{};
+    Layout lay;
+    std::vector<ooc_op> ops;
+    double pred = 0.0;
+    ooc_status st = accum_part(part, a->M, a->N, K, alpha, beta_eff, a->R, a->budget, &a->opts, &pb, &plan, &lay,
+                               &ops, &pred);
+    if (st != OOC_OK) return st;
+    if (ops.empty()) continue;
+    const int64_t r0 = part == 0 ? 0 : a->R;
+    HostMats hm{A ? A + r0 * lda : nullptr, lda, B, ldb, a->C + r0 * a->ldc, a->ldc};
+    ooc_stats ps{};
+    const double t_plan = now_s() - t_enter;
+    st = run_ops(c, streams, plan, ops, static_cast<double*>(a->mem), (int64_t)(lay.bytes / 8), hm,
+                 a->opts.profile != 0, nullptr, 0, &ps);
+    total.plan = plan;
+    total.t_plan_s = t_plan;
+    total.t_pipeline_s += ps.t_pipeline_s;
+    total.t_h2d_busy_s += ps.t_h2d_busy_s;
+    total.t_d2h_busy_s += ps.t_d2h_busy_s;
+    total.t_kernel_busy_s += ps.t_kernel_busy_s;
+    total.t_mma_busy_s += ps.t_mma_busy_s;
+    total.mma_launches += ps.mma_launches;
+    total.t_predicted_s += pred;
+    total.arena_bytes = std::max<uint64_t>(total.arena_bytes, lay.bytes);
+    total.ops += (int64_t)ops.size();
+    total.blocks_done += ps.blocks_done;
+    for (const ooc_op& o : ops) {
+      if (o.kind == OOC_OP_H2D) total.bytes_h2d += (uint64_t)(o.rows * o.cols) * 8;
+      else if (o.kind == OOC_OP_D2H) total.bytes_d2h += (uint64_t)(o.rows * o.cols) * 8;
+      else ++total.kernels;
+      if (o.kind == OOC_OP_GEMM || o.kind == OOC_OP_SPLIT_GEMM) ++total.tasks;
+    }
+    if (st != OOC_OK) {
+      if (stats) *stats = total;
+      return st;
+    }
+  }
+  ++a->steps;
+  total.flops = 2.0 * (double)a->M * (double)a->N * (double)K;
+  total.t_total_s = now_s() - t_enter;
+  if (stats) *stats = total;
+  return OOC_OK;
+}
+
+}  // namespace
 }  // namespace ooc
 
 using namespace ooc;
@@ -656,6 +780,135 @@ ooc_status ooc_copy_to_host(int32_t device, void* dst, const void* src, size_t b
   if (st != OOC_OK) return st;
   HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost), "hipMemcpy D2H");
   return OOC_OK;
+}
+
+ooc_status ooc_accum_resident_rows(int64_t M, int64_t N, size_t budget_bytes, int64_t* rows) {
+  if (!rows) return fail(OOC_ERR_ARG, "rows is NULL");
+  if (M < 0 || N < 0) return fail(OOC_ERR_ARG, "negative matrix size");
+  *rows = accum_resident_rows(M, N, budget_bytes);
+  return OOC_OK;
+}
+
+ooc_status ooc_accum_schedule(int64_t M, int64_t N, int64_t K, double alpha, double beta_eff, size_t budget_bytes,
+                              const ooc_opts* opts, int32_t part, ooc_op* ops, int64_t cap, int64_t* nops,
+                              uint64_t* arena_bytes) {
+  if (!nops) return fail(OOC_ERR_ARG, "nops is NULL");
+  if (M < 0 || N < 0 || K < 0) return fail(OOC_ERR_ARG, "negative size");
+  if (part != 0 && part != 1) return fail(OOC_ERR_ARG, "part must be 0 or 1");
+  Problem pb;
+  ooc_plan_t plan{};
+  Layout lay;
+  std::vector<ooc_op> v;
+  ooc_status st = accum_part(part, M, N, K, alpha, beta_eff, accum_resident_rows(M, N, budget_bytes), budget_bytes,
+                             opts, &pb, &plan, &lay, &v, nullptr);
+  if (st != OOC_OK) return st;
+  *nops = (int64_t)v.size();
+  if (arena_bytes) *arena_bytes = v.empty() ? 0 : lay.bytes;
+  for (int64_t x = 0; x < (int64_t)v.size() && x < cap; ++x)
+    if (ops) ops[x] = v[x];
+  if ((int64_t)v.size() > cap) return fail(OOC_ERR_CAPACITY, "more ops than cap");
+  return OOC_OK;
+}
+
+ooc_status ooc_accum_begin(int64_t M, int64_t N, double beta, double* C, int64_t ldc, size_t budget_bytes,
+                           const ooc_opts* opts, ooc_accum* out) {
+  if (!out) return fail(OOC_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (M < 0 || N < 0) return fail(OOC_ERR_ARG, "negative matrix size");
+  if (M > 0 && N > 0 && (!C || ldc < N)) return fail(OOC_ERR_ARG, "bad C or ldc");
+  const int dev = opts ? opts->device : 0;
+  ooc_status st = ensure_device(dev);
+  if (st != OOC_OK) return st;
+  if (!range_pinned(C, M, N, ldc)) return fail(OOC_ERR_NOT_PINNED, "C is not page-locked host memory (use ooc_host_alloc)");
+  ooc_accum_s* a = new ooc_accum_s();
+  a->dev = dev;
+  a->M = M; a->N = N; a->beta = beta; a->C = C; a->ldc = ldc; a->budget = budget_bytes;
+  if (opts) a->opts = *opts;
+  a->opts.timeline = nullptr;
+  a->opts.timeline_cap = 0;
+  a->opts.arena = nullptr;
+  a->opts.arena_bytes = 0;
+  a->R = accum_resident_rows(M, N, budget_bytes);
+  DevCtx& c = g_dev[dev];
+  std::lock_guard<std::mutex> lock(c.mu);
+  st = ensure_streams(c);
+  if (st == OOC_OK && M > 0 && N > 0) {
+    size_t fr = 0, tot = 0;
+    hipError_t e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) st = hip_fail(e, "hipMemGetInfo");
+    else if (budget_bytes > fr)
+      st = fail(OOC_ERR_DEVICE_MEM, "session budget " + std::to_string(budget_bytes) + " bytes, device has " +
+                                        std::to_string(fr) + " free");
+    else if ((e = hipMalloc(&a->mem, budget_bytes)) != hipSuccess) {
+      (void)hipGetLastError();
+      a->mem = nullptr;
+      st = fail(OOC_ERR_DEVICE_MEM, std::string("hipMalloc of the session arena: ") + hipGetErrorString(e));
+    }
+  }
+  // the resident rows start as C_in (only read when beta != 0)
+  if (st == OOC_OK && a->R > 0 && beta != 0.0) {
+    hipError_t e = hipMemcpy2DAsync(a->mem, (size_t)N * 8, C, (size_t)ldc * 8, (size_t)N * 8, (size_t)a->R,
+                                    hipMemcpyHostToDevice, c.st[0]);
+    const hipError_t es = hipStreamSynchronize(c.st[0]);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) st = hip_fail(e, "loading the resident rows of C");
+  }
+  if (st != OOC_OK) {
+    if (a->mem) (void)hipFree(a->mem);
+    delete a;
+    return st;
+  }
+  *out = a;
+  return OOC_OK;
+}
+
+ooc_status ooc_accum_step(ooc_accum acc, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                          int64_t ldb, ooc_stats* stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!acc) return fail(OOC_ERR_ARG, "session is NULL");
+  if (K < 0) return fail(OOC_ERR_ARG, "negative K");
+  ooc_status st = check_args(acc->M, acc->N, K, alpha, A, lda, B, ldb, 1.0, acc->C, acc->ldc);
+  if (st != OOC_OK) return st;
+  if (acc->M == 0 || acc->N == 0) {
+    ++acc->steps;
+    return OOC_OK;
+  }
+  if (K > 0 && alpha != 0.0 && (!range_pinned(A, acc->M, K, lda) || !range_pinned(B, K, acc->N, ldb)))
+    return fail(OOC_ERR_NOT_PINNED, "A or B is not page-locked host memory (use ooc_host_alloc)");
+  st = ensure_device(acc->dev);
+  if (st != OOC_OK) return st;
+  DevCtx& c = g_dev[acc->dev];
+  std::lock_guard<std::mutex> lock(c.mu);
+  return accum_step_locked(c, acc, K, alpha, A, lda, B, ldb, stats);
+}
+
+ooc_status ooc_accum_end(ooc_accum acc, ooc_stats* stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!acc) return fail(OOC_ERR_ARG, "session is NULL");
+  ooc_status st = OOC_OK;
+  if (acc->M > 0 && acc->N > 0) {
+    st = ensure_device(acc->dev);
+    if (st == OOC_OK) {
+      DevCtx& c = g_dev[acc->dev];
+      std::lock_guard<std::mutex> lock(c.mu);
+      // no step: the result is beta*C (a step with K = 0 reads neither A nor B)
+      if (acc->steps == 0) st = accum_step_locked(c, acc, 0, 0.0, nullptr, 1, nullptr, 1, stats);
+      if (st == OOC_OK && acc->R > 0) {
+        hipError_t e = hipMemcpy2DAsync(acc->C, (size_t)acc->ldc * 8, acc->mem, (size_t)acc->N * 8,
+                                        (size_t)acc->N * 8, (size_t)acc->R, hipMemcpyDeviceToHost, c.st[2]);
+        const hipError_t es = hipStreamSynchronize(c.st[2]);
+        if (e == hipSuccess) e = es;
+        if (e != hipSuccess) st = hip_fail(e, "writing the resident rows of C back");
+        else if (stats) stats->bytes_d2h += (uint64_t)acc->R * acc->N * 8;
+      }
+      if (acc->mem) {
+        const hipError_t e = hipFree(acc->mem);
+        if (e != hipSuccess && st == OOC_OK) st = hip_fail(e, "hipFree of the session arena");
+      }
+    }
+  }
+  delete acc;
+  return st;
 }
 
 ooc_status ooc_release(int32_t device) {

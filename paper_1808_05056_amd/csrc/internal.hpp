@@ -16,6 +16,14 @@ ooc_status fail(ooc_status st, const std::string& msg);
 struct Problem {
   int64_t M = 0, N = 0, K = 0;
   double alpha = 1.0, beta = 0.0;
+  // Accumulation sessions: with c_resident, C (M x N) already lives on the
+  // device at element 0 of the arena with leading dimension c_ld; the plan
+  // has no C buffers and moves no C, and its first K panel of each block
+  // computes c = alpha*a*b + beta*c in place.  base: first arena element the
+  // plan's own buffers may use (elements below it belong to resident C).
+  bool c_resident = false;
+  int64_t c_ld = 0;
+  int64_t base = 0;
   // K as the pipeline sees it: 0 when alpha == 0 or K == 0 (A and B are not read).
   int64_t keff() const { return (alpha == 0.0 || K == 0) ? 0 : K; }
 };

@@ -47,12 +47,16 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
   const int64_t h = ceil_div(pb.M, mb), w = ceil_div(pb.N, nb);
   Layout L;
   const bool single = (h * w == 1) && (K == 0 || kb >= K);
+  // resident C (accumulation sessions) needs no C buffers
+  const int64_t slot_c = pb.c_resident ? 0 : mb * nb;
+  if (pb.base < 0 || (pb.c_resident && (pb.c_ld < pb.N || pb.base < (pb.M - 1) * pb.c_ld + pb.N)))
+    return fail(OOC_ERR_ARG, "plan: resident C region malformed");
   if (single) {
     // one block: each operand needs exactly one buffer (the in-core case)
     L.slotA = mb * kb;
     L.slotB = kb * nb;
-    L.slotC = mb * nb;
-    L.offA = 0;
+    L.slotC = slot_c;
+    L.offA = pb.base;
     L.offB = L.offA + (K > 0 ? L.slotA : 0);
     L.offC = L.offB + (K > 0 ? L.slotB : 0);
     L.offD = L.offC + L.slotC;
@@ -60,13 +64,13 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
   } else {
     L.slotA = mb * kb;
     L.slotB = kb * nb;
-    L.slotC = mb * nb;
-    L.offA = 0;
+    L.slotC = slot_c;
+    L.offA = pb.base;
     L.offB = L.offA + (K > 0 ? plan.nbuf_a * L.slotA : 0);
     L.offC = L.offB + (K > 0 ? plan.nbuf_b * L.slotB : 0);
     L.offD = L.offC + plan.nbuf_c * L.slotC;
     // staging buffers for the initial C (only when C is read at all)
-    if (plan.nbuf_d > 0 && pb.beta != 0.0) {
+    if (plan.nbuf_d > 0 && pb.beta != 0.0 && !pb.c_resident) {
       L.nbufD = plan.nbuf_d;
       L.slotD = mb * nb;
     }
@@ -373,8 +377,10 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
         break;
       }
     }
-    const double h2d = 8.0 * ((double)M * K * a_loads + (double)K * N * b_loads + (pb.beta != 0 ? (double)M * N : 0));
-    const double d2h = 8.0 * (double)M * N;
+    const bool c_moves = !pb.c_resident;
+    const double h2d = 8.0 * ((double)M * K * a_loads + (double)K * N * b_loads +
+                              (pb.beta != 0 && c_moves ? (double)M * N : 0));
+    const double d2h = c_moves ? 8.0 * (double)M * N : 0.0;
     const double t_link = std::max(h2d / (mc.h2d_gbs * 1e9), d2h / (mc.d2h_gbs * 1e9));
     // the bound does not depend on the stream count: one entry per count
     for (int ns : stream_opts) {
@@ -544,9 +550,12 @@ struct PlanKey {
   bool beta_nonzero;
   uint64_t budget;
   int planner, precision, slices, nstreams;
+  bool c_resident;
+  int64_t c_ld, base;
   bool operator<(const PlanKey& o) const {
-    return std::tie(M, N, K, beta_nonzero, budget, planner, precision, slices, nstreams) <
-           std::tie(o.M, o.N, o.K, o.beta_nonzero, o.budget, o.planner, o.precision, o.slices, o.nstreams);
+    return std::tie(M, N, K, beta_nonzero, budget, planner, precision, slices, nstreams, c_resident, c_ld, base) <
+           std::tie(o.M, o.N, o.K, o.beta_nonzero, o.budget, o.planner, o.precision, o.slices, o.nstreams,
+                    o.c_resident, o.c_ld, o.base);
   }
 };
 std::mutex g_plan_mu;
@@ -565,7 +574,7 @@ ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts*
                        double* predicted) {
   PlanKey key{pb.M, pb.N, pb.keff(), pb.beta != 0.0, budget_bytes,
               opts ? opts->planner : 0, opts ? opts->precision : 0, opts ? opts->slices : 0,
-              opts ? opts->nstreams : 0};
+              opts ? opts->nstreams : 0, pb.c_resident, pb.c_ld, pb.base};
   {
     std::lock_guard<std::mutex> lock(g_plan_mu);
     auto it = g_plan_cache.find(key);

@@ -196,6 +196,10 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     if (plan.order == OOC_ORDER_ROWS_P || plan.order == OOC_ORDER_ROWS_PS) return spread(tk.j, w);
     return P - 1;
   };
+  // resident C (accumulation sessions): blocks live at their place in the
+  // resident matrix; only the op that last wrote each block is tracked
+  const bool resident = pb.c_resident;
+  std::vector<int> r_last_writer(resident ? h * w : 0, -1);
   // C bookkeeping: block key -> buffer, the op that last wrote it
   std::vector<int> c_close(plan.nbuf_c, -1);    // D2H op that emptied the buffer
   std::vector<int64_t> c_block(plan.nbuf_c, -1);  // open block key, -1 if free
@@ -280,10 +284,13 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     // C block (i, j)
     const int64_t ckey = tk.i * w + tk.j;
     int sc = -1;
-    for (int s = 0; s < plan.nbuf_c; ++s)
-      if (c_block[s] == ckey) sc = s;
+    if (!resident)
+      for (int s = 0; s < plan.nbuf_c; ++s)
+        if (c_block[s] == ckey) sc = s;
     int c_dep = -1;
-    if (opens[t]) {
+    if (resident) {
+      c_dep = r_last_writer[ckey];  // earlier K panels of the block, possibly on another stream
+    } else if (opens[t]) {
       if (sc >= 0) return fail(OOC_ERR_ARG, "schedule: C block opened twice");
       for (int s = 0; s < plan.nbuf_c; ++s) {
         if (c_block[s] >= 0) continue;
@@ -337,7 +344,14 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
       g.off_a = lay.offA + sa * lay.slotA; g.ld_a = k;
       g.off_b = lay.offB + sb * lay.slotB; g.ld_b = n;
     }
-    g.off_c = lay.offC + sc * lay.slotC; g.ld_c = n;
+    if (resident) {
+      g.slot = -1;
+      g.off_c = i0 * pb.c_ld + j0;
+      g.ld_c = pb.c_ld;
+    } else {
+      g.off_c = lay.offC + sc * lay.slotC;
+      g.ld_c = n;
+    }
     g.off_w = lay.offW; g.len_w = lay.lenW;
     g.alpha = pb.alpha;
     g.beta = opens[t] ? (staged ? 0.0 : pb.beta) : 1.0;
@@ -362,6 +376,10 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
       pbf.readers[sb][ops[gx].stream] = gx;
     }
     if (fold_here) pd.readers[sd][ops[gx].stream] = gx;
+    if (resident) {
+      r_last_writer[ckey] = gx;
+      continue;  // resident blocks stay on the device
+    }
     c_last_writer[sc] = gx;
     // C block home after its last panel
     if (closes[t]) {
