@@ -71,3 +71,45 @@ def check_rows(w, pp, rows, gate=oracle.GATE, label=""):
     ref, D, Cin = reference_rows(w, pp.A, pp.B, rows)
     lit, gen = gate_errors(pp.C[rows], ref, w.alpha, D, w.beta, Cin, gate, label=f"{label}{len(rows)} rows: ")
     return lit if w.beta == 0.0 else gen
+
+
+class HipRuntime:
+    """A few calls of the HIP runtime that the library itself links (the
+    soname resolves to the copy already loaded with libooc).  torch carries a
+    HIP runtime of its own; a second runtime in the process could not see the
+    GPU after the library's had initialised it, so the GPU tests create their
+    caller-owned streams here."""
+
+    def __init__(self):
+        import ctypes
+        self._ct = ctypes
+        self.lib = ctypes.CDLL("libamdhip64.so.7")
+        self.lib.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self.lib.hipStreamDestroy.argtypes = [ctypes.c_void_p]
+        self.lib.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+        self.lib.hipMemGetInfo.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+        self.lib.hipSetDevice.argtypes = [ctypes.c_int]
+
+    def _check(self, rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} failed with HIP error {rc}")
+
+    def set_device(self, dev):
+        self._check(self.lib.hipSetDevice(dev), "hipSetDevice")
+
+    def stream_create(self):
+        """A non-blocking stream at the default priority."""
+        s = self._ct.c_void_p()
+        self._check(self.lib.hipStreamCreateWithFlags(self._ct.byref(s), 1), "hipStreamCreateWithFlags")
+        return s.value
+
+    def stream_destroy(self, s):
+        self._check(self.lib.hipStreamDestroy(s), "hipStreamDestroy")
+
+    def stream_synchronize(self, s):
+        self._check(self.lib.hipStreamSynchronize(s), "hipStreamSynchronize")
+
+    def mem_free(self):
+        fr, tot = self._ct.c_size_t(), self._ct.c_size_t()
+        self._check(self.lib.hipMemGetInfo(self._ct.byref(fr), self._ct.byref(tot)), "hipMemGetInfo")
+        return fr.value

@@ -255,21 +255,25 @@ def test_degenerate_shapes_small_budgets(case):
 # ---- boundary options: borrowed caller streams, arena release, planning time, overlap ---
 
 def test_borrowed_streams_arena_release_and_stats():
-    """The pipeline runs on three caller-owned streams (created by torch at the
-    default priority), the result meets the gate, the stats carry the planning
-    time and the copy/compute overlap, and release_arena frees the arena before
-    the call returns (device free memory is back)."""
-    import torch
+    """The pipeline runs on three caller-owned streams (created at the default
+    priority through the HIP runtime the library links), the result meets the
+    gate, the stats carry the planning time and the copy/compute overlap, and
+    release_arena frees the arena before the call returns (device free memory
+    is back)."""
+    from gpu_helpers import HipRuntime
+    hip = HipRuntime()
     w = W.Workload("borrowed", 2048, 2048, 2048, 1.0, 0.5, 256 * MiB, seed=31)
     pp = PinnedProblem(w)
+    streams = []
     try:
         ooc.ooc_release(-1)
-        streams = [torch.cuda.Stream(device=0) for _ in range(3)]
+        hip.set_device(0)
+        streams = [hip.stream_create() for _ in range(3)]
         plan = ooc.make_plan(512, 1024, 2048, ooc.ORDER_COLS, 2, 2, 2, 3)
-        opts = ooc.make_opts(streams=[s.cuda_stream for s in streams], profile=True)
-        free0 = torch.cuda.mem_get_info(0)[0]
+        opts = ooc.make_opts(streams=streams, profile=True)
+        free0 = hip.mem_free()
         _, stats = ooc.ooc_gemm_planned(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, plan, opts)
-        free_cached = torch.cuda.mem_get_info(0)[0]
+        free_cached = hip.mem_free()
         _say(f"borrowed streams: overlap {stats.overlap:.3f} t_plan {stats.t_plan_s * 1e3:.3f} ms "
              f"t_total {stats.t_total_s * 1e3:.2f} ms arena {stats.arena_bytes}")
         check_rows(w, pp, np.arange(w.M))
@@ -277,14 +281,16 @@ def test_borrowed_streams_arena_release_and_stats():
         assert 0.0 < stats.t_plan_s < stats.t_total_s
         assert free0 - free_cached >= 0.9 * stats.arena_bytes  # cached for the next call
         synth.fill(pp.C, w.spec_c())
-        opts = ooc.make_opts(streams=[s.cuda_stream for s in streams], release_arena=True)
+        opts = ooc.make_opts(streams=streams, release_arena=True)
         _, stats = ooc.ooc_gemm_planned(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, plan, opts)
-        free_released = torch.cuda.mem_get_info(0)[0]
+        free_released = hip.mem_free()
         check_rows(w, pp, np.arange(w.M))
         assert free_released - free_cached >= 0.5 * stats.arena_bytes
         assert stats.overlap == 0.0  # not profiled
         for s in streams:
-            s.synchronize()
+            hip.stream_synchronize(s)
     finally:
+        for s in streams:
+            hip.stream_destroy(s)
         pp.free()
         ooc.ooc_release(-1)
