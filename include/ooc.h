@@ -348,6 +348,26 @@ ooc_status ooc_split_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k
                                  const double* A, int64_t lda, const double* B, int64_t ldb,
                                  double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid allocation): ooc_split_gemm_device
+ * without any allocation.  The slice workspace is a static device array of
+ * OOC_NOALLOC_SCRATCH_BYTES per device, held by every device the library runs
+ * on until the process ends; the call is OOC_ERR_CAPACITY when the workspace
+ * of (m, n, min(k, 8192), s) exceeds it (m = n = k = 1024 at s = 8 needs
+ * 40 MiB).  A, B and C are device pointers as for ooc_split_gemm_device, the
+ * result is the same bit for bit.  The kernels are enqueued on `stream` (a
+ * hipStream_t; NULL: the null stream) and the call returns without waiting:
+ * C is complete when that stream's work is.  Every call on a device shares
+ * its one scratch array, so calls whose work overlaps in time on one device
+ * (on different streams, or from several host threads) race and give
+ * unspecified results; calls queued on one stream are safe.  Errors:
+ * OOC_ERR_ARG as ooc_split_gemm_device, OOC_ERR_CAPACITY, OOC_ERR_NO_DEVICE,
+ * OOC_ERR_HIP (launch failure). */
+#define OOC_NOALLOC_SCRATCH_BYTES (64u << 20)
+ooc_status ooc_split_gemm_device_noalloc(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,
+                                         const double* A, int64_t lda, const double* B, int64_t ldb,
+                                         double beta, double* C, int64_t ldc, void* stream);
+
 /* The same with s INT8 slices of 7 bits (OOC_SPLIT_INT8) on INT8 matrix cores
  * with exact INT32 sums; arguments, rounding and errors as above. */
 ooc_status ooc_split_int8_gemm_device(int32_t device, int64_t m, int64_t n, int64_t k, int32_t s, double alpha,

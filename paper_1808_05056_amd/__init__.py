@@ -118,6 +118,7 @@ _sig("ooc_device_copy", i32, [i32, vp, vp, sz])
 _sig("ooc_dgemm_device", i32, [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 _sig("ooc_split_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
 _sig("ooc_split_int8_gemm_device", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, i32, P(dbl)])
+_sig("ooc_split_gemm_device_noalloc", i32, [i32, i64, i64, i64, i32, dbl, vp, i64, vp, i64, dbl, vp, i64, vp])
 P_flt = ctypes.POINTER(ctypes.c_float)
 _sig("ooc_mlp_features", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P_flt])
 _sig("ooc_mlp_forward", i32, [i32, i32, i32, P_flt, P_flt, i64, P_flt])
@@ -136,7 +137,7 @@ _sig("ooc_version", ctypes.c_char_p, [])
 EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_device_copy", "ooc_dgemm_device",
-           "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_mlp_features", "ooc_mlp_forward",
+           "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_split_gemm_device_noalloc", "ooc_mlp_features", "ooc_mlp_forward",
            "ooc_mlp_grad", "ooc_mlp_adam",
            "ooc_mlp_train", "ooc_mlp_fit", "ooc_mlp_save", "ooc_mlp_load", "ooc_mlp_loaded", "ooc_mlp_predict",
            "ooc_accum_begin", "ooc_accum_step", "ooc_accum_end", "ooc_accum_resident_rows", "ooc_accum_schedule",
@@ -379,6 +380,14 @@ def ooc_split_gemm_device(m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, re
     _check(_lib.ooc_split_gemm_device(device, m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps,
                                       ctypes.byref(ms) if timed else None))
     return ms.value if timed else None
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # OOC_NOALLOC_SCRATCH_BYTES
+
+
+def ooc_split_gemm_device_noalloc(m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, stream=None, device=0):
+    """Enqueues the product on `stream` (raw hipStream_t, None: the null stream) and returns without waiting."""
+    _check(_lib.ooc_split_gemm_device_noalloc(device, m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, stream))
 
 
 def ooc_split_int8_gemm_device(m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps=1, timed=False, device=0):

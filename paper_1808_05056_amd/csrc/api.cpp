@@ -528,6 +528,8 @@ ooc_status accum_part(int part, int64_t M, int64_t N, int64_t K, double alpha, d
 
 }  // namespace
 
+ooc_status use_device(int dev) { return ensure_device(dev); }
+
 }  // namespace ooc
 
 struct ooc_accum_s {

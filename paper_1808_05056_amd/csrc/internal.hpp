@@ -13,6 +13,10 @@ namespace ooc {
 void set_error(const std::string& msg);
 ooc_status fail(ooc_status st, const std::string& msg);
 
+// Make `dev` the calling thread's current device, checking once that it is a
+// gfx950 (OOC_ERR_NO_DEVICE otherwise).  Allocates nothing.
+ooc_status use_device(int dev);
+
 struct Problem {
   int64_t M = 0, N = 0, K = 0;
   double alpha = 1.0, beta = 0.0;
