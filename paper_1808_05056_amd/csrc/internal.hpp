@@ -74,10 +74,11 @@ struct Machine {
   double kernel_k0 = 30.0;         // per-tile fixed cost in units of k
   double kernel_scalar_factor = 1.15;  // odd leading dimensions (8-byte loads)
   double kernel_launch_s = 6e-6;
-  double split_tflops_per_product = 725.0;  // BF16 slice-product rate (TFLOP/s of BF16 work), two tiles per CU
-  double split_tflops_1wg_per_product = 350.0;  // same with one tile per CU
-  double split_k0 = 160.0;                   // per weight and tile: pipeline start in units of k
-  double split_int8_speedup = 2.0;           // INT8 slice products per BF16 slice product in the same time
+  double split_tflops_per_product = 990.0;  // BF16 slice-product rate (TFLOP/s of BF16 work), 256 x 128 tiles,
+                                            // one per CU, slice-sum traffic excluded (8192^3 launches at s = 5)
+  double split_k0 = 160.0;                  // per weight and tile: pipeline start in units of k
+  double int8_tops_per_product = 1450.0;    // INT8 slice-product rate (TOP/s), 128 x 128 tiles, two per CU
+  double int8_tops_1wg_per_product = 700.0; // same with one tile per CU
   double hbm_bytes_per_s = 5e12;            // streaming rate of the split kernel's slice-sum tile
   int cus = 256;
 };

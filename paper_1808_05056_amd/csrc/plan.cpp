@@ -186,17 +186,29 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
     else if (rest > 0) t += tile_flops / r1;
   }
   if ((k & 1) || (n & 1)) t *= mc.kernel_scalar_factor;
+  if (precision == OOC_SPLIT_BF16) {
+    // the BF16 slice-product kernel computes whole 256 x 128 tiles, one per CU
+    // at a time, in waves of one tile per CU; every weight's pass over a tile
+    // pays a pipeline start of split_k0 k
+    const double mp = std::ceil(m / 256.0) * 256.0, np = std::ceil(n / 128.0) * 128.0;
+    const double products = slices * (slices + 1) / 2.0;
+    const double tiles16 = (double)ceil_div(m, 256) * (double)ceil_div(n, 128);
+    const double stile = 2.0 * 256.0 * 128.0 * (products * (double)k + slices * mc.split_k0);
+    const double ts = std::ceil(tiles16 / mc.cus) * stile / (mc.split_tflops_per_product * 1e12 / mc.cus);
+    const double slice_s = (mp + np) * k * (8.0 + 2.0 * slices) / 4e12;
+    // the FP64 slice-sum tile is read and written once per weight (s weights)
+    const double sum_s = (double)slices * 16.0 * mp * np / mc.hbm_bytes_per_s;
+    return mc.kernel_launch_s * 6 + slice_s + sum_s + ts;
+  }
   if (precision != OOC_FP64) {
-    // the slice-product kernel computes whole 128 x 128 tiles, two per CU at
-    // a time, in waves like the FP64 kernel; every weight's pass over a tile
-    // pays a pipeline start of split_k0 k (at the BF16 rate; INT8 products
-    // run split_int8_speedup times faster, the start costs the same time)
+    // the INT8 slice-product kernel computes whole 128 x 128 tiles, two per
+    // CU at a time, in waves like the FP64 kernel; every weight's pass over a
+    // tile pays a pipeline start of split_k0 k at half the INT8 rate
     const double mp = std::ceil(m / 128.0) * 128.0, np = std::ceil(n / 128.0) * 128.0;
     const double products = slices * (slices + 1) / 2.0;
-    const double speed = precision == OOC_SPLIT_INT8 ? mc.split_int8_speedup : 1.0;
-    const double stile = 2.0 * 128.0 * 128.0 * (products * (double)k / speed + slices * mc.split_k0);
-    const double s2 = mc.split_tflops_per_product * 1e12 / mc.cus;
-    const double s1 = mc.split_tflops_1wg_per_product * 1e12 / mc.cus;
+    const double stile = 2.0 * 128.0 * 128.0 * (products * (double)k + 2.0 * slices * mc.split_k0);
+    const double s2 = mc.int8_tops_per_product * 1e12 / mc.cus;
+    const double s1 = mc.int8_tops_1wg_per_product * 1e12 / mc.cus;
     double ts;
     if (tiles <= mc.cus) {
       ts = stile / s1;

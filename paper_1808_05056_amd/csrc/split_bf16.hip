@@ -12,11 +12,15 @@
 //     Each step is exact; |m_1| <= 256 and |m_p| <= 128 (p >= 2) are integers that
 //     BF16 holds exactly.  Same for B with f_j.
 //  3. For each weight t = p + q (2 <= t <= s+1), U_t = sum over p + q = t of
-//     sum_k mA_p[i,k] mB_q[k,j].  A product of slices is at most 2^16 (t = 2),
-//     2^15 (t = 3) or 2^14 in magnitude, so inside a window of 256, 128 or 64 k
-//     of all pairs of the weight every partial sum is an integer below 2^24 and
-//     the FP32 MFMA accumulation is exact; window sums are added into an int32
-//     U_t, exact for K panels of at most 8192.
+//     sum_k mA_p[i,k] mB_q[k,j].  |m_1| <= 2^8 and |m_p| <= 2^7 (p >= 2), so a
+//     product of slices p and q is at most 2^16 (p = q = 1), 2^15 (one of them
+//     1) or 2^14, and the products of one k over all pairs of weight t sum to
+//     at most B(t) = 2^16 (t <= 3) or 2^16 + (t-3) 2^14 (t >= 4).  Inside a
+//     window of W(t) = 256 (t <= 3), 128 (t <= 7) or 64 (t >= 8) k every
+//     partial sum is an integer of magnitude at most W(t) B(t) <= 2^24 (equal
+//     at t = 2, 3 and 7: no margin), so the FP32 MFMA accumulation is exact
+//     (kWindowsExact checks every t up to 9); window sums are added into an
+//     int32 U_t, exact for K panels of at most 8192.
 //  4. S = sum over t from s+1 down to 2 of U_t * 2^(e_i + f_j - 8t), accumulated
 //     in FP64 from the smallest weight to the largest.
 //  5. C = alpha*S + beta*C + gamma*D with separate roundings (no fused
@@ -220,47 +224,54 @@ __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const do
   }
 }
 
-// Slice products.  A workgroup of 4 waves (2 x 2) computes a 128 x 128 block
-// of C; each wave a 64 x 64 block as 2 x 2 tiles of V_MFMA_F32_32X32X16_BF16.
-// For each weight t (from s+1 down to 2) the kernel walks the K range in
-// chunks of 64; every chunk of every pair (p, t-p) is staged in LDS (A plane
-// rows and transposed B plane rows, k contiguous), double-buffered with the
-// next chunk prefetched into registers without a break at window or weight
-// boundaries.  FP32 accumulators are folded into
-// integer sums U_t after windows of 256 (t <= 3), 128 (t <= 7) or 64 k, the
-// longest windows whose partial sums provably stay below 2^24; with at most
-// 8192 k per launch |U_t| < 8192 * 10 * 2^14 < 2^31, so int32 holds U_t
-// exactly.  Between weights the FP64 slice sum S lives in a workspace tile;
-// the last weight's pass finishes S and writes C.
-// Operand layout of V_MFMA_F32_32X32X16_BF16: lane l supplies A[l%32][8*(l/32) .. +8]
-// and B[8*(l/32) .. +8][l%32]; accumulator element v of lane l is
-// D[8*(v/4) + 4*(l/32) + v%4][l%32].
-constexpr int SBM = 128, SBN = 128, SKC = 64, SPAD = 8;  // tile, k chunk, LDS row padding (bf16)
+// Tiles of the INT8 slice-product kernel (128 x 128) and its LDS row padding (elements).
+constexpr int SBM = 128, SBN = 128, SKC = 64, SPAD = 8;
 
-// S = S + U_t 2^(e_i + f_j - bits t) for one 128 x 128 tile whose integer sums
-// U_t sit in LDS (row-major), walked row by row with consecutive threads on
-// consecutive columns; the last weight (t = 2) finishes S and writes
-// C = alpha*S + beta*C + gamma*D with separate roundings.
-__device__ __forceinline__ void slice_sum_update(const int32_t* Ul, int t, int s, int bits, int tid, int64_t m0,
-                                                 int64_t n0, int64_t m, int64_t n, int64_t npad,
-                                                 const int32_t* __restrict__ ea, const int32_t* __restrict__ fb,
-                                                 double* __restrict__ Sws, double alpha, double beta,
-                                                 double* __restrict__ C, int64_t ldc, double gamma,
+// The exactness windows of the BF16 slice products (k per window), and the
+// bound on the sum over all pairs of weight t of one k's slice products.
+__host__ __device__ constexpr int window_k(int t) { return t <= 3 ? 256 : (t <= 7 ? 128 : 64); }
+__host__ __device__ constexpr int64_t pair_sum_bound(int t) {
+  int64_t b = 0;
+  for (int p = 1; p < t; ++p) {
+    const int q = t - p;
+    b += (int64_t)(p == 1 ? 256 : 128) * (q == 1 ? 256 : 128);
+  }
+  return b;
+}
+__host__ __device__ constexpr bool windows_exact() {
+  for (int t = 2; t <= 9; ++t)
+    if (window_k(t) * pair_sum_bound(t) > (int64_t(1) << 24)) return false;
+  return true;
+}
+constexpr bool kWindowsExact = windows_exact();
+static_assert(kWindowsExact, "an exactness window lets an FP32 partial sum exceed 2^24");
+
+// S = S + U_t 2^(e_i + f_j - bits t) for one TBM x TBN tile whose integer
+// sums U_t sit in LDS (row-major), walked row by row with consecutive threads
+// on consecutive columns (NT threads); ea and fb hold the tile's row and
+// column exponents (tile-relative).  The last weight (t = 2) finishes S and
+// writes C = alpha*S + beta*C + gamma*D with separate roundings.
+template <int TBM, int TBN, int NT>
+__device__ __forceinline__ void slice_sum_update(const int32_t* Ul, const int32_t* ea, const int32_t* fb, int t,
+                                                 int s, int bits, int tid, int64_t m0, int64_t n0, int64_t m,
+                                                 int64_t n, int64_t npad, double* __restrict__ Sws, double alpha,
+                                                 double beta, double* __restrict__ C, int64_t ldc, double gamma,
                                                  const double* __restrict__ D, int64_t ldd) {
   // separate roundings: the products and sums below are not fused (the pragma
   // covers operations written in this function; HIP's __dmul_rn / __dadd_rn
   // inline plain operations from a header compiled with contraction on)
 #pragma clang fp contract(off)
-  const int c = tid & (SBN - 1);
+  static_assert(NT % TBN == 0, "whole rows per pass");
+  const int c = tid % TBN;
   const int64_t col = n0 + c;
-  const int32_t ff = fb[col];
+  const int32_t ff = fb[c];
 #pragma unroll 4
-  for (int r = tid / SBN; r < SBM; r += 256 / SBN) {
+  for (int r = tid / TBN; r < TBM; r += NT / TBN) {
     const int64_t row = m0 + r;
-    const int32_t ee = ea[row];
+    const int32_t ee = ea[r];
     const bool bad = ee == kBad || ff == kBad;
     double* ps = Sws + row * npad + col;
-    const double term = bad ? 0.0 : ldexp((double)Ul[r * SBN + c], ee + ff - bits * t);
+    const double term = bad ? 0.0 : ldexp((double)Ul[r * TBN + c], ee + ff - bits * t);
     const double S = (t == s + 1) ? term : (*ps + term);
     if (t > 2) {
       *ps = S;
@@ -300,78 +311,135 @@ __device__ inline void xcd_band_tile(int b, int tiles_m, int tiles_n, int gm_row
   *tn = in_group / gm;
 }
 
-__device__ inline int fold_window_chunks(int t) { return t <= 3 ? 4 : (t <= 7 ? 2 : 1); }
 
-__global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64_t kpad, int s,
+// BF16 slice products.  A workgroup of 8 waves (4 x 2) computes a 256 x 128
+// tile of C, each wave a 64 x 64 block as 2 x 2 tiles of
+// V_MFMA_F32_32X32X16_BF16 (one workgroup per CU, two waves per SIMD).  For each
+// weight t (from s+1 down to 2) the steps walk the exactness windows, inside a
+// window the pairs (p, t-p), inside a pair the window's 64-k chunks.  The A
+// and B plane rows of a step (256 + 128 rows of 128 bytes) are loaded straight
+// into one of three LDS stages, two steps ahead of the products; the direct
+// loads are written in asm so the compiler does not wait for all of them
+// before each LDS read, and the barrier between steps is a bare s_barrier
+// after an explicit wait for the next step's loads only (__syncthreads would
+// also wait for the loads of the step after).  At each window's end the FP32
+// accumulators are folded into the int32 sums U_t; at each weight's end the
+// sums go through LDS (the stages are idle by then) into
+// S = S + U_t 2^(e_i + f_j - 8t), accumulated in the workspace tile, and the
+// last weight writes C.  A row's 16-byte slots are permuted
+// (slot = chunk ^ ((row + row / 8) & 7)) so that 16-byte LDS reads of 8 or of
+// 16 consecutive rows fall in distinct banks.
+// Operand layout of V_MFMA_F32_32X32X16_BF16: lane l supplies A[l%32][8*(l/32) .. +8]
+// and B[8*(l/32) .. +8][l%32]; accumulator element v of lane l is
+// D[8*(v/4) + 4*(l/32) + v%4][l%32].
+constexpr int GBM = 256, GBN = 128, GKC = 64;  // tile rows, columns, k per step
+constexpr int GWM = 4, GWN = 2;                 // waves along M and N (64 x 64 each)
+constexpr int GNT = 64 * GWM * GWN;             // threads per workgroup
+constexpr int GROW = GKC * 2;                   // bytes per tile row and step
+constexpr int GA = GBM * GROW, GB = GBN * GROW, GSTAGE = GA + GB;
+constexpr int GNST = 3;                         // LDS stages
+constexpr int GALD = GBM / 8 / (GWM * GWN), GBLD = GBN / 8 / (GWM * GWN);  // 1-KB loads per wave and step
+constexpr int GLD = GALD + GBLD;
+static_assert(GALD * 8 * GWM * GWN == GBM && GBLD * 8 * GWM * GWN == GBN, "load split");
+static_assert(GBM * GBN * 4 <= GNST * GSTAGE, "sum buffer");
+
+__device__ __forceinline__ int gswz(int r) { return (r + (r >> 3)) & 7; }
+
+// One 16-byte-per-lane load into LDS at lds_addr + 16 * lane (M0 = the
+// wave-uniform LDS byte address; one wait state after M0 is written).
+__device__ __forceinline__ void load_lds16(const void* g, uint32_t lds_addr) {
+  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "{m0}"(lds_addr) : "memory");
+}
+
+// Wait until at most N vector-memory operations of this wave are in flight and
+// its LDS operations are done, then the workgroup barrier.
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier() {
+  constexpr int imm = (N & 15) | (7 << 4) | ((N >> 4) << 14);  // vmcnt(N) expcnt(7) lgkmcnt(0)
+  __builtin_amdgcn_s_waitcnt(imm);
+  asm volatile("s_barrier" ::: "memory");
+}
+
+__global__ __launch_bounds__(GNT, 1) void split_gemm(int64_t m, int64_t n, int64_t kpad, int s,
                                                      const uint16_t* __restrict__ Ap, const uint16_t* __restrict__ Bp,
                                                      int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
                                                      const int32_t* __restrict__ fb, double* __restrict__ Sws,
                                                      double alpha, double beta, double* __restrict__ C, int64_t ldc,
                                                      double gamma, const double* __restrict__ D, int64_t ldd) {
-  // staging buffers for two chunks of A and B, or the tile's integer sums during a fold
-  __shared__ __attribute__((aligned(16))) union {
-    struct {
-      uint16_t A[2][SBM][SKC + SPAD];
-      uint16_t B[2][SBN][SKC + SPAD];
-    } st;
-    int32_t U[SBM * SBN];
-  } sm;
-  static_assert(sizeof(int32_t) * SBM * SBN <= 2 * (SBM + SBN) * (SKC + SPAD) * sizeof(uint16_t), "fold buffer");
-  auto& As = sm.st.A;
-  auto& Bs = sm.st.B;
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[GNST * GSTAGE];
+  __shared__ int32_t eas[GBM], fbs[GBN];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / GWN, wn = w % GWN;
   int tm, tn;
-  xcd_band_tile((int)blockIdx.x, (int)(mpad / SBM), (int)(npad / SBN), kBandRows, &tm, &tn);
-  const int64_t m0 = (int64_t)tm * SBM, n0 = (int64_t)tn * SBN;
-  // global -> register staging: each thread moves 4 x 16 bytes of A and of B per
-  // chunk: a 16-element quarter lq of rows lr and lr + 64 of the 64-k chunk
-  const int lr = tid >> 2, lq = (tid & 3) * 16;
-  // (named registers, not arrays: an array here was placed in scratch memory,
-  // which serialised every global load behind its store)
-  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-  const int nchunks = (int)(kpad / SKC);
+  xcd_band_tile((int)blockIdx.x, (int)(mpad / GBM), (int)(npad / GBN), kBandRows, &tm, &tn);
+  const int64_t m0 = (int64_t)tm * GBM, n0 = (int64_t)tn * GBN;
+  for (int r = tid; r < GBM; r += GNT) eas[r] = ea[m0 + r];
+  for (int c = tid; c < GBN; c += GNT) fbs[c] = fb[n0 + c];
+  const int nchunks = (int)(kpad / GKC);
 
-  auto gload = [&](int p, int q, int cc) {
-    const uint16_t* pa = Ap + ((int64_t)(p - 1) * mpad + m0) * kpad + (int64_t)cc * SKC + lq;
-    const uint16_t* pb = Bp + ((int64_t)(q - 1) * npad + n0) * kpad + (int64_t)cc * SKC + lq;
-    const uint4* a0 = reinterpret_cast<const uint4*>(pa + (int64_t)lr * kpad);
-    const uint4* a1 = reinterpret_cast<const uint4*>(pa + (int64_t)(lr + 64) * kpad);
-    const uint4* b0 = reinterpret_cast<const uint4*>(pb + (int64_t)lr * kpad);
-    const uint4* b1 = reinterpret_cast<const uint4*>(pb + (int64_t)(lr + 64) * kpad);
-    ra0 = a0[0]; ra1 = a0[1]; ra2 = a1[0]; ra3 = a1[1];
-    rb0 = b0[0]; rb1 = b0[1]; rb2 = b1[0]; rb3 = b1[1];
+  // direct loads: wave w fills tile rows [8 GALD w, +8 GALD) of A and
+  // [8 GBLD w, +8 GBLD) of B, 8 rows per 1-KB load; lane l writes slot (l & 7)
+  // of row (l >> 3) of the load's 8, which holds the row's k-chunk slot ^ gswz(row)
+  const int lrow = lane >> 3, lslot = lane & 7;
+  const uint16_t* a_src = Ap + (m0 + 8 * GALD * w + lrow) * kpad;
+  const uint16_t* b_src = Bp + (n0 + 8 * GBLD * w + lrow) * kpad;
+  const uint32_t lds0 = (uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char*)lds;
+  const uint32_t la0 = __builtin_amdgcn_readfirstlane(lds0 + (8 * GALD * w) * GROW);
+  const uint32_t lb0 = __builtin_amdgcn_readfirstlane(lds0 + GA + (8 * GBLD * w) * GROW);
+  auto issue = [&](int p, int q, int cc, int stage) {
+    const uint16_t* pa = a_src + (int64_t)(p - 1) * mpad * kpad + (int64_t)cc * GKC;
+    const uint16_t* pb = b_src + (int64_t)(q - 1) * npad * kpad + (int64_t)cc * GKC;
+    const uint32_t so = (uint32_t)stage * GSTAGE;
+#pragma unroll
+    for (int j = 0; j < GALD; ++j)
+      load_lds16(pa + (int64_t)8 * j * kpad + 8 * (lslot ^ gswz(8 * (GALD * w + j) + lrow)), la0 + so + 1024 * j);
+#pragma unroll
+    for (int j = 0; j < GBLD; ++j)
+      load_lds16(pb + (int64_t)8 * j * kpad + 8 * (lslot ^ gswz(8 * (GBLD * w + j) + lrow)), lb0 + so + 1024 * j);
   };
-  auto lstore = [&](int buf) {
-    *reinterpret_cast<uint4*>(&As[buf][lr][lq]) = ra0;
-    *reinterpret_cast<uint4*>(&As[buf][lr][lq + 8]) = ra1;
-    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq]) = ra2;
-    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq + 8]) = ra3;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq]) = rb0;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq + 8]) = rb1;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq]) = rb2;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq + 8]) = rb3;
+  const int fr = lane & 31, fh = lane >> 5;
+  const int a_row0 = wm * 64 + fr, b_row0 = wn * 64 + fr;
+  auto frags = [&](const unsigned char* As, const unsigned char* Bs, int kk, bf16x8 (&a)[2], bf16x8 (&b)[2]) {
+    const int ch = 2 * kk + fh;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = a_row0 + 32 * i;
+      a[i] = *reinterpret_cast<const bf16x8*>(As + r * GROW + ((ch ^ gswz(r)) << 4));
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int r = b_row0 + 32 * j;
+      b[j] = *reinterpret_cast<const bf16x8*>(Bs + r * GROW + ((ch ^ gswz(r)) << 4));
+    }
   };
 
-  const int fr = lane & 31, fk = 8 * (lane >> 5);
-  // The steps of one weight t run window by window; inside a window over the
-  // pairs (p, t-p), each over the window's chunks.  The next step is always
-  // prefetched, also across window boundaries (a window only folds the FP32
-  // accumulators into the integer sums) and across weights (the next weight's
-  // first step is loaded into registers before the slice-sum update).
-  struct Step { int c0, wlen, pi, ci; };
-  auto first_step = [&](int t) { return Step{0, nchunks < fold_window_chunks(t) ? nchunks : fold_window_chunks(t), 0, 0}; };
-  auto plo_of = [&](int t) { return t - s > 1 ? t - s : 1; };
-  {
-    const int t0 = s + 1;
-    gload(plo_of(t0), t0 - plo_of(t0), 0);
-    lstore(0);
-    __syncthreads();
-  }
   for (int t = s + 1; t >= 2; --t) {
-    const int plo = plo_of(t), phi = t - 1 < s ? t - 1 : s;
-    const int np = phi - plo + 1;
-    const int wc = fold_window_chunks(t);
+    const int plo = t - s > 1 ? t - s : 1, phi = t - 1 < s ? t - 1 : s;
+    const int np = phi - plo + 1, wc = window_k(t) / GKC;
+    const int nsteps = np * nchunks;
+    // prefetch cursor: window start, window length, pair, chunk in window
+    int f_c0 = 0, f_wl = nchunks < wc ? nchunks : wc, f_pi = 0, f_ci = 0;
+    auto fadv = [&]() {
+      if (++f_ci < f_wl) return;
+      f_ci = 0;
+      if (++f_pi < np) return;
+      f_pi = 0;
+      f_c0 += f_wl;
+      f_wl = (nchunks - f_c0) < wc ? (nchunks - f_c0) : wc;
+    };
+    int issued = 0;
+#pragma unroll
+    for (int x = 0; x < GNST - 1; ++x) {
+      if (issued < nsteps) {
+        issue(plo + f_pi, t - plo - f_pi, f_c0 + f_ci, x);
+        fadv();
+        ++issued;
+      }
+    }
+    if (issued >= 2)
+      wait_vm_barrier<GLD>();  // step 0 has landed, step 1 may be in flight
+    else
+      wait_vm_barrier<0>();
     int32_t U[2][2][16];  // exact: |U_t| < 8192 * 10 * 2^14 < 2^31 for K panels of at most 8192
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -379,88 +447,84 @@ __global__ __launch_bounds__(256, 2) void split_gemm(int64_t m, int64_t n, int64
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) U[i][j][v] = 0;
-    f32x16 acc[2][2];
+    int stage = 0, st = 0;
+    for (int c0 = 0; c0 < nchunks; c0 += wc) {
+      const int wl = (nchunks - c0) < wc ? (nchunks - c0) : wc;
+      const int wsteps = np * wl;
+      f32x16 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
-    const int nsteps = np * nchunks;
-    Step cur = first_step(t);
-    for (int st = 0; st < nsteps; ++st) {
-      const int buf = st & 1;
-      // the step after this one (within weight t)
-      Step nx = cur;
-      bool window_end = false;
-      if (++nx.ci == nx.wlen) {
-        nx.ci = 0;
-        if (++nx.pi == np) {
-          nx.pi = 0;
-          window_end = true;
-          nx.c0 += nx.wlen;
-          nx.wlen = (nchunks - nx.c0) < wc ? (nchunks - nx.c0) : wc;
+          for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+      for (int x = 0; x < wsteps; ++x, ++st) {
+        const bool more = issued < nsteps;
+        if (more) {  // two steps ahead, into the stage every wave left at the last barrier
+          issue(plo + f_pi, t - plo - f_pi, f_c0 + f_ci, stage == 0 ? GNST - 1 : stage - 1);
+          fadv();
+          ++issued;
         }
+        const unsigned char* As = lds + stage * GSTAGE;
+        const unsigned char* Bs = As + GA;
+        bf16x8 a0[2], b0[2], a1[2], b1[2];
+        frags(As, Bs, 0, a0, b0);
+#pragma unroll
+        for (int kk = 0; kk < GKC / 16; ++kk) {
+          // fragments of the next k16 step are read while this one multiplies
+          if (kk % 2 == 0) {
+            if (kk + 1 < GKC / 16) frags(As, Bs, kk + 1, a1, b1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[i], b0[j], acc[i][j], 0, 0, 0);
+          } else {
+            if (kk + 1 < GKC / 16) frags(As, Bs, kk + 1, a0, b0);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[i], b1[j], acc[i][j], 0, 0, 0);
+          }
+        }
+        // the next step has landed (the one after it may still be in flight),
+        // and every wave is done with this step's stage
+        if (issued - (st + 2) >= 1)
+          wait_vm_barrier<GLD>();
+        else
+          wait_vm_barrier<0>();
+        stage = stage == GNST - 1 ? 0 : stage + 1;
       }
-      const bool more = st + 1 < nsteps;
-      if (more) gload(plo + nx.pi, t - (plo + nx.pi), nx.c0 + nx.ci);
+      // fold the window's FP32 sums into the int32 weight sums (exact)
 #pragma unroll
-      for (int kk = 0; kk < SKC; kk += 16) {
-        bf16x8 a[2], b[2];
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 32 + fr][kk + fk]);
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 32 + fr][kk + fk]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      if (window_end || !more) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              U[i][j][v] += (int32_t)acc[i][j][v];
-              acc[i][j][v] = 0.f;
-            }
-      }
-      if (more) lstore(buf ^ 1);
-      __syncthreads();
-      cur = nx;
+          for (int v = 0; v < 16; ++v) U[i][j][v] += (int32_t)acc[i][j][v];
     }
-    // prefetch the next weight's first step while the slice sums are added
-    if (t > 2) gload(plo_of(t - 1), (t - 1) - plo_of(t - 1), 0);
-    // S = S + U_t 2^(e_i + f_j - 8t), from the smallest weight up.  The sums go
-    // through LDS (the staging buffers are idle now) so that the update below
-    // walks the tile row by row with consecutive threads on consecutive columns.
-    int32_t* Ul = sm.U;  // [SBM][SBN]
-    __syncthreads();
+    // the weight's sums through LDS (every stage is idle), then the FP64 slice-sum update
+    int32_t* Ul = reinterpret_cast<int32_t*>(lds);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v)
-          Ul[(wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4)) * SBN + wn * 64 + j * 32 + (lane & 31)] =
-              U[i][j][v];
-    __syncthreads();
-    slice_sum_update(Ul, t, s, 8, tid, m0, n0, m, n, npad, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
-    __syncthreads();  // LDS is staging space again
-    if (t > 2) {
-      lstore(0);
-      __syncthreads();
-    }
+          Ul[(wm * 64 + 32 * i + 8 * (v >> 2) + 4 * fh + (v & 3)) * GBN + wn * 64 + 32 * j + fr] = U[i][j][v];
+    wait_vm_barrier<0>();
+    slice_sum_update<GBM, GBN, GNT>(Ul, eas, fbs, t, s, 8, tid, m0, n0, m, n, npad, Sws, alpha, beta, C, ldc, gamma,
+                                    D, ldd);
+    wait_vm_barrier<0>();  // LDS is staging space again
   }
 }
 
 // INT8 slice products on V_MFMA_I32_32X32X32_I8 (lane l supplies A[l%32][16*(l/32) .. +16]
-// and B[16*(l/32) .. +16][l%32]; accumulator layout as for the BF16 form).  The
-// same tiling and staging as split_gemm, byte for byte: a 128-k chunk of INT8
-// planes is the 128 bytes of a 64-k BF16 chunk, and tiles are dealt to the
-// XCDs in the same bands (xcd_band_tile).  A product of two INT8 slices is
+// and B[16*(l/32) .. +16][l%32]; accumulator layout as for the BF16 form).
+// 128 x 128 tiles of 4 waves (64 x 64 each), two workgroups per CU, 128-k
+// chunks (128 bytes per row) staged in LDS through registers, double-buffered,
+// and tiles dealt to the XCDs in bands (xcd_band_tile).  A product of two INT8 slices is
 // below 2^14 and the INT32 accumulation is exact, so no windows: one weight's
 // sum over every pair and the whole K panel (at most 8192 k:
 // |U_t| < 8 * 8192 * 2^14 = 2^30) stays in the accumulators.
@@ -575,7 +639,8 @@ __global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, in
           Ul[(wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4)) * SBN + wn * 64 + j * 32 + (lane & 31)] =
               acc[i][j][v];
     __syncthreads();
-    slice_sum_update(Ul, t, s, 7, tid, m0, n0, m, n, npad, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
+    slice_sum_update<SBM, SBN, 256>(Ul, ea + m0, fb + n0, t, s, 7, tid, m0, n0, m, n, npad, Sws, alpha, beta, C, ldc,
+                                    gamma, D, ldd);
     __syncthreads();  // LDS is staging space again
     if (t > 2) {
       lstore(0);
@@ -586,17 +651,20 @@ __global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, in
 
 inline int64_t pad64(int64_t x) { return (x + 63) / 64 * 64; }
 inline int64_t pad128(int64_t x) { return (x + 127) / 128 * 128; }
+inline int64_t pad256(int64_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
 // Workspace: A planes [s][mp][kp], B planes [s][np][kp] (BF16 or INT8),
 // row and column exponents (int32), column maxima (uint64), slice-sum tile
-// [mp][np] (FP64), with mp, np = m, n rounded up to 128 and kp = k rounded up
+// [mp][np] (FP64), with mp = m rounded up to the slice-product kernel's tile
+// rows (256 BF16, 128 INT8), np = n rounded up to 128 and kp = k rounded up
 // to a whole number of 128-byte chunks (64 BF16 or 128 INT8 elements).
 static int64_t pad_k(int64_t k, SliceFormat f) { return f == kSliceInt8 ? pad128(k) : pad64(k); }
+static int64_t pad_m(int64_t m, SliceFormat f) { return f == kSliceInt8 ? pad128(m) : pad256(m); }
 
 size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat f) {
-  const int64_t mp = pad128(m), np = pad128(n), kp = pad_k(k < kSplitMaxK ? k : kSplitMaxK, f);
+  const int64_t mp = pad_m(m, f), np = pad128(n), kp = pad_k(k < kSplitMaxK ? k : kSplitMaxK, f);
   return (size_t)((int64_t)f * s * (mp + np) * kp + 4 * (mp + np) + 8 * np + 8 * mp * np);
 }
 
@@ -632,7 +700,7 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
   if (m <= 0 || n <= 0) return hipSuccess;
   if (s < 1 || s > 8) return hipErrorInvalidValue;
   if (k <= 0) return launch_dgemm_f64(m, n, 0, alpha, nullptr, 1, nullptr, 1, beta, C, ldc, gamma, D, ldd, stream);
-  const int64_t mp = pad128(m), np = pad128(n), kp = pad_k(k, f);
+  const int64_t mp = pad_m(m, f), np = pad128(n), kp = pad_k(k, f);
   if (split_workspace_bytes(m, n, k, s, f) > ws_bytes) return hipErrorInvalidValue;
   const int eb = (int)f;
   uint8_t* Ap = static_cast<uint8_t*>(workspace);
@@ -677,17 +745,17 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
   hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
   with_s(slice_b);
   // one-dimensional grids: the kernels map workgroups to tiles in XCD bands
-  const dim3 grid((unsigned)((np / SBN) * (mp / SBM)));
+  const dim3 grid8((unsigned)((np / SBN) * (mp / SBM))), grid16((unsigned)((np / GBN) * (mp / GBM)));
   const bool timed = timer && timer->used < timer->count;
   if (timed) {
     const hipError_t e = hipEventRecord(timer->events[2 * timer->used], stream);
     if (e != hipSuccess) return e;
   }
   if (f == kSliceInt8)
-    hipLaunchKernelGGL(split_gemm_i8, grid, dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
+    hipLaunchKernelGGL(split_gemm_i8, grid8, dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
                        beta, C, ldc, gamma, D, ldd);
   else
-    hipLaunchKernelGGL(split_gemm, grid, dim3(256), 0, stream, m, n, kp, s, reinterpret_cast<const uint16_t*>(Ap),
+    hipLaunchKernelGGL(split_gemm, grid16, dim3(GNT), 0, stream, m, n, kp, s, reinterpret_cast<const uint16_t*>(Ap),
                        reinterpret_cast<const uint16_t*>(Bp), mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
