@@ -11,6 +11,7 @@ Contents
                  executor/hazard checker for an operation list
   split_ref.py   the split-BF16 product (error-free slicing, Ozaki et al. 2012)
   mlp_ref.py     the MLP planner network: forward, backward, MSE, Adam in FP64
+  chol_ref.py    Cholesky factorisation and symmetric rank-k update (plain definitions)
 """
 import ctypes
 import os

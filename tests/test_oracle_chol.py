@@ -1,0 +1,117 @@
+"""Pins of the Cholesky and rank-k-update references (oracle/chol_ref.py)
+against results the mathematics fixes: exact factors of integer SPD matrices,
+closed forms, the breakdown column of indefinite matrices, the backward-error
+bound, and brute force on tiny inputs."""
+import numpy as np
+import pytest
+
+from oracle import chol_ref
+
+
+def _int_factor(n, seed, lo=-3, hi=3, dmax=4):
+    """A random integer lower-triangular L with positive diagonal."""
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.integers(lo, hi + 1, (n, n)).astype(np.float64), -1)
+    L[np.arange(n), np.arange(n)] = rng.integers(1, dmax + 1, n)
+    return L
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (40, 3), (123, 4)])
+def test_integer_factor_recovered_exactly(n, seed):
+    # A = L L^T has integer entries below 2^53; every pivot is the square of
+    # an integer and every quotient divides exactly, so the factor comes back
+    # bit for bit (a transposed operand, a wrong index or sign breaks this)
+    L = _int_factor(n, seed)
+    A = L @ L.T
+    assert np.array_equal(chol_ref.potrf_lower(A), L)
+
+
+def test_upper_triangle_is_not_read():
+    L = _int_factor(9, 5)
+    A = L @ L.T
+    A[np.triu_indices(9, 1)] = np.nan
+    assert np.array_equal(chol_ref.potrf_lower(A), L)
+
+
+def test_identity_and_diagonal():
+    assert np.array_equal(chol_ref.potrf_lower(np.eye(5)), np.eye(5))
+    d = np.array([4.0, 9.0, 2.0, 0.25, 1e-6])
+    assert np.array_equal(chol_ref.potrf_lower(np.diag(d)), np.diag(np.sqrt(d)))
+
+
+def test_tridiagonal_laplacian_closed_form():
+    # tridiag(-1, 2, -1): pivots (k+1)/k (1-based), so l_kk = sqrt((k+1)/k)
+    # and l_{k+1,k} = -sqrt(k/(k+1))
+    n = 30
+    A = 2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    L = chol_ref.potrf_lower(A)
+    k = np.arange(1, n + 1, dtype=np.float64)
+    assert np.allclose(np.diag(L), np.sqrt((k + 1) / k), rtol=1e-15, atol=0)
+    assert np.allclose(np.diag(L, -1), -np.sqrt(k[:-1] / (k[:-1] + 1)), rtol=1e-15, atol=0)
+    assert np.all(np.tril(L, -2) == 0.0)
+
+
+def test_two_by_two_by_hand():
+    A = np.array([[4.0, 6.0], [6.0, 25.0]])
+    # l11 = 2, l21 = 6/2 = 3, l22 = sqrt(25 - 9) = 4
+    assert np.array_equal(chol_ref.potrf_lower(A), np.array([[2.0, 0.0], [3.0, 4.0]]))
+
+
+@pytest.mark.parametrize("col", [0, 3, 6])
+def test_breakdown_column(col):
+    L = _int_factor(8, 7)
+    A = L @ L.T
+    # make pivot `col` zero: subtract its value from the diagonal entry
+    A[col, col] -= L[col, col] ** 2
+    with pytest.raises(chol_ref.NotPositiveDefinite) as ei:
+        chol_ref.potrf_lower(A)
+    assert ei.value.column == col
+
+
+def test_backward_error_bound_random_spd():
+    rng = np.random.default_rng(11)
+    n = 200
+    G = rng.standard_normal((n, n))
+    A = G @ G.T / n + np.eye(n)
+    L = chol_ref.potrf_lower(A)
+    R = np.abs(A - L @ L.T)
+    # L @ L.T itself rounds; the bound of Theorem 10.3 has room for it at this n
+    assert np.all(R <= 2.0 * chol_ref.backward_bound(L))
+    # and it is not vacuous: a perturbed factor fails it
+    Lb = L.copy()
+    Lb[n // 2, n // 3] += 1e-9
+    assert not np.all(np.abs(A - Lb @ Lb.T) <= 2.0 * chol_ref.backward_bound(Lb))
+
+
+def test_syrk_brute_force_and_triangles():
+    rng = np.random.default_rng(3)
+    n, k = 6, 5
+    A = rng.integers(-4, 5, (n, k)).astype(np.float64)
+    C = rng.integers(-9, 10, (n, n)).astype(np.float64)
+    got = chol_ref.syrk_lower(1.5, A, -2.0, C)
+    for i in range(n):
+        for j in range(n):
+            if i >= j:
+                s = 0.0
+                for kk in range(k):
+                    s += A[i, kk] * A[j, kk]
+                assert got[i, j] == 1.5 * s - 2.0 * C[i, j]
+            else:
+                assert got[i, j] == C[i, j]
+
+
+def test_syrk_beta_zero_ignores_lower_c():
+    A = np.arange(12, dtype=np.float64).reshape(4, 3)
+    C = np.full((4, 4), np.nan)
+    got = chol_ref.syrk_lower(1.0, A, 0.0, C)
+    low = np.tril(np.ones((4, 4), dtype=bool))
+    assert np.array_equal(got[low], (A @ A.T)[low])
+    assert np.all(np.isnan(got[~low]))
+
+
+def test_factor_of_syrk_result():
+    # potrf(syrk(I-shifted)) round trip on integers: A = L L^T built by syrk
+    L = _int_factor(17, 9)
+    A = chol_ref.syrk_lower(1.0, L, 0.0, np.zeros((17, 17)))
+    A = np.tril(A) + np.tril(A, -1).T
+    assert np.array_equal(chol_ref.potrf_lower(A), L)
