@@ -47,7 +47,8 @@ typedef enum {
   OOC_ERR_HIP = 5,        /* a HIP runtime call failed (message in ooc_last_error) */
   OOC_ERR_NO_DEVICE = 6,  /* no usable gfx950 device with that ordinal */
   OOC_ERR_INJECTED = 7,   /* failure injected by OOC_FAIL_AT (tests of error paths) */
-  OOC_ERR_CAPACITY = 8    /* an output array is too small (ooc_schedule, ooc_plan_candidates) */
+  OOC_ERR_CAPACITY = 8,   /* an output array is too small (ooc_schedule, ooc_plan_candidates) */
+  OOC_ERR_NOT_SPD = 9     /* ooc_potrf: the matrix is not positive definite (see its info) */
 } ooc_status;
 
 /* FP64: tile products in FP64 on matrix cores.  SPLIT_BF16: each tile product
@@ -186,6 +187,19 @@ ooc_status ooc_gemm(int64_t M, int64_t N, int64_t K, double alpha,
                     double beta, double* C, int64_t ldc, size_t budget_bytes,
                     const ooc_opts* opts, ooc_stats* stats);
 
+/* The product with a transposed B and an optional triangular result:
+ *     C = alpha * A * op(B) + beta * C
+ * op(B) = B (transb == 0; B is K x N, ldb >= N) or B^T (transb == 1; B is
+ * N x K, ldb >= K: the symmetric rank-k update and the Cholesky updates use
+ * op(B) = A^T).  lower == 1 computes only the elements C_ij with i >= j (FP64
+ * precision only, OOC_ERR_ARG otherwise): C blocks wholly above the diagonal
+ * are skipped, and the elements with i < j of blocks that straddle it are
+ * copied to the device and back unchanged (never read by the arithmetic, so
+ * NaN there stays NaN).  Everything else as for ooc_gemm. */
+ooc_status ooc_gemm_ex(int32_t transb, int32_t lower, int64_t M, int64_t N, int64_t K, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, size_t budget_bytes, const ooc_opts* opts, ooc_stats* stats);
+
 /* Choose a plan for the problem and budget (host only, no device access). */
 ooc_status ooc_plan(int64_t M, int64_t N, int64_t K, double beta, size_t budget_bytes,
                     const ooc_opts* opts, ooc_plan_t* out);
@@ -230,12 +244,26 @@ typedef enum {
   OOC_OP_H2D = 0,        /* host submatrix -> device buffer (2-D pitched copy) */
   OOC_OP_D2H = 1,        /* device buffer -> host submatrix */
   OOC_OP_GEMM = 2,       /* FP64 tile product c = alpha*a*b + beta*c + gamma*d on device buffers */
-  OOC_OP_SPLIT_GEMM = 3  /* the same product from BF16 or INT8 slices (the plan's precision): slices
+  OOC_OP_SPLIT_GEMM = 3, /* the same product from BF16 or INT8 slices (the plan's precision): slices
                             and exponents of the A and B panels are written to the workspace
                             (off_w, len_w), then multiplied */
+  OOC_OP_POTRF = 4,      /* Cholesky factorisation in place of the rows x rows block at off_c (ld_c):
+                            its lower triangle becomes L with block = L L^T, the strict upper triangle
+                            is untouched; a pivot that is not positive stores k0 + its column + 1 in
+                            the double at off_w if that is still 0 (later columns unspecified) */
+  OOC_OP_TRSM = 5        /* X <- X L^{-T}: X is rows x cols at off_c (ld_c), L the cols x cols lower
+                            triangle at off_a (ld_a) */
 } ooc_op_kind;
 
 #define OOC_MAX_WAITS 6
+
+/* Flags of product ops.  TRANSB: the B panel holds B^T (n x k, leading
+ * dimension ld_b >= k).  LOWER: only elements of c on or below the diagonal
+ * of the whole result are written, element (r, c) of the block at
+ * (row0, col0) when row0 + r >= col0 + c; the others are neither read nor
+ * written (FP64 products only). */
+#define OOC_OPF_TRANSB 1
+#define OOC_OPF_LOWER 2
 
 typedef struct {
   int32_t kind;               /* ooc_op_kind */
@@ -243,8 +271,10 @@ typedef struct {
   int32_t task;               /* index of the tile task this op serves */
   int32_t nwait;              /* entries used in wait[] */
   int32_t wait[OOC_MAX_WAITS];/* earlier ops (other streams) that must complete first */
-  int32_t mat;                /* copies: 0 = A, 1 = B, 2 = C */
+  int32_t mat;                /* copies: host matrix index (ooc_gemm: 0 = A, 1 = B, 2 = C) */
   int32_t slot;               /* device buffer index within its operand's pool */
+  int32_t flags;              /* GEMM / SPLIT_GEMM: OOC_OPF_* bits */
+  int32_t reserved;           /* 0 */
   int64_t row0, col0;         /* copies: host submatrix origin; GEMM: C block origin (i0, j0) */
   int64_t rows, cols;         /* copies: submatrix extent; GEMM: m, n */
   int64_t k0, k;              /* GEMM: K panel origin and length */
@@ -262,6 +292,78 @@ typedef struct {
 ooc_status ooc_schedule(int64_t M, int64_t N, int64_t K, double alpha, double beta,
                         const ooc_plan_t* plan, ooc_op* ops, int64_t cap, int64_t* nops,
                         uint64_t* arena_bytes);
+
+/* ooc_schedule for the ooc_gemm_ex forms (host only). */
+ooc_status ooc_schedule_ex(int32_t transb, int32_t lower, int64_t M, int64_t N, int64_t K, double alpha,
+                           double beta, const ooc_plan_t* plan, ooc_op* ops, int64_t cap, int64_t* nops,
+                           uint64_t* arena_bytes);
+
+/* ---- the general pipeline: operation lists on the HIP backend --------------------
+ * The product is planned (ooc_plan), turned into an operation list
+ * (ooc_schedule) and run by an executor.  The executor is open to other
+ * out-of-core algorithms built from the same operations -- copies between
+ * host submatrices and a device arena, and the kernels of ooc_op_kind -- the
+ * paper's host-controls-device model (Sections III-IV: the host issues
+ * asynchronous copies and kernels on streams, ordered by events) as an
+ * interface.  ooc_potrf is built this way. */
+typedef struct {
+  double* ptr;            /* page-locked host memory, row-major */
+  int64_t rows, cols, ld; /* ld >= cols (elements) */
+} ooc_host_matrix;
+
+/* Run ops[0 .. nops) on device opts->device.  Op x first waits for the ops
+ * in its wait set (earlier ops only, any stream), then runs on stream
+ * op.stream (0, 1 or 2; a stream runs its ops in list order).  Copies move
+ * the rows x cols submatrix at (row0, col0) of mats[op.mat] to or from the
+ * arena at element off_c with leading dimension ld_c; kernels read and
+ * write the arena as ooc_op_kind states.  The arena is arena_bytes of device
+ * memory: opts->arena when given, else the device's cached arena; SPLIT_GEMM
+ * ops use opts->precision and opts->slices.  Before anything is issued every
+ * op is validated (kind, stream, waits, copies inside their host matrix,
+ * every kernel operand inside the arena): OOC_ERR_ARG names the first
+ * offender.  The ordering is the caller's: two ops that touch a common arena
+ * element, one of them writing it, must be ordered by a stream or a chain of
+ * waits (ooc_check_ops finds violations).  Returns after every stream has
+ * drained; stats as for ooc_gemm (plan left zero). */
+ooc_status ooc_run_ops(const ooc_op* ops, int64_t nops, const ooc_host_matrix* mats, int32_t nmats,
+                       uint64_t arena_bytes, const ooc_opts* opts, ooc_stats* stats);
+
+/* Ordering check of an operation list (host only): OOC_OK if every two ops
+ * that touch a common arena element, one of them writing it, are ordered;
+ * else OOC_ERR_ARG with *x > *y the first such pair.  OOC_ERR_CAPACITY above
+ * 32768 ops (the check keeps an nops x nops bit matrix). */
+ooc_status ooc_check_ops(const ooc_op* ops, int64_t nops, int64_t* x, int64_t* y);
+
+/* ---- out-of-core level-3 routines built on the pipeline ---------------------------
+ * The paper names level-3 routines and dense factorisations whose bulk of
+ * work is the out-of-core product as the next step (Section VII). */
+
+/* Symmetric rank-k update C = alpha * A * A^T + beta * C on the lower
+ * triangle (i >= j) of the N x N matrix C (ldc >= N); A is N x K (lda >= K).
+ * The strict upper triangle of C is left unchanged.  This is
+ * ooc_gemm_ex(1, 1, N, N, K, alpha, A, lda, A, lda, beta, C, ldc, ...): the
+ * blocks wholly above the diagonal are not computed. */
+ooc_status ooc_syrk(int64_t N, int64_t K, double alpha, const double* A, int64_t lda, double beta, double* C,
+                    int64_t ldc, size_t budget_bytes, const ooc_opts* opts, ooc_stats* stats);
+
+/* Cholesky factorisation A = L L^T of the N x N symmetric positive definite
+ * matrix A in place (row-major, lda >= N, page-locked): the lower triangle is
+ * read and overwritten by L; the strict upper triangle is left unchanged.
+ * Left-looking by block columns of b columns (the largest multiple of 64 up
+ * to 8192 whose b x b block and two 256-row chunks fit the budget): the
+ * update of a block column by the columns to its left is one out-of-core
+ * product (C = C - A B^T on the lower triangle, ooc_gemm_ex); its diagonal
+ * block is factored on the device and the rows below are solved against it
+ * chunk by chunk (an operation list of POTRF and TRSM ops on the executor).
+ * Every quotient is a true division: an integer SPD matrix with an integer
+ * factor gets it exactly.  *info = 0 on success; OOC_ERR_NOT_SPD with
+ * *info = j + 1 for the first column j whose pivot is not positive (the
+ * block columns before j's hold L, the rest of the lower triangle is
+ * unspecified).  The products run in FP64 whatever opts->precision says.
+ * stats: totals over the calls (flops = N^3/3 + N^2/2 + N/6, bytes, times;
+ * blocks_done = block columns finished). */
+ooc_status ooc_potrf(int64_t N, double* A, int64_t lda, size_t budget_bytes, const ooc_opts* opts, int64_t* info,
+                     ooc_stats* stats);
 
 /* ---- accumulation sessions: repeated invocation ----------------------------------
  * The paper's MMOOC can serve as the local step of an outer algorithm (SUMMA or

@@ -25,7 +25,10 @@ An operation is a dict with keys
   stream, waits (list of earlier op indices), task
   copies: mat ('A'|'B'|'C'), row0, col0, rows, cols, dev_off, dev_ld (elements)
   gemm:   m, n, k, i0, j0, k0, off_a, lda, off_b, ldb, off_c, ldc, alpha, beta
-          and optionally off_d, ldd, gamma: c = alpha*a@b + beta*c + gamma*d
+          and optionally off_d, ldd, gamma: c = alpha*a@b + beta*c + gamma*d;
+          transb: b is stored transposed (n x k); lower: only the elements of
+          c with i0 + r >= j0 + c (on or below the diagonal of the whole
+          result) are computed and written
   other kernels: reads / writes, lists of (offset, rows, cols, ld) device regions.
 """
 import random
@@ -127,7 +130,8 @@ def _regions(op):
     if k == "d2h":
         return [(op["dev_off"], op["rows"], op["cols"], op["dev_ld"])], []
     if k in ("gemm", "split_gemm"):
-        reads = [(op["off_a"], op["m"], op["k"], op["lda"]), (op["off_b"], op["k"], op["n"], op["ldb"])]
+        b = (op["off_b"], op["n"], op["k"], op["ldb"]) if op.get("transb") else (op["off_b"], op["k"], op["n"], op["ldb"])
+        reads = [(op["off_a"], op["m"], op["k"], op["lda"]), b]
         if k == "split_gemm" and op.get("len_w", 0) > 0:
             ws = (op["off_w"], 1, op["len_w"], op["len_w"])
             if op["beta"] != 0.0:
@@ -202,9 +206,10 @@ def _host_rect(op):
     return op["i0"], op["j0"], op["m"], op["n"]
 
 
-def check_cover(ops, M, N, K, returns_home=True):
+def check_cover(ops, M, N, K, returns_home=True, lower=False):
     """Coverage of the result by an operation list.  Returns a list of
-    problems (empty = fine):
+    problems (empty = fine); with lower, only the elements C_ij with i >= j
+    are owed (cells wholly above the diagonal are not checked):
       * every C element is returned to the host (d2h of mat 'C') exactly once
         (with returns_home=False, for C that stays on the device between the
         steps of an accumulation session: never);
@@ -231,6 +236,8 @@ def check_cover(ops, M, N, K, returns_home=True):
             if rows[ri + 1] <= r0 or cols[ci + 1] <= c0:
                 continue
             cell = f"C[{r0}:{rows[ri + 1]}, {c0}:{cols[ci + 1]}]"
+            if lower and rows[ri + 1] - 1 < c0:
+                continue  # every element of the cell lies above the diagonal
             home = [x for x in homes if covers(ops[x], r0, c0)]
             if len(home) != (1 if returns_home else 0):
                 problems.append(f"{cell} returned {len(home)} times")
@@ -301,7 +308,10 @@ def execute(ops, A, B, C, arena_elems, seed=0, poison=np.nan, kernels=None, aren
                 view(op["dev_off"], op["rows"], op["cols"], op["dev_ld"])
         elif k == "gemm":
             a = view(op["off_a"], op["m"], op["k"], op["lda"])
-            b = view(op["off_b"], op["k"], op["n"], op["ldb"])
+            if op.get("transb"):
+                b = view(op["off_b"], op["n"], op["k"], op["ldb"]).T
+            else:
+                b = view(op["off_b"], op["k"], op["n"], op["ldb"])
             c = view(op["off_c"], op["m"], op["n"], op["ldc"])
             prod = a @ b if op["k"] else np.zeros((op["m"], op["n"]))
             if op["alpha"] == 0.0:
@@ -311,7 +321,12 @@ def execute(ops, A, B, C, arena_elems, seed=0, poison=np.nan, kernels=None, aren
                 res = res + op["beta"] * c
             if op.get("gamma", 0.0) != 0.0:
                 res = res + op["gamma"] * view(op["off_d"], op["m"], op["n"], op["ldd"])
-            c[...] = res
+            if op.get("lower"):
+                r, cc = np.indices((op["m"], op["n"]))
+                keep = op["i0"] + r >= op["j0"] + cc
+                c[keep] = res[keep]
+            else:
+                c[...] = res
         else:
             if kernels is None or k not in kernels:
                 raise ValueError(f"no CPU model for op kind {k}")

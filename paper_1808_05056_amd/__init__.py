@@ -27,15 +27,17 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ---- ABI types (mirror include/ooc.h) ------------------------------------------------
 
 OOC_OK, OOC_ERR_ARG, OOC_ERR_BUDGET, OOC_ERR_DEVICE_MEM, OOC_ERR_NOT_PINNED, OOC_ERR_HIP, \
-    OOC_ERR_NO_DEVICE, OOC_ERR_INJECTED, OOC_ERR_CAPACITY = range(9)
+    OOC_ERR_NO_DEVICE, OOC_ERR_INJECTED, OOC_ERR_CAPACITY, OOC_ERR_NOT_SPD = range(10)
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_BUDGET", 3: "ERR_DEVICE_MEM", 4: "ERR_NOT_PINNED", 5: "ERR_HIP",
-                6: "ERR_NO_DEVICE", 7: "ERR_INJECTED", 8: "ERR_CAPACITY"}
+                6: "ERR_NO_DEVICE", 7: "ERR_INJECTED", 8: "ERR_CAPACITY", 9: "ERR_NOT_SPD"}
 FP64, SPLIT_BF16, SPLIT_INT8 = 0, 1, 2
 PLAN_AUTO, PLAN_PAPER, PLAN_MODEL, PLAN_MLP = 0, 1, 2, 3
 ORDER_COLS, ORDER_ROWS, ORDER_COLS_P, ORDER_ROWS_P, ORDER_COLS_PS, ORDER_ROWS_PS = 0, 1, 2, 3, 4, 5
-OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM = range(4)
-OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_gemm"}
+OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM, OP_POTRF, OP_TRSM = range(6)
+OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_gemm", 4: "potrf", 5: "trsm"}
+OP_KINDS = {v: k for k, v in OP_NAMES.items()}
 MAX_WAITS = 6
+OPF_TRANSB, OPF_LOWER = 1, 2
 
 i32, i64, u64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -61,6 +63,10 @@ class ooc_opts(ctypes.Structure):
                 ("streams", vp * 3), ("release_arena", i32)]
 
 
+class ooc_host_matrix(ctypes.Structure):
+    _fields_ = [("ptr", vp), ("rows", i64), ("cols", i64), ("ld", i64)]
+
+
 class ooc_stats(ctypes.Structure):
     _fields_ = [("plan", ooc_plan_t), ("t_total_s", dbl), ("t_pipeline_s", dbl), ("t_h2d_busy_s", dbl),
                 ("t_d2h_busy_s", dbl), ("t_kernel_busy_s", dbl), ("t_predicted_s", dbl), ("flops", dbl),
@@ -76,7 +82,8 @@ class ooc_stats(ctypes.Structure):
 
 class ooc_op(ctypes.Structure):
     _fields_ = [("kind", i32), ("stream", i32), ("task", i32), ("nwait", i32), ("wait", i32 * MAX_WAITS),
-                ("mat", i32), ("slot", i32), ("row0", i64), ("col0", i64), ("rows", i64), ("cols", i64),
+                ("mat", i32), ("slot", i32), ("flags", i32), ("reserved", i32), ("row0", i64), ("col0", i64),
+                ("rows", i64), ("cols", i64),
                 ("k0", i64), ("k", i64), ("off_a", i64), ("ld_a", i64), ("off_b", i64), ("ld_b", i64),
                 ("off_c", i64), ("ld_c", i64), ("off_d", i64), ("ld_d", i64), ("off_w", i64), ("len_w", i64),
                 ("alpha", dbl), ("beta", dbl), ("gamma", dbl)]
@@ -102,6 +109,13 @@ _sig("ooc_plan_candidates", i32, [i64, i64, i64, dbl, sz, P(ooc_opts), P(ooc_pla
 _sig("ooc_plan_predict", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(dbl)])
 _sig("ooc_plan_simulate", i32, [i64, i64, i64, dbl, P(ooc_plan_t), P(dbl), i64, P(i64)])
 _sig("ooc_schedule", i32, [i64, i64, i64, dbl, dbl, P(ooc_plan_t), P(ooc_op), i64, P(i64), P(u64)])
+_sig("ooc_schedule_ex", i32, [i32, i32, i64, i64, i64, dbl, dbl, P(ooc_plan_t), P(ooc_op), i64, P(i64), P(u64)])
+_sig("ooc_syrk", i32, [i64, i64, dbl, vp, i64, dbl, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
+_sig("ooc_potrf", i32, [i64, vp, i64, sz, P(ooc_opts), P(i64), P(ooc_stats)])
+_sig("ooc_run_ops", i32, [P(ooc_op), i64, P(ooc_host_matrix), i32, u64, P(ooc_opts), P(ooc_stats)])
+_sig("ooc_check_ops", i32, [P(ooc_op), i64, P(i64), P(i64)])
+_sig("ooc_gemm_ex", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, sz, P(ooc_opts),
+                          P(ooc_stats)])
 _sig("ooc_accum_begin", i32, [i64, i64, dbl, vp, i64, sz, P(ooc_opts), P(vp)])
 _sig("ooc_accum_step", i32, [vp, i64, dbl, vp, i64, vp, i64, P(ooc_stats)])
 _sig("ooc_accum_end", i32, [vp, P(ooc_stats)])
@@ -134,7 +148,7 @@ _sig("ooc_mlp_predict", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P(dbl)
 _sig("ooc_last_error", ctypes.c_char_p, [])
 _sig("ooc_version", ctypes.c_char_p, [])
 
-EXPORTS = ["ooc_gemm", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
+EXPORTS = ["ooc_gemm", "ooc_gemm_ex", "ooc_schedule_ex", "ooc_syrk", "ooc_potrf", "ooc_run_ops", "ooc_check_ops", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_device_copy", "ooc_dgemm_device",
            "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_split_gemm_device_noalloc", "ooc_mlp_features", "ooc_mlp_forward",
@@ -214,6 +228,94 @@ def ooc_gemm(alpha, A, B, beta, C, budget_bytes, opts=None, raise_on_error=True)
     return s, st
 
 
+def ooc_gemm_ex(alpha, A, B, beta, C, budget_bytes, transb=False, lower=False, opts=None, raise_on_error=True):
+    """C = alpha*A@op(B) + beta*C in place with op(B) = B.T when transb (B is N x K);
+    with lower only C's elements on and below the diagonal.  Returns (status, ooc_stats)."""
+    M, N = C.shape
+    K = A.shape[1] if A is not None else 0
+    pa, lda = _mat_arg(A, "A")
+    pb, ldb = _mat_arg(B, "B")
+    pc, ldc = _mat_arg(C, "C")
+    st = ooc_stats()
+    s = _lib.ooc_gemm_ex(1 if transb else 0, 1 if lower else 0, M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc,
+                         budget_bytes, ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
+
+
+def ooc_syrk(alpha, A, beta, C, budget_bytes, opts=None, raise_on_error=True):
+    """C = alpha*A@A.T + beta*C on the lower triangle of C (N x N); A is N x K.  Returns (status, ooc_stats)."""
+    N = C.shape[0]
+    K = A.shape[1]
+    pa, lda = _mat_arg(A, "A")
+    pc, ldc = _mat_arg(C, "C")
+    st = ooc_stats()
+    s = _lib.ooc_syrk(N, K, alpha, pa, lda, beta, pc, ldc, budget_bytes,
+                      ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
+
+
+def ooc_potrf(A, budget_bytes, opts=None, raise_on_error=True):
+    """Cholesky factor of A (N x N, page-locked) in place on its lower triangle.  Returns (status, info, ooc_stats)."""
+    N = A.shape[0]
+    pa, lda = _mat_arg(A, "A")
+    st = ooc_stats()
+    info = i64()
+    s = _lib.ooc_potrf(N, pa, lda, budget_bytes, ctypes.byref(opts) if opts is not None else None,
+                       ctypes.byref(info), ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, info.value, st
+
+
+def make_op(kind, stream=0, waits=(), **fields):
+    """An ooc_op: kind by name ('h2d', 'd2h', 'gemm', 'split_gemm', 'potrf', 'trsm'), other fields by name."""
+    o = ooc_op()
+    o.kind = OP_KINDS[kind]
+    o.stream = stream
+    waits = list(waits)
+    if len(waits) > MAX_WAITS:
+        raise ValueError("too many waits")
+    o.nwait = len(waits)
+    for x, w in enumerate(waits):
+        o.wait[x] = w
+    for k, v in fields.items():
+        setattr(o, k, v)
+    return o
+
+
+def _op_array(ops):
+    arr = (ooc_op * max(len(ops), 1))()
+    for x, o in enumerate(ops):
+        arr[x] = o
+    return arr
+
+
+def ooc_run_ops(ops, mats, arena_bytes, opts=None, raise_on_error=True):
+    """Run a list of ooc_op on the device; mats: list of page-locked 2-D float64 arrays (op.mat indexes them).
+    Returns (status, ooc_stats)."""
+    hm = (ooc_host_matrix * max(len(mats), 1))()
+    for x, M in enumerate(mats):
+        p, ld = _mat_arg(M, f"mats[{x}]")
+        hm[x] = ooc_host_matrix(p, M.shape[0], M.shape[1], ld)
+    st = ooc_stats()
+    s = _lib.ooc_run_ops(_op_array(ops), len(ops), hm, len(mats), arena_bytes,
+                         ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
+
+
+def ooc_check_ops(ops):
+    """(status, x, y): OOC_OK, or OOC_ERR_ARG with the first unordered conflicting pair x > y."""
+    x, y = i64(), i64()
+    s = _lib.ooc_check_ops(_op_array(ops), len(ops), ctypes.byref(x), ctypes.byref(y))
+    return s, x.value, y.value
+
+
 def ooc_gemm_raw(M, N, K, alpha, pa, lda, pb, ldb, beta, pc, ldc, budget_bytes, opts=None):
     """The ABI call with raw pointers and sizes (for argument-check tests). Returns (status, stats)."""
     st = ooc_stats()
@@ -285,16 +387,19 @@ def ooc_plan_simulate(M, N, K, beta, plan):
     return t[: 2 * n.value].reshape(-1, 2)
 
 
-def ooc_schedule(M, N, K, alpha, beta, plan):
+def ooc_schedule(M, N, K, alpha, beta, plan, transb=False, lower=False):
     """The operation list as dicts (keys as in the CPU schedule checker) and the arena size in elements."""
     n = i64()
     ab = u64()
-    st = _lib.ooc_schedule(M, N, K, alpha, beta, ctypes.byref(plan), None, 0, ctypes.byref(n), ctypes.byref(ab))
+    tb, lo = 1 if transb else 0, 1 if lower else 0
+    st = _lib.ooc_schedule_ex(tb, lo, M, N, K, alpha, beta, ctypes.byref(plan), None, 0, ctypes.byref(n),
+                              ctypes.byref(ab))
     if st not in (OOC_OK, OOC_ERR_CAPACITY):
         _check(st)
     cap = max(n.value, 1)
     arr = (ooc_op * cap)()
-    _check(_lib.ooc_schedule(M, N, K, alpha, beta, ctypes.byref(plan), arr, cap, ctypes.byref(n), ctypes.byref(ab)))
+    _check(_lib.ooc_schedule_ex(tb, lo, M, N, K, alpha, beta, ctypes.byref(plan), arr, cap, ctypes.byref(n),
+                                ctypes.byref(ab)))
     return _ops_as_dicts(arr, n.value), ab.value // 8
 
 
@@ -308,9 +413,15 @@ def _ops_as_dicts(arr, count):
             d.update(mat="ABC"[o.mat], row0=o.row0, col0=o.col0, rows=o.rows, cols=o.cols, dev_off=o.off_c,
                      dev_ld=o.ld_c)
         else:
+            if kind in ("potrf", "trsm"):
+                d.update(m=o.rows, n=o.cols, k0=o.k0, off_a=o.off_a, lda=o.ld_a, off_c=o.off_c, ldc=o.ld_c,
+                         off_w=o.off_w)
+                ops.append(d)
+                continue
             d.update(m=o.rows, n=o.cols, k=o.k, i0=o.row0, j0=o.col0, k0=o.k0, off_a=o.off_a, lda=o.ld_a,
                      off_b=o.off_b, ldb=o.ld_b, off_c=o.off_c, ldc=o.ld_c, off_d=o.off_d, ldd=o.ld_d,
-                     off_w=o.off_w, len_w=o.len_w, alpha=o.alpha, beta=o.beta, gamma=o.gamma)
+                     off_w=o.off_w, len_w=o.len_w, alpha=o.alpha, beta=o.beta, gamma=o.gamma,
+                     transb=bool(o.flags & OPF_TRANSB), lower=bool(o.flags & OPF_LOWER))
         ops.append(d)
     return ops
 

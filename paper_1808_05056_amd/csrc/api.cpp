@@ -126,10 +126,19 @@ int env_int(const char* name, int dflt) {
   return v ? std::atoi(v) : dflt;
 }
 
-struct HostMats {
-  const double* A; int64_t lda;
-  const double* B; int64_t ldb;
-  double* C; int64_t ldc;
+// A host matrix an operation list copies from or to (op.mat indexes them).
+struct HostMat {
+  double* p;
+  int64_t ld;
+};
+typedef std::vector<HostMat> HostMats;
+
+// What an operation list needs from its plan: stream count and the split
+// precision of its SPLIT_GEMM ops.
+struct RunCfg {
+  int nstreams;
+  int precision;
+  int slices;
 };
 
 // Length of the union of intervals [a, b).
@@ -161,7 +170,7 @@ double overlap_fraction(const std::vector<std::pair<double, double>>& copies,
   return std::max(0.0, std::min(1.0, both / uc));
 }
 
-ooc_status run_ops(DevCtx& c, hipStream_t* streams, const ooc_plan_t& plan, const std::vector<ooc_op>& ops,
+ooc_status run_ops(DevCtx& c, hipStream_t* streams, const RunCfg& plan, const std::vector<ooc_op>& ops,
                    double* arena, int64_t arena_elems, const HostMats& hm, bool profile, double* timeline,
                    int64_t timeline_cap, ooc_stats* st) {
   const size_t n = ops.size();
@@ -222,9 +231,8 @@ ooc_status run_ops(DevCtx& c, hipStream_t* streams, const ooc_plan_t& plan, cons
       switch (o.kind) {
         case OOC_OP_H2D:
         case OOC_OP_D2H: {
-          const double* hbase = o.mat == 0 ? hm.A : (o.mat == 1 ? hm.B : hm.C);
-          const int64_t hld = o.mat == 0 ? hm.lda : (o.mat == 1 ? hm.ldb : hm.ldc);
-          double* host = const_cast<double*>(hbase) + o.row0 * hld + o.col0;
+          const int64_t hld = hm[o.mat].ld;
+          double* host = hm[o.mat].p + o.row0 * hld + o.col0;
           double* dev = arena + o.off_c;
           // Always a 2-D (row-pitched) copy, also for contiguous blocks: on
           // MI355X a plain 1-D host-to-device copy running beside a 1-D
@@ -243,7 +251,9 @@ ooc_status run_ops(DevCtx& c, hipStream_t* streams, const ooc_plan_t& plan, cons
         }
         case OOC_OP_GEMM:
           e = launch_dgemm_f64(o.rows, o.cols, o.k, o.alpha, arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b,
-                               o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d, s);
+                               o.beta, arena + o.off_c, o.ld_c, o.gamma, arena + o.off_d, o.ld_d, s,
+                               (o.flags & OOC_OPF_TRANSB) != 0,
+                               (o.flags & OOC_OPF_LOWER) ? o.col0 - o.row0 : kNoTri);
           break;
         case OOC_OP_SPLIT_GEMM: {
           KernelTimer kt;
@@ -254,9 +264,15 @@ ooc_status run_ops(DevCtx& c, hipStream_t* streams, const ooc_plan_t& plan, cons
           e = launch_split_gemm(slice_format(plan.precision), o.rows, o.cols, o.k, plan.slices, o.alpha,
                                 arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b, o.beta, arena + o.off_c, o.ld_c,
                                 o.gamma, arena + o.off_d, o.ld_d, arena + o.off_w, (size_t)o.len_w * 8, s,
-                                profile ? &kt : nullptr);
+                                profile ? &kt : nullptr, (o.flags & OOC_OPF_TRANSB) != 0);
           break;
         }
+        case OOC_OP_POTRF:
+          e = launch_potrf_lower(o.rows, arena + o.off_c, o.ld_c, arena + o.off_w, o.k0, s);
+          break;
+        case OOC_OP_TRSM:
+          e = launch_trsm_rlt(o.rows, o.cols, arena + o.off_c, o.ld_c, arena + o.off_a, o.ld_a, s);
+          break;
         default:
           status = OOC_ERR_ARG;
           msg = "unknown operation kind";
@@ -341,8 +357,61 @@ ooc_status run_ops(DevCtx& c, hipStream_t* streams, const ooc_plan_t& plan, cons
   return OOC_OK;
 }
 
+// Run an operation list on device `dev` (selected, page-lock checks done by
+// the caller): the device arena of arena_bytes is opts->arena when given,
+// else the device's cached arena (reallocated when too small or larger than
+// budget_bytes, freed afterwards with opts->release_arena); pipeline stream x
+// is opts->streams[x] when given, else the device's own.
+ooc_status exec_list(int dev, const std::vector<ooc_op>& ops, const HostMats& hm, uint64_t arena_bytes,
+                     uint64_t budget_bytes, const RunCfg& cfg, const ooc_opts* opts, ooc_stats* stats) {
+  DevCtx& c = g_dev[dev];
+  std::lock_guard<std::mutex> lock(c.mu);
+  ooc_status st = ensure_streams(c);
+  if (st != OOC_OK) return st;
+  double* arena = nullptr;
+  if (opts && opts->arena) {
+    if (opts->arena_bytes < arena_bytes) return fail(OOC_ERR_ARG, "opts->arena is smaller than the plan's footprint");
+    arena = static_cast<double*>(opts->arena);
+  } else {
+    if (c.arena && (c.arena_bytes < arena_bytes || c.arena_bytes > budget_bytes)) {
+      HIPCHK(hipFree(c.arena), "hipFree");
+      c.arena = nullptr;
+      c.arena_bytes = 0;
+    }
+    if (!c.arena && arena_bytes > 0) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
+      if (arena_bytes > fr)
+        return fail(OOC_ERR_DEVICE_MEM, "plan needs " + std::to_string(arena_bytes) + " bytes, device has " +
+                                            std::to_string(fr) + " free");
+      hipError_t e = hipMalloc(&c.arena, arena_bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        c.arena = nullptr;
+        return fail(OOC_ERR_DEVICE_MEM, std::string("hipMalloc of the arena failed: ") + hipGetErrorString(e));
+      }
+      c.arena_bytes = arena_bytes;
+    }
+    arena = static_cast<double*>(c.arena);
+  }
+  // pipeline streams: the caller's where given (borrowed), else the device's own
+  hipStream_t streams[3];
+  for (int x = 0; x < 3; ++x)
+    streams[x] = (opts && opts->streams[x]) ? static_cast<hipStream_t>(opts->streams[x]) : c.st[x];
+  st = run_ops(c, streams, cfg, ops, arena, (int64_t)(arena_bytes / 8), hm, opts && opts->profile,
+               opts ? opts->timeline : nullptr, opts ? opts->timeline_cap : 0, stats);
+  if (opts && opts->release_arena && !opts->arena && c.arena) {
+    // run_ops drained every stream it used, so nothing reads the arena any more
+    const hipError_t e = hipFree(c.arena);
+    c.arena = nullptr;
+    c.arena_bytes = 0;
+    if (e != hipSuccess && st == OOC_OK) st = hip_fail(e, "hipFree of the arena");
+  }
+  return st;
+}
+
 ooc_status check_args(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
-                      int64_t ldb, double beta, double* C, int64_t ldc) {
+                      int64_t ldb, double beta, double* C, int64_t ldc, bool transb = false) {
   (void)beta;
   if (M < 0 || N < 0 || K < 0) return fail(OOC_ERR_ARG, "negative matrix size");
   const bool need_ab = M > 0 && N > 0 && K > 0 && alpha != 0.0;
@@ -353,21 +422,25 @@ ooc_status check_args(int64_t M, int64_t N, int64_t K, double alpha, const doubl
   if (need_ab) {
     if (!A || !B) return fail(OOC_ERR_ARG, "A or B is NULL");
     if (lda < K) return fail(OOC_ERR_ARG, "lda < K");
-    if (ldb < N) return fail(OOC_ERR_ARG, "ldb < N");
+    if (transb ? ldb < K : ldb < N) return fail(OOC_ERR_ARG, transb ? "ldb < K (B transposed)" : "ldb < N");
   }
   return OOC_OK;
 }
 
 ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
                      int64_t ldb, double beta, double* C, int64_t ldc, size_t budget_bytes, const ooc_plan_t* given,
-                     const ooc_opts* opts, ooc_stats* stats) {
+                     const ooc_opts* opts, ooc_stats* stats, bool transb = false, bool lower = false) {
   const double t_enter = now_s();
   if (stats) std::memset(stats, 0, sizeof(*stats));
-  ooc_status st = check_args(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  ooc_status st = check_args(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, transb);
   if (st != OOC_OK) return st;
   if (M == 0 || N == 0) return OOC_OK;
+  if (lower && opts && opts->precision != OOC_FP64)
+    return fail(OOC_ERR_ARG, "lower-triangle products run in FP64 precision only");
   Problem pb;
   pb.M = M; pb.N = N; pb.K = K; pb.alpha = alpha; pb.beta = beta;
+  pb.transb = transb;
+  pb.lower = lower;
   ooc_plan_t plan;
   double predicted = 0.0;
   if (given) {
@@ -392,60 +465,22 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
   st = ensure_device(dev);
   if (st != OOC_OK) return st;
   const int64_t keff = pb.keff();
-  if (keff > 0 && (!range_pinned(A, M, K, lda) || !range_pinned(B, K, N, ldb)))
+  if (keff > 0 && (!range_pinned(A, M, K, lda) || !(transb ? range_pinned(B, N, K, ldb) : range_pinned(B, K, N, ldb))))
     return fail(OOC_ERR_NOT_PINNED, "A or B is not page-locked host memory (use ooc_host_alloc)");
   if (!range_pinned(C, M, N, ldc)) return fail(OOC_ERR_NOT_PINNED, "C is not page-locked host memory (use ooc_host_alloc)");
 
-  DevCtx& c = g_dev[dev];
-  std::lock_guard<std::mutex> lock(c.mu);
-  st = ensure_streams(c);
-  if (st != OOC_OK) return st;
-  double* arena = nullptr;
-  if (opts && opts->arena) {
-    if (opts->arena_bytes < lay.bytes) return fail(OOC_ERR_ARG, "opts->arena is smaller than the plan's footprint");
-    arena = static_cast<double*>(opts->arena);
-  } else {
-    if (c.arena && (c.arena_bytes < lay.bytes || c.arena_bytes > budget_bytes)) {
-      HIPCHK(hipFree(c.arena), "hipFree");
-      c.arena = nullptr;
-      c.arena_bytes = 0;
-    }
-    if (!c.arena && lay.bytes > 0) {
-      size_t fr = 0, tot = 0;
-      HIPCHK(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
-      if (lay.bytes > fr)
-        return fail(OOC_ERR_DEVICE_MEM, "plan needs " + std::to_string(lay.bytes) + " bytes, device has " +
-                                            std::to_string(fr) + " free");
-      hipError_t e = hipMalloc(&c.arena, lay.bytes);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        c.arena = nullptr;
-        return fail(OOC_ERR_DEVICE_MEM, std::string("hipMalloc of the arena failed: ") + hipGetErrorString(e));
-      }
-      c.arena_bytes = lay.bytes;
-    }
-    arena = static_cast<double*>(c.arena);
-  }
-  // pipeline streams: the caller's where given (borrowed), else the device's own
-  hipStream_t streams[3];
-  for (int x = 0; x < 3; ++x)
-    streams[x] = (opts && opts->streams[x]) ? static_cast<hipStream_t>(opts->streams[x]) : c.st[x];
-  HostMats hm{A, lda, B, ldb, C, ldc};
-  st = run_ops(c, streams, plan, ops, arena, (int64_t)(lay.bytes / 8), hm, opts && opts->profile,
-               opts ? opts->timeline : nullptr, opts ? opts->timeline_cap : 0, stats);
-  if (opts && opts->release_arena && !opts->arena && c.arena) {
-    // run_ops drained every stream it used, so nothing reads the arena any more
-    const hipError_t e = hipFree(c.arena);
-    c.arena = nullptr;
-    c.arena_bytes = 0;
-    if (e != hipSuccess && st == OOC_OK) st = hip_fail(e, "hipFree of the arena");
-  }
+  HostMats hm{{const_cast<double*>(A), lda}, {const_cast<double*>(B), ldb}, {C, ldc}};
+  st = exec_list(dev, ops, hm, lay.bytes, budget_bytes, RunCfg{plan.nstreams, plan.precision, plan.slices}, opts,
+                 stats);
   if (stats) {
     stats->t_plan_s = t_plan;
     stats->plan = plan;
     stats->t_total_s = now_s() - t_enter;
     stats->t_predicted_s = predicted;
-    stats->flops = 2.0 * (double)M * (double)N * (double)K;
+    // useful flops: every element of C, or with lower those with i >= j
+    const double elems = !lower ? (double)M * (double)N
+                                : (M >= N ? (double)N * (N + 1) / 2.0 + (double)(M - N) * N : (double)M * (M + 1) / 2.0);
+    stats->flops = 2.0 * elems * (double)K;
     stats->arena_bytes = lay.bytes;
     stats->ops = (int64_t)ops.size();
     int64_t tasks = 0, kern = 0;
@@ -473,6 +508,148 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
                  plan.precision != OOC_FP64 ? std::to_string(plan.slices).c_str() : "", ops.size(),
                  (unsigned long long)lay.bytes, now_s() - t_enter, predicted, (int)st);
   }
+  return st;
+}
+
+// Totals of one more call's stats into `t` (ooc_potrf adds its products and panels).
+void add_stats(ooc_stats* t, const ooc_stats& s) {
+  t->t_pipeline_s += s.t_pipeline_s;
+  t->t_h2d_busy_s += s.t_h2d_busy_s;
+  t->t_d2h_busy_s += s.t_d2h_busy_s;
+  t->t_kernel_busy_s += s.t_kernel_busy_s;
+  t->t_plan_s += s.t_plan_s;
+  t->t_mma_busy_s += s.t_mma_busy_s;
+  t->mma_launches += s.mma_launches;
+  t->bytes_h2d += s.bytes_h2d;
+  t->bytes_d2h += s.bytes_d2h;
+  t->arena_bytes = std::max(t->arena_bytes, s.arena_bytes);
+  t->ops += s.ops;
+  t->tasks += s.tasks;
+  t->kernels += s.kernels;
+}
+
+// Copy and kernel counts and bytes of an operation list (stats of ooc_run_ops and the panels of ooc_potrf).
+void list_stats(const std::vector<ooc_op>& ops, ooc_stats* st) {
+  for (const ooc_op& o : ops) {
+    if (o.kind == OOC_OP_H2D) st->bytes_h2d += (uint64_t)(o.rows * o.cols) * 8;
+    else if (o.kind == OOC_OP_D2H) st->bytes_d2h += (uint64_t)(o.rows * o.cols) * 8;
+    else ++st->kernels;
+  }
+  st->ops = (int64_t)ops.size();
+}
+
+// Panel width of the out-of-core Cholesky factorisation: the largest multiple
+// of 64 up to 8192 (and N rounded up to 64) whose b x b diagonal block, two
+// chunk buffers of 256 rows and the status word fit the budget.
+int64_t potrf_panel(int64_t N, uint64_t budget_elems) {
+  int64_t b = std::min<int64_t>(8192, (N + 63) / 64 * 64);
+  while (b > 64 && (uint64_t)(b * b + 2 * 256 * b + 8) > budget_elems) b -= 64;
+  return (uint64_t)(b * b + 2 * 256 * b + 8) <= budget_elems ? b : 0;
+}
+
+ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, const ooc_opts* opts, int64_t* info,
+                      ooc_stats* stats) {
+  const double t_enter = now_s();
+  ooc_stats total{};
+  if (info) *info = 0;
+  if (N < 0) return fail(OOC_ERR_ARG, "negative matrix size");
+  if (N == 0) {
+    if (stats) *stats = total;
+    return OOC_OK;
+  }
+  if (!A || lda < N) return fail(OOC_ERR_ARG, "bad A or lda");
+  const int64_t b = potrf_panel(N, budget_bytes / 8);
+  if (b == 0) return fail(OOC_ERR_BUDGET, "the budget holds no 64-column panel of the factorisation");
+  const int dev = opts ? opts->device : 0;
+  ooc_status st = ensure_device(dev);
+  if (st != OOC_OK) return st;
+  if (!range_pinned(A, N, N, lda)) return fail(OOC_ERR_NOT_PINNED, "A is not page-locked host memory");
+  ooc_opts gopts{};
+  if (opts) gopts = *opts;
+  gopts.precision = OOC_FP64;
+  gopts.timeline = nullptr;
+  gopts.timeline_cap = 0;
+  double* hstat = nullptr;  // the panel's status word comes home here
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hstat), 8), "hipHostMalloc");
+  for (int64_t j0 = 0; j0 < N && st == OOC_OK; j0 += b) {
+    const int64_t jb = std::min(b, N - j0);
+    double* panel = A + j0 * lda + j0;
+    // the block column's update by the columns to its left: C = C - L_left L_top^T (lower triangle)
+    if (j0 > 0) {
+      ooc_stats gs{};
+      st = gemm_impl(N - j0, jb, j0, -1.0, A + j0 * lda, lda, A + j0 * lda, lda, 1.0, panel, lda, budget_bytes,
+                     nullptr, &gopts, &gs, true, true);
+      add_stats(&total, gs);
+      if (st != OOC_OK) break;
+    }
+    // the panel: factor the diagonal block, then solve the rows below against it in chunks
+    const int64_t below = N - j0 - jb;
+    const int64_t base = jb * jb + 8;  // chunk buffers after the block and the status word
+    const int64_t r = below > 0 ? std::max<int64_t>(1, std::min<int64_t>(below, ((int64_t)(budget_bytes / 8) - base) / (2 * jb))) : 0;
+    std::vector<ooc_op> ops;
+    auto push = [&](ooc_op o, std::initializer_list<int> waits) {
+      o.nwait = 0;
+      for (int w : waits)
+        if (w >= 0) o.wait[o.nwait++] = w;
+      ops.push_back(o);
+      return (int)ops.size() - 1;
+    };
+    ooc_op o{};
+    o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 0;
+    o.row0 = j0; o.col0 = j0; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
+    const int h_diag = push(o, {});
+    o = ooc_op{};
+    o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 1; o.rows = 1; o.cols = 1; o.off_c = jb * jb; o.ld_c = 1;
+    const int h_stat = push(o, {});
+    o = ooc_op{};
+    o.kind = OOC_OP_POTRF; o.stream = 1; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
+    o.off_w = jb * jb; o.len_w = 1; o.k0 = j0;
+    const int k_potrf = push(o, {h_diag, h_stat});
+    o = ooc_op{};
+    o.kind = OOC_OP_D2H; o.stream = 2; o.mat = 0;
+    o.row0 = j0; o.col0 = j0; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
+    push(o, {k_potrf});
+    o = ooc_op{};
+    o.kind = OOC_OP_D2H; o.stream = 2; o.mat = 1; o.rows = 1; o.cols = 1; o.off_c = jb * jb; o.ld_c = 1;
+    push(o, {k_potrf});
+    std::vector<int> home(2, -1);  // last copy home out of each chunk buffer
+    for (int64_t q = 0; q * r < below; ++q) {
+      const int64_t i0 = j0 + jb + q * r, rr = std::min(r, N - i0);
+      const int buf = (int)(q & 1);
+      o = ooc_op{};
+      o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 0;
+      o.row0 = i0; o.col0 = j0; o.rows = rr; o.cols = jb; o.off_c = base + buf * r * jb; o.ld_c = jb;
+      const int h = push(o, {home[buf]});
+      o = ooc_op{};
+      o.kind = OOC_OP_TRSM; o.stream = 1; o.rows = rr; o.cols = jb;
+      o.off_c = base + buf * r * jb; o.ld_c = jb; o.off_a = 0; o.ld_a = jb;
+      const int k = push(o, {h});
+      o = ooc_op{};
+      o.kind = OOC_OP_D2H; o.stream = 2; o.mat = 0;
+      o.row0 = i0; o.col0 = j0; o.rows = rr; o.cols = jb; o.off_c = base + buf * r * jb; o.ld_c = jb;
+      home[buf] = push(o, {k});
+    }
+    *hstat = 0.0;
+    ooc_stats ps{};
+    HostMats hm{{A, lda}, {hstat, 1}};
+    const uint64_t arena_bytes = (uint64_t)(base + 2 * r * jb) * 8;
+    st = exec_list(dev, ops, hm, arena_bytes, budget_bytes, RunCfg{3, OOC_FP64, 0}, &gopts, &ps);
+    list_stats(ops, &ps);
+    ps.arena_bytes = arena_bytes;
+    add_stats(&total, ps);
+    if (st == OOC_OK && *hstat != 0.0) {
+      if (info) *info = (int64_t)*hstat;
+      st = fail(OOC_ERR_NOT_SPD, "the matrix is not positive definite: pivot " + std::to_string((int64_t)*hstat - 1) +
+                                     " is not positive");
+      break;
+    }
+    if (st == OOC_OK) ++total.blocks_done;
+  }
+  (void)hipHostFree(hstat);
+  const double n = (double)N;
+  total.flops = n * n * n / 3.0 + n * n / 2.0 + n / 6.0;
+  total.t_total_s = now_s() - t_enter;
+  if (stats) *stats = total;
   return st;
 }
 
@@ -568,10 +745,12 @@ ooc_status accum_step_locked(DevCtx& c, ooc_accum_s* a, int64_t K, double alpha,
     if (st != OOC_OK) return st;
     if (ops.empty()) continue;
     const int64_t r0 = part == 0 ? 0 : a->R;
-    HostMats hm{A ? A + r0 * lda : nullptr, lda, B, ldb, a->C + r0 * a->ldc, a->ldc};
+    HostMats hm{{const_cast<double*>(A ? A + r0 * lda : nullptr), lda}, {const_cast<double*>(B), ldb},
+                {a->C + r0 * a->ldc, a->ldc}};
     ooc_stats ps{};
     const double t_plan = now_s() - t_enter;
-    st = run_ops(c, streams, plan, ops, static_cast<double*>(a->mem), (int64_t)(lay.bytes / 8), hm,
+    st = run_ops(c, streams, RunCfg{plan.nstreams, plan.precision, plan.slices}, ops, static_cast<double*>(a->mem),
+                 (int64_t)(lay.bytes / 8), hm,
                  a->opts.profile != 0, nullptr, 0, &ps);
     total.plan = plan;
     total.t_plan_s = t_plan;
@@ -614,6 +793,72 @@ ooc_status ooc_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double*
                     int64_t ldb, double beta, double* C, int64_t ldc, size_t budget_bytes, const ooc_opts* opts,
                     ooc_stats* stats) {
   return gemm_impl(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, budget_bytes, nullptr, opts, stats);
+}
+
+ooc_status ooc_gemm_ex(int32_t transb, int32_t lower, int64_t M, int64_t N, int64_t K, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                       int64_t ldc, size_t budget_bytes, const ooc_opts* opts, ooc_stats* stats) {
+  if ((transb != 0 && transb != 1) || (lower != 0 && lower != 1))
+    return fail(OOC_ERR_ARG, "transb and lower must be 0 or 1");
+  return gemm_impl(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, budget_bytes, nullptr, opts, stats, transb != 0,
+                   lower != 0);
+}
+
+ooc_status ooc_syrk(int64_t N, int64_t K, double alpha, const double* A, int64_t lda, double beta, double* C,
+                    int64_t ldc, size_t budget_bytes, const ooc_opts* opts, ooc_stats* stats) {
+  return ooc_gemm_ex(1, 1, N, N, K, alpha, A, lda, A, lda, beta, C, ldc, budget_bytes, opts, stats);
+}
+
+ooc_status ooc_potrf(int64_t N, double* A, int64_t lda, size_t budget_bytes, const ooc_opts* opts, int64_t* info,
+                     ooc_stats* stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  return potrf_impl(N, A, lda, budget_bytes, opts, info, stats);
+}
+
+ooc_status ooc_run_ops(const ooc_op* ops, int64_t nops, const ooc_host_matrix* mats, int32_t nmats,
+                       uint64_t arena_bytes, const ooc_opts* opts, ooc_stats* stats) {
+  const double t_enter = now_s();
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const int prec = opts ? opts->precision : OOC_FP64;
+  const int slices = (opts && opts->slices > 0) ? opts->slices : 6;
+  int ns = 1;
+  ooc_status st = validate_ops(ops, nops, mats, nmats, (int64_t)(arena_bytes / 8), prec, slices, &ns);
+  if (st != OOC_OK) return st;
+  if (nops == 0) return OOC_OK;
+  const int dev = opts ? opts->device : 0;
+  st = ensure_device(dev);
+  if (st != OOC_OK) return st;
+  std::vector<char> used(nmats, 0);
+  for (int64_t x = 0; x < nops; ++x)
+    if (ops[x].kind == OOC_OP_H2D || ops[x].kind == OOC_OP_D2H) used[ops[x].mat] = 1;
+  HostMats hm;
+  for (int m = 0; m < nmats; ++m) {
+    if (used[m] && !range_pinned(mats[m].ptr, mats[m].rows, mats[m].cols, mats[m].ld))
+      return fail(OOC_ERR_NOT_PINNED, "host matrix " + std::to_string(m) + " is not page-locked");
+    hm.push_back({mats[m].ptr, mats[m].ld});
+  }
+  std::vector<ooc_op> v(ops, ops + nops);
+  st = exec_list(dev, v, hm, arena_bytes, arena_bytes, RunCfg{ns, prec, slices}, opts, stats);
+  if (stats) {
+    list_stats(v, stats);
+    stats->arena_bytes = arena_bytes;
+    stats->t_total_s = now_s() - t_enter;
+  }
+  return st;
+}
+
+ooc_status ooc_check_ops(const ooc_op* ops, int64_t nops, int64_t* x, int64_t* y) {
+  if (nops < 0 || (nops > 0 && !ops) || !x || !y) return fail(OOC_ERR_ARG, "NULL argument");
+  if (nops > 32768) return fail(OOC_ERR_CAPACITY, "ooc_check_ops handles at most 32768 ops");
+  for (int64_t k = 0; k < nops; ++k)
+    for (int w = 0; w < ops[k].nwait; ++w)
+      if (ops[k].nwait > OOC_MAX_WAITS || ops[k].wait[w] < 0 || ops[k].wait[w] >= k)
+        return fail(OOC_ERR_ARG, "op " + std::to_string(k) + " waits on an op that is not earlier in the list");
+  *x = *y = -1;
+  if (find_hazard(ops, nops, x, y))
+    return fail(OOC_ERR_ARG, "ops " + std::to_string(*y) + " and " + std::to_string(*x) +
+                                 " touch a common arena element, one writing it, and are not ordered");
+  return OOC_OK;
 }
 
 ooc_status ooc_gemm_planned(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
@@ -708,10 +953,18 @@ ooc_status ooc_plan_simulate(int64_t M, int64_t N, int64_t K, double beta, const
 
 ooc_status ooc_schedule(int64_t M, int64_t N, int64_t K, double alpha, double beta, const ooc_plan_t* plan,
                         ooc_op* ops, int64_t cap, int64_t* nops, uint64_t* arena_bytes) {
+  return ooc_schedule_ex(0, 0, M, N, K, alpha, beta, plan, ops, cap, nops, arena_bytes);
+}
+
+ooc_status ooc_schedule_ex(int32_t transb, int32_t lower, int64_t M, int64_t N, int64_t K, double alpha,
+                           double beta, const ooc_plan_t* plan, ooc_op* ops, int64_t cap, int64_t* nops,
+                           uint64_t* arena_bytes) {
   if (!plan || !nops) return fail(OOC_ERR_ARG, "NULL argument");
   if (M < 0 || N < 0 || K < 0) return fail(OOC_ERR_ARG, "negative size");
   Problem pb;
   pb.M = M; pb.N = N; pb.K = K; pb.alpha = alpha; pb.beta = beta;
+  pb.transb = transb != 0;
+  pb.lower = lower != 0;
   Layout lay;
   ooc_status st = OOC_OK;
   if (M > 0 && N > 0) {

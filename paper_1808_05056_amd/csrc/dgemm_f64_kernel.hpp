@@ -57,11 +57,11 @@ struct Cfg {
 // while it issues its MFMA block, PIPE = load the next k sub-step's operands
 // from LDS before issuing the current sub-step's MFMAs.
 template <int BM, int BN, int BK, int WM, int WN, bool VEC, int MINBLOCKS, int GM = GROUP_M, bool PRIO = false,
-          bool PIPE = false>
+          bool PIPE = false, bool TB = false>
 __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
     int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda,
     const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
-    double gamma, const double* __restrict__ D, int64_t ldd, int tiles_m, int tiles_n) {
+    double gamma, const double* __restrict__ D, int64_t ldd, int tiles_m, int tiles_n, int64_t tri) {
   using CF = Cfg<BM, BN, BK, WM, WN>;
   constexpr int FM = CF::FM, FN = CF::FN, VA = CF::VA, VB = CF::VB;
   __shared__ __attribute__((aligned(16))) double As[2][BK][BM + PAD];
@@ -85,9 +85,11 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
   const int lane = tid & 63, wid = tid >> 6;
   const int wm = wid / WN, wn = wid % WN;
 
-  // global-load assignment: A row ar, k offset ak (VA doubles); B k-row bk, column offset bn (VB doubles)
+  // global-load assignment: A row ar, k offset ak (VA doubles); B k-row bk, column offset bn (VB doubles),
+  // or with TB B column (row of the transposed B) btn, k offset btk (VB doubles)
   const int ar = tid / CF::A_TPR, ak = (tid % CF::A_TPR) * VA;
   const int bk = tid / CF::B_TPR, bn = (tid % CF::B_TPR) * VB;
+  const int btn = tid / (BK / VB), btk = (tid % (BK / VB)) * VB;
 
   const bool full_mn = (m0 + BM <= M) && (n0 + BN <= N);
   double ra[VA], rb[VB];
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
     const int64_t brow = k0 + bk;
     if (fast) {
       const double* pa = A + arow * lda + k0 + ak;
-      const double* pb = B + brow * ldb + n0 + bn;
+      const double* pb = TB ? B + (n0 + btn) * ldb + k0 + btk : B + brow * ldb + n0 + bn;
       if (VEC) {
 #pragma unroll
         for (int e = 0; e < VA; e += 2) {
@@ -122,18 +124,32 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
         const int64_t kk = k0 + ak + e;
         ra[e] = (arow < M && kk < K) ? A[arow * lda + kk] : 0.0;
       }
+      if (TB) {
+        const int64_t nn = n0 + btn;
 #pragma unroll
-      for (int e = 0; e < VB; ++e) {
-        const int64_t nn = n0 + bn + e;
-        rb[e] = (brow < K && nn < N) ? B[brow * ldb + nn] : 0.0;
+        for (int e = 0; e < VB; ++e) {
+          const int64_t kk = k0 + btk + e;
+          rb[e] = (nn < N && kk < K) ? B[nn * ldb + kk] : 0.0;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < VB; ++e) {
+          const int64_t nn = n0 + bn + e;
+          rb[e] = (brow < K && nn < N) ? B[brow * ldb + nn] : 0.0;
+        }
       }
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < VA; ++e) As[buf][ak + e][ar] = ra[e];
+    if (TB) {
 #pragma unroll
-    for (int e = 0; e < VB; e += 2) *reinterpret_cast<double2*>(&Bs[buf][bk][bn + e]) = make_double2(rb[e], rb[e + 1]);
+      for (int e = 0; e < VB; ++e) Bs[buf][btk + e][btn] = rb[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VB; e += 2) *reinterpret_cast<double2*>(&Bs[buf][bk][bn + e]) = make_double2(rb[e], rb[e + 1]);
+    }
   };
 
   dbl4 acc[FM][FN];
@@ -205,7 +221,7 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + am0 + i * 16 + lk + 4 * v;
-        if (row < M && col < N) {
+        if (row < M && col < N && row - col >= tri) {
           double* pc = C + row * ldc + col;
           double val = alpha * acc[i][j][v];
           if (beta != 0.0) val += beta * *pc;
@@ -220,10 +236,11 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
 // Launch one configuration; checks the grid size and picks 16-byte loads when
 // the operands allow them.
 template <int BM, int BN, int BK, int WM, int WN, int MINBLOCKS, int GM = GROUP_M, bool PRIO = false,
-          bool PIPE = false>
+          bool PIPE = false, bool TB = false>
 hipError_t launch(int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda, const double* B,
                   int64_t ldb, double beta, double* C, int64_t ldc, double gamma, const double* D, int64_t ldd,
-                  hipStream_t stream) {
+                  int64_t tri, hipStream_t stream) {
+  static_assert(!TB || ((BK / (BN * BK / (64 * WM * WN))) * BN == 64 * WM * WN), "TB load split");
   using CF = Cfg<BM, BN, BK, WM, WN>;
   if (m <= 0 || n <= 0) return hipSuccess;
   const int64_t tm = (m + BM - 1) / BM, tn = (n + BN - 1) / BN;
@@ -234,11 +251,11 @@ hipError_t launch(int64_t m, int64_t n, int64_t k, double alpha, const double* A
   if (gamma == 0.0) D = nullptr;
   dim3 grid((unsigned)(tm * tn)), block(CF::NT);
   if (vec)
-    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, true, MINBLOCKS, GM, PRIO, PIPE>), grid, block, 0, stream, m, n, k,
-                       alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn);
+    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, true, MINBLOCKS, GM, PRIO, PIPE, TB>), grid, block, 0, stream, m, n,
+                       k, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn, tri);
   else
-    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, false, MINBLOCKS, GM, PRIO, PIPE>), grid, block, 0, stream, m, n,
-                       k, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn);
+    hipLaunchKernelGGL((kernel<BM, BN, BK, WM, WN, false, MINBLOCKS, GM, PRIO, PIPE, TB>), grid, block, 0, stream, m,
+                       n, k, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, (int)tm, (int)tn, tri);
   return hipGetLastError();
 }
 

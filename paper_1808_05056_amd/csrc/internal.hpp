@@ -28,6 +28,9 @@ struct Problem {
   bool c_resident = false;
   int64_t c_ld = 0;
   int64_t base = 0;
+  // op(B) = B^T (B stored N x K); only the lower triangle of C (FP64 plans)
+  bool transb = false;
+  bool lower = false;
   // K as the pipeline sees it: 0 when alpha == 0 or K == 0 (A and B are not read).
   int64_t keff() const { return (alpha == 0.0 || K == 0) ? 0 : K; }
 };
@@ -99,6 +102,14 @@ ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts*
 
 // Forget cached plan choices (after a new planner network is loaded).
 void clear_plan_cache();
+
+// Operation lists given by a caller (oplist.cpp): validation against the
+// host matrices and the arena (OOC_ERR_ARG naming the first bad op; the
+// stream count the list uses in *nstreams_out), and the first pair of
+// unordered ops (x > y) that touch a common arena element, one writing it.
+ooc_status validate_ops(const ooc_op* ops, int64_t n, const ooc_host_matrix* mats, int nmats, int64_t arena_elems,
+                        int precision, int slices, int* nstreams_out);
+bool find_hazard(const ooc_op* ops, int64_t n, int64_t* x, int64_t* y);
 
 // MLP planner hook: predicted times for candidate plans, or false if no model is loaded.
 bool mlp_predict(const Problem& pb, uint64_t budget_bytes, const std::vector<ooc_plan_t>& plans,

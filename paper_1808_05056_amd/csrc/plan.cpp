@@ -40,6 +40,8 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
     return fail(OOC_ERR_ARG, "plan: slices must be 1..8");
   if (plan.nbuf_d < 0) return fail(OOC_ERR_ARG, "plan: nbuf_d must be >= 0");
   if (plan.group < 0) return fail(OOC_ERR_ARG, "plan: group must be >= 0");
+  if (pb.lower && plan.precision != OOC_FP64)
+    return fail(OOC_ERR_ARG, "plan: lower-triangle products run in FP64 precision only");
   // clamp to the problem (a block larger than the matrix is the matrix)
   const int64_t mb = std::min(plan.mb, std::max<int64_t>(pb.M, 1));
   const int64_t nb = std::min(plan.nb, std::max<int64_t>(pb.N, 1));
@@ -69,8 +71,10 @@ ooc_status plan_layout(const Problem& pb, const ooc_plan_t& plan, Layout* lay) {
     L.offB = L.offA + (K > 0 ? plan.nbuf_a * L.slotA : 0);
     L.offC = L.offB + (K > 0 ? plan.nbuf_b * L.slotB : 0);
     L.offD = L.offC + plan.nbuf_c * L.slotC;
-    // staging buffers for the initial C (only when C is read at all)
-    if (plan.nbuf_d > 0 && pb.beta != 0.0 && !pb.c_resident) {
+    // staging buffers for the initial C (only when C is read at all; not for
+    // lower-triangle products, whose straddling blocks carry their upper part
+    // through their own buffer)
+    if (plan.nbuf_d > 0 && pb.beta != 0.0 && !pb.c_resident && !pb.lower) {
       L.nbufD = plan.nbuf_d;
       L.slotD = mb * nb;
     }
@@ -435,7 +439,7 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
           // C-stationary blocks with K panels streamed
           const int64_t P = ceil_div(K, kb);
           for (int nd : {0, 1}) {
-            if (nd && pb.beta == 0.0) continue;
+            if (nd && (pb.beta == 0.0 || pb.lower)) continue;
             p.nbuf_d = nd;
             p.nbuf_a = 2; p.nbuf_b = 2; p.nbuf_c = 2;
             p.order = OOC_ORDER_COLS; consider(p);
@@ -564,10 +568,12 @@ struct PlanKey {
   int planner, precision, slices, nstreams;
   bool c_resident;
   int64_t c_ld, base;
+  bool transb, lower;
   bool operator<(const PlanKey& o) const {
-    return std::tie(M, N, K, beta_nonzero, budget, planner, precision, slices, nstreams, c_resident, c_ld, base) <
+    return std::tie(M, N, K, beta_nonzero, budget, planner, precision, slices, nstreams, c_resident, c_ld, base,
+                    transb, lower) <
            std::tie(o.M, o.N, o.K, o.beta_nonzero, o.budget, o.planner, o.precision, o.slices, o.nstreams,
-                    o.c_resident, o.c_ld, o.base);
+                    o.c_resident, o.c_ld, o.base, o.transb, o.lower);
   }
 };
 std::mutex g_plan_mu;
@@ -586,7 +592,7 @@ ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts*
                        double* predicted) {
   PlanKey key{pb.M, pb.N, pb.keff(), pb.beta != 0.0, budget_bytes,
               opts ? opts->planner : 0, opts ? opts->precision : 0, opts ? opts->slices : 0,
-              opts ? opts->nstreams : 0, pb.c_resident, pb.c_ld, pb.base};
+              opts ? opts->nstreams : 0, pb.c_resident, pb.c_ld, pb.base, pb.transb, pb.lower};
   {
     std::lock_guard<std::mutex> lock(g_plan_mu);
     auto it = g_plan_cache.find(key);

@@ -154,7 +154,15 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
   const int ns = plan.nstreams;
 
   std::vector<Task> tasks = make_tasks(plan.order, h, w, P, plan.group);
+  // lower-triangle products: blocks wholly above the diagonal have no work
+  // (the last row of block (i, j) lies above its first column)
+  auto above = [&](int64_t i, int64_t j) { return std::min(M, (i + 1) * mb) - 1 < j * nb; };
+  auto straddles = [&](int64_t i, int64_t j) { return !above(i, j) && i * mb < std::min(N, (j + 1) * nb) - 1; };
+  if (pb.lower)
+    tasks.erase(std::remove_if(tasks.begin(), tasks.end(), [&](const Task& tk) { return above(tk.i, tk.j); }),
+                tasks.end());
   const int64_t T = (int64_t)tasks.size();
+  if (T == 0) return OOC_OK;
   std::vector<int64_t> ka(T), kbk(T);
   for (int64_t t = 0; t < T; ++t) {
     ka[t] = tasks[t].i * P + tasks[t].p;
@@ -172,6 +180,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
       last[ck] = t;
     }
     for (int64_t c = 0; c < h * w; ++c) {
+      if (first[c] < 0) continue;  // skipped (above the diagonal)
       opens[first[c]] = 1;
       closes[last[c]] = 1;
     }
@@ -272,8 +281,13 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
         ooc_op op = blank(OOC_OP_H2D, t);
         op.mat = 1;
         op.slot = sb;
-        op.row0 = k0; op.col0 = j0; op.rows = k; op.cols = n;
-        op.off_c = lay.offB + sb * lay.slotB; op.ld_c = n;
+        if (pb.transb) {  // rows j0.. of the stored B^T: the panel is kept n x k
+          op.row0 = j0; op.col0 = k0; op.rows = n; op.cols = k;
+          op.off_c = lay.offB + sb * lay.slotB; op.ld_c = k;
+        } else {
+          op.row0 = k0; op.col0 = j0; op.rows = k; op.cols = n;
+          op.off_c = lay.offB + sb * lay.slotB; op.ld_c = n;
+        }
         loads.push_back({op, pbf.readers[sb], &pbf.load_op[sb]});
         pbf.readers[sb] = {-1, -1, -1};
         pbf.key[sb] = kbk[t];
@@ -301,7 +315,9 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
                                      std::to_string(plan.nbuf_c) + ")");
       c_block[sc] = ckey;
       c_dep = c_close[sc];  // previous content must be home before it is overwritten
-      if (pb.beta != 0.0 && !staged) {
+      // a lower-triangle product's block that straddles the diagonal is loaded
+      // even with beta == 0: its elements above the diagonal go home unchanged
+      if ((pb.beta != 0.0 && !staged) || (pb.lower && straddles(tk.i, tk.j))) {
         ooc_op op = blank(OOC_OP_H2D, t);
         op.mat = 2;
         op.slot = sc;
@@ -342,8 +358,9 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     g.k0 = k0; g.k = k;
     if (K > 0) {
       g.off_a = lay.offA + sa * lay.slotA; g.ld_a = k;
-      g.off_b = lay.offB + sb * lay.slotB; g.ld_b = n;
+      g.off_b = lay.offB + sb * lay.slotB; g.ld_b = pb.transb ? k : n;
     }
+    g.flags = (pb.transb ? OOC_OPF_TRANSB : 0) | (pb.lower ? OOC_OPF_LOWER : 0);
     if (resident) {
       g.slot = -1;
       g.off_c = i0 * pb.c_ld + j0;

@@ -671,23 +671,24 @@ size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat
 static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                               double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                              hipStream_t stream, KernelTimer* timer);
+                              hipStream_t stream, KernelTimer* timer, bool transb);
 
 hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                              double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                             hipStream_t stream, KernelTimer* timer) {
+                             hipStream_t stream, KernelTimer* timer, bool transb) {
   // K panels of at most kSplitMaxK: C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C
   if (m <= 0 || n <= 0) return hipSuccess;
   if (f != kSliceBF16 && f != kSliceInt8) return hipErrorInvalidValue;
   if (k <= kSplitMaxK)
     return split_panel(f, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, workspace, ws_bytes, stream,
-                       timer);
+                       timer, transb);
   for (int64_t k0 = 0; k0 < k; k0 += kSplitMaxK) {
     const int64_t kk = (k - k0) < kSplitMaxK ? (k - k0) : kSplitMaxK;
     const bool first = k0 == 0;
-    hipError_t e = split_panel(f, m, n, kk, s, alpha, A + k0, lda, B + k0 * ldb, ldb, first ? beta : 1.0, C, ldc,
-                               first ? gamma : 0.0, D, ldd, workspace, ws_bytes, stream, timer);
+    hipError_t e = split_panel(f, m, n, kk, s, alpha, A + k0, lda, transb ? B + k0 : B + k0 * ldb, ldb,
+                               first ? beta : 1.0, C, ldc, first ? gamma : 0.0, D, ldd, workspace, ws_bytes, stream,
+                               timer, transb);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -696,7 +697,7 @@ hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int
 static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                               double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                              hipStream_t stream, KernelTimer* timer) {
+                              hipStream_t stream, KernelTimer* timer, bool transb) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (s < 1 || s > 8) return hipErrorInvalidValue;
   if (k <= 0) return launch_dgemm_f64(m, n, 0, alpha, nullptr, 1, nullptr, 1, beta, C, ldc, gamma, D, ldd, stream);
@@ -718,6 +719,16 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
     else
       hipLaunchKernelGGL((split_rows<sv, 2>), rows_grid, dim3(256), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
   };
+  // with transb the stored B^T (n x k) is sliced by rows, straight into the
+  // transposed planes the slice-product kernels read
+  const dim3 brows_grid((unsigned)(np / 4));
+  auto slice_bt = [&](auto S) {
+    constexpr int sv = decltype(S)::value;
+    if (f == kSliceInt8)
+      hipLaunchKernelGGL((split_rows<sv, 1>), brows_grid, dim3(256), 0, stream, n, k, B, ldb, np, kp, Bp, fb);
+    else
+      hipLaunchKernelGGL((split_rows<sv, 2>), brows_grid, dim3(256), 0, stream, n, k, B, ldb, np, kp, Bp, fb);
+  };
   auto slice_b = [&](auto S) {
     constexpr int sv = decltype(S)::value;
     if (f == kSliceInt8)
@@ -738,12 +749,16 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
     }
   };
   with_s(slice_a);
-  hipLaunchKernelGGL(zero_u64, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream,
-                     reinterpret_cast<uint64_t*>(bmax), np);
-  hipLaunchKernelGGL(col_absmax, dim3((unsigned)((n + 255) / 256), (unsigned)((k + 255) / 256)), dim3(256), 0, stream,
-                     k, n, B, ldb, bmax);
-  hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
-  with_s(slice_b);
+  if (transb) {
+    with_s(slice_bt);
+  } else {
+    hipLaunchKernelGGL(zero_u64, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<uint64_t*>(bmax), np);
+    hipLaunchKernelGGL(col_absmax, dim3((unsigned)((n + 255) / 256), (unsigned)((k + 255) / 256)), dim3(256), 0,
+                       stream, k, n, B, ldb, bmax);
+    hipLaunchKernelGGL(col_exponents, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream, np, bmax, fb);
+    with_s(slice_b);
+  }
   // one-dimensional grids: the kernels map workgroups to tiles in XCD bands
   const dim3 grid8((unsigned)((np / SBN) * (mp / SBM))), grid16((unsigned)((np / GBN) * (mp / GBM)));
   const bool timed = timer && timer->used < timer->count;

@@ -1,0 +1,248 @@
+"""GPU parity of the out-of-core level-3 routines built on the pipeline
+(transposed-B and lower-triangle products, the rank-k update, the Cholesky
+factorisation) and of the general executor, against the oracle: bit-exact
+where every intermediate value is an integer, within the normalised gate or
+the backward-error bound otherwise.  Budgets are small so that every call
+runs several blocks, panels and chunks."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import chol_ref
+import paper_1808_05056_amd as ooc
+
+pytestmark = pytest.mark.gpu
+MiB = 1 << 20
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pinned(X):
+    P = ooc.PinnedMatrix(X.shape[0], X.shape[1])
+    P.array[...] = X
+    return P
+
+
+def _int_factor(n, seed):
+    rng = np.random.default_rng(seed)
+    L = np.tril(rng.integers(-3, 4, (n, n)).astype(np.float64), -1)
+    L[np.arange(n), np.arange(n)] = rng.integers(1, 5, n)
+    return L
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n))
+    return G @ G.T / n + np.eye(n)
+
+
+# ---- transposed-B and lower-triangle products --------------------------------------
+
+GEMM_EX = [
+    # M, N, K, transb, lower, beta, budget, integer inputs
+    (700, 650, 900, True, False, 0.5, 2 * MiB, True),
+    (700, 650, 900, True, True, 0.5, 2 * MiB, True),
+    (640, 640, 300, False, True, 0.0, 1 * MiB, False),
+    (513, 777, 1025, True, True, -1.0, 3 * MiB, False),
+]
+
+
+@pytest.mark.parametrize("case", range(len(GEMM_EX)))
+def test_gemm_ex_against_the_oracle(case):
+    M, N, K, transb, lower, beta, budget, integer = GEMM_EX[case]
+    _say(f"gemm_ex case {GEMM_EX[case]}")
+    dist = synth.INT if integer else synth.NORMAL
+    A = synth.matrix(M, K, synth.spec(900 + case, 0, dist))
+    Bs = synth.matrix(N, K, synth.spec(900 + case, 1, dist)) if transb else synth.matrix(K, N, synth.spec(900 + case, 1, dist))
+    C0 = synth.matrix(M, N, synth.spec(900 + case, 2, dist))
+    up = np.triu(np.ones((M, N), dtype=bool), 1)
+    if lower:
+        C0[up] = np.nan  # above the diagonal: neither read nor changed
+    Pa, Pb, Pc = _pinned(A), _pinned(Bs), _pinned(C0)
+    try:
+        _, st = ooc.ooc_gemm_ex(1.25, Pa.array, Pb.array, beta, Pc.array, budget, transb=transb, lower=lower)
+        got = Pc.array.copy()
+        B = np.ascontiguousarray(Bs.T) if transb else Bs
+        Cin = np.where(up, 0.0, C0) if lower else C0
+        ref, D = oracle.gemm_rows(1.25, A, B, beta, Cin if beta != 0.0 else None)
+        keep = ~up if lower else np.ones((M, N), dtype=bool)
+        if integer:
+            assert np.array_equal(got[keep], ref[keep])
+        else:
+            lit, gen = oracle.errors(np.where(keep, got, ref), ref, 1.25, D, beta, Cin if beta != 0.0 else None)
+            _say(f"  error literal {lit:.3e} generalised {gen:.3e}; plan {st.plan}")
+            assert gen <= oracle.GATE
+        if lower:
+            assert np.all(np.isnan(got[up]))
+        assert st.arena_bytes <= budget
+    finally:
+        for P in (Pa, Pb, Pc):
+            P.free()
+        ooc.ooc_release(-1)
+
+
+def test_syrk_against_the_oracle():
+    N, K = 900, 700
+    A = synth.matrix(N, K, synth.spec(77, 0, synth.INT))
+    C0 = synth.matrix(N, N, synth.spec(77, 2, synth.INT))
+    C0[np.triu_indices(N, 1)] = np.nan
+    Pa, Pc = _pinned(A), _pinned(C0)
+    try:
+        _, st = ooc.ooc_syrk(-0.5, Pa.array, 2.0, Pc.array, 2 * MiB)
+        want = chol_ref.syrk_lower(-0.5, A, 2.0, C0)
+        assert np.array_equal(Pc.array, want, equal_nan=True)
+        _say(f"syrk: plan {st.plan} ops {st.ops} arena {st.arena_bytes}")
+    finally:
+        Pa.free(); Pc.free()
+        ooc.ooc_release(-1)
+
+
+# ---- Cholesky factorisation --------------------------------------------------------
+
+@pytest.mark.parametrize("n,budget", [(37, 1 * MiB), (700, 2 * MiB), (1500, 3 * MiB)])
+def test_potrf_integer_factor_exact(n, budget):
+    L = _int_factor(n, n)
+    A = L @ L.T
+    A[np.triu_indices(n, 1)] = np.nan  # never read, left as it was
+    P = _pinned(A)
+    try:
+        _, info, st = ooc.ooc_potrf(P.array, budget)
+        _say(f"potrf n={n}: panels {st.blocks_done} ops {st.ops} arena {st.arena_bytes} t {st.t_total_s * 1e3:.1f} ms")
+        got = P.array
+        assert info == 0
+        assert np.array_equal(np.tril(got), L)
+        assert np.all(np.isnan(got[np.triu_indices(n, 1)]))
+        assert st.arena_bytes <= budget
+    finally:
+        P.free()
+        ooc.ooc_release(-1)
+
+
+def test_potrf_random_spd_against_the_oracle():
+    n = 2000
+    A = _spd(n, 5)
+    P = _pinned(A)
+    try:
+        _, info, st = ooc.ooc_potrf(P.array, 4 * MiB)
+        L = np.tril(P.array)
+        Lref = chol_ref.potrf_lower(A)
+        fwd = np.max(np.abs(L - Lref)) / np.max(np.abs(Lref))
+        back = np.abs(A - L @ L.T)
+        bound = 2.0 * chol_ref.backward_bound(L)
+        _say(f"potrf n={n}: forward {fwd:.3e}, backward worst ratio {np.max(back / bound):.3e}, panels {st.blocks_done}")
+        assert info == 0
+        assert fwd <= 1e-12
+        assert np.all(back <= bound)
+    finally:
+        P.free()
+        ooc.ooc_release(-1)
+
+
+@pytest.mark.parametrize("col", [0, 333, 699])
+def test_potrf_reports_the_failing_pivot(col):
+    n = 700
+    L = _int_factor(n, 3)
+    A = L @ L.T
+    A[col, col] -= L[col, col] ** 2  # pivot col becomes 0
+    P = _pinned(A)
+    try:
+        st, info, _ = ooc.ooc_potrf(P.array, 2 * MiB, raise_on_error=False)
+        assert st == ooc.OOC_ERR_NOT_SPD and info == col + 1
+        # the block columns before the failing one hold L
+        b = 256
+        done = (col // b) * b
+        assert np.array_equal(np.tril(P.array)[:, :done], L[:, :done])
+    finally:
+        P.free()
+        ooc.ooc_release(-1)
+
+
+def test_potrf_large_sampled_rows():
+    # 12288^2 (1.1 GiB) through a 256 MiB budget: several panels, chunked solves,
+    # out-of-core updates; checked on sampled rows by the backward-error bound
+    n = 12288
+    G = synth.matrix(n, 64, synth.spec(4242, 0, synth.UNIFORM))
+    P = ooc.PinnedMatrix(n, n)
+    try:
+        A = P.array
+        A[...] = G @ G.T / 64.0
+        A[np.arange(n), np.arange(n)] += 2.0
+        diag = A.diagonal().copy()
+        rows = np.array([0, 1, 4095, 4096, 8191, 8192, 12287] + list(np.random.default_rng(1).integers(0, n, 9)))
+        Arows = A[rows].copy()
+        _, info, st = ooc.ooc_potrf(A, 256 * MiB)
+        _say(f"potrf n={n}: {st.flops / st.t_total_s / 1e12:.2f} TFLOP/s, {st.t_total_s:.3f} s, panels "
+             f"{st.blocks_done}, H2D {st.bytes_h2d / 1e9:.2f} GB")
+        assert info == 0
+        Lf = np.tril(A)
+        aL = np.abs(Lf)
+        gamma = (n + 1) * 2.0 ** -53 / (1 - (n + 1) * 2.0 ** -53)
+        for r, arow in zip(rows, Arows):
+            # (L L^T)[r, :r+1] = L[:r+1, :] @ L[r, :], against the bound of the backward error
+            prod = Lf[:r + 1, :r + 1] @ Lf[r, :r + 1]
+            bnd = 2.0 * gamma * (aL[:r + 1, :r + 1] @ aL[r, :r + 1])
+            assert np.all(np.abs(arow[:r + 1] - prod) <= bnd), r
+        assert np.all(np.diagonal(A) > 0)
+    finally:
+        P.free()
+        ooc.ooc_release(-1)
+
+
+# ---- the general executor: hand-built operation lists -------------------------------
+
+def test_run_ops_product_list():
+    A = synth.matrix(300, 200, synth.spec(5, 0, synth.INT))
+    B = synth.matrix(200, 250, synth.spec(5, 1, synth.INT))
+    Pa, Pb, Pc = _pinned(A), _pinned(B), _pinned(np.full((300, 250), np.nan))
+    try:
+        offb, offc = 300 * 200, 300 * 200 + 200 * 250
+        ops = [ooc.make_op("h2d", 0, mat=0, rows=300, cols=200, off_c=0, ld_c=200),
+               ooc.make_op("h2d", 0, mat=1, rows=200, cols=250, off_c=offb, ld_c=250),
+               ooc.make_op("gemm", 1, waits=[0, 1], rows=300, cols=250, k=200, off_a=0, ld_a=200, off_b=offb,
+                           ld_b=250, off_c=offc, ld_c=250, alpha=1.0, beta=0.0),
+               ooc.make_op("d2h", 2, waits=[2], mat=2, rows=300, cols=250, off_c=offc, ld_c=250)]
+        assert ooc.ooc_check_ops(ops)[0] == ooc.OOC_OK
+        ooc.ooc_run_ops(ops, [Pa.array, Pb.array, Pc.array], (offc + 300 * 250) * 8)
+        assert np.array_equal(Pc.array, A @ B)
+    finally:
+        for P in (Pa, Pb, Pc):
+            P.free()
+        ooc.ooc_release(-1)
+
+
+def test_run_ops_factor_and_solve_list():
+    # a 192-column panel: factor its diagonal block, solve the 500 rows below
+    # against it (in two chunks through one buffer), all as one operation list
+    n, b = 692, 192
+    L = _int_factor(n, 8)
+    A = L @ L.T
+    Pa = _pinned(A)
+    Ps = _pinned(np.zeros((1, 1)))
+    try:
+        base = b * b + 8
+        ops = [ooc.make_op("h2d", 0, mat=0, rows=b, cols=b, off_c=0, ld_c=b),
+               ooc.make_op("h2d", 0, mat=1, rows=1, cols=1, off_c=b * b, ld_c=1),
+               ooc.make_op("potrf", 1, waits=[0, 1], rows=b, cols=b, off_c=0, ld_c=b, off_w=b * b, len_w=1),
+               ooc.make_op("d2h", 2, waits=[2], mat=0, rows=b, cols=b, off_c=0, ld_c=b),
+               ooc.make_op("d2h", 2, waits=[2], mat=1, rows=1, cols=1, off_c=b * b, ld_c=1)]
+        for q, (r0, rr) in enumerate([(b, 250), (b + 250, 250)]):
+            w = [len(ops) - 1] if q else []
+            ops.append(ooc.make_op("h2d", 0, waits=w, mat=0, row0=r0, rows=rr, cols=b, off_c=base, ld_c=b))
+            ops.append(ooc.make_op("trsm", 1, waits=[len(ops) - 1], rows=rr, cols=b, off_c=base, ld_c=b, off_a=0,
+                                   ld_a=b))
+            ops.append(ooc.make_op("d2h", 2, waits=[len(ops) - 1], mat=0, row0=r0, rows=rr, cols=b, off_c=base,
+                                   ld_c=b))
+        st, x, y = ooc.ooc_check_ops(ops)
+        assert st == ooc.OOC_OK, (x, y)
+        ooc.ooc_run_ops(ops, [Pa.array, Ps.array], (base + 250 * b) * 8)
+        assert Ps.array[0, 0] == 0.0
+        assert np.array_equal(np.tril(Pa.array[:, :b]), L[:, :b])
+    finally:
+        Pa.free(); Ps.free()
+        ooc.ooc_release(-1)
