@@ -246,3 +246,24 @@ def test_run_ops_factor_and_solve_list():
     finally:
         Pa.free(); Ps.free()
         ooc.ooc_release(-1)
+
+
+def test_gemm_ex_transposed_b_split_bf16():
+    # op(B) = B^T through the split-BF16 form: the stored B^T is sliced by rows
+    M, N, K = 600, 520, 1300
+    A = synth.matrix(M, K, synth.spec(321, 0, synth.NORMAL, row_exp=(-10, 10)))
+    Bs = synth.matrix(N, K, synth.spec(321, 1, synth.NORMAL, row_exp=(-10, 10)))
+    C0 = synth.matrix(M, N, synth.spec(321, 2, synth.UNIFORM))
+    Pa, Pb, Pc = _pinned(A), _pinned(Bs), _pinned(C0)
+    try:
+        _, st = ooc.ooc_gemm_ex(1.0, Pa.array, Pb.array, 0.5, Pc.array, 8 * MiB, transb=True,
+                                opts=ooc.make_opts(precision=ooc.SPLIT_BF16, slices=6))
+        ref, D = oracle.gemm_rows(1.0, A, np.ascontiguousarray(Bs.T), 0.5, C0)
+        lit, gen = oracle.errors(Pc.array, ref, 1.0, D, 0.5, C0)
+        _say(f"split transb: error literal {lit:.3e} generalised {gen:.3e}; plan {st.plan}")
+        assert st.plan.precision == ooc.SPLIT_BF16
+        assert gen <= oracle.GATE
+    finally:
+        for P in (Pa, Pb, Pc):
+            P.free()
+        ooc.ooc_release(-1)
