@@ -13,8 +13,8 @@
 // Both recurse on halves: potrf(A11); A21 <- A21 L11^{-T}; A22 <- A22 - A21 A21^T
 // (lower triangle); potrf(A22), and trsm on X1 = X[:, :n1]; X2 <- X2 - X1 L21^T;
 // trsm on X2, so nearly all their flops run in the FP64 matrix-core tile
-// kernel; blocks of at most 64 (potrf) or 32 (trsm) columns are finished by
-// the leaf kernels below.  Every quotient is a true division (no reciprocal), so integer
+// kernel; blocks of at most 64 columns are finished by the leaf kernels
+// below.  Every quotient is a true division (no reciprocal), so integer
 // inputs whose factor is integer give it exactly.
 #include <hip/hip_runtime.h>
 
@@ -26,7 +26,8 @@ namespace ooc {
 namespace {
 
 constexpr int kLeaf = 64;   // potrf leaf: one wave, the block in LDS
-constexpr int kLeafT = 32;  // trsm leaf: a row of X in registers per thread
+constexpr int kLeafT = 64;  // trsm leaf: one thread per row of X, rows and L in LDS
+constexpr int kLeafRows = 64;  // rows of X per trsm-leaf workgroup (one wave: more workgroups per leaf)
 
 // One wave factors an n x n block (n <= 64) held in LDS, column by column:
 // pivot, scale the column below it, update the trailing lower triangle.  A
@@ -66,19 +67,19 @@ __global__ __launch_bounds__(64) void potrf_leaf(int n, double* __restrict__ A, 
     if (l <= r) A[r * lda + l] = a[r][l];
 }
 
-// X <- X L^{-T} for X (m x n, n <= 32): each thread solves one row,
+// X <- X L^{-T} for X (m x n, n <= 64): each thread solves one row,
 // x_j = (x_j - sum_{k<j} x_k L_jk) / L_jj, with L and the rows in LDS (a
-// thread's row as a column of xs, so the 256 threads read consecutive words).
-__global__ __launch_bounds__(256) void trsm_leaf(int64_t m, int n, double* __restrict__ X, int64_t ldx,
-                                                 const double* __restrict__ L, int64_t ldl) {
+// thread's row as a column of xs, so the threads read consecutive words).
+__global__ __launch_bounds__(kLeafRows) void trsm_leaf(int64_t m, int n, double* __restrict__ X, int64_t ldx,
+                                                       const double* __restrict__ L, int64_t ldl) {
   __shared__ double lt[kLeafT][kLeafT + 1];
-  __shared__ double xs[kLeafT][256];
-  for (int e = threadIdx.x; e < kLeafT * kLeafT; e += 256) {
+  __shared__ double xs[kLeafT][kLeafRows];
+  for (int e = threadIdx.x; e < kLeafT * kLeafT; e += kLeafRows) {
     const int r = e / kLeafT, c = e % kLeafT;
     lt[r][c] = (r < n && c <= r) ? L[r * ldl + c] : (r == c ? 1.0 : 0.0);
   }
   const int t = threadIdx.x;
-  const int64_t row = (int64_t)blockIdx.x * 256 + t;
+  const int64_t row = (int64_t)blockIdx.x * kLeafRows + t;
   double* xr = X + row * ldx;
   const bool live = row < m;
   for (int j = 0; j < n; ++j) xs[j][t] = live ? xr[j] : 0.0;
@@ -104,7 +105,8 @@ hipError_t launch_trsm_rlt(int64_t m, int64_t n, double* X, int64_t ldx, const d
                            hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (n <= kLeafT) {
-    hipLaunchKernelGGL(trsm_leaf, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, (int)n, X, ldx, L, ldl);
+    hipLaunchKernelGGL(trsm_leaf, dim3((unsigned)((m + kLeafRows - 1) / kLeafRows)), dim3(kLeafRows), 0, s, m,
+                       (int)n, X, ldx, L, ldl);
     return hipGetLastError();
   }
   const int64_t n1 = half_of(n, kLeafT), n2 = n - n1;
