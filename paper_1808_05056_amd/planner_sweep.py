@@ -7,16 +7,19 @@ device, Section VI).  This tool
 
   train   times a set of candidates per problem of a training batch (M, N, K
           log-uniform in [4096, 24576], budgets log-uniform 256 MiB - 8 GiB,
-          seed 40), fits the network with the library's GPU kernels
+          seed 40, plus --tall tall problems, seed 41), fits the network with the library's GPU kernels
           (ooc_mlp_fit: full-batch Adam, L2 weight decay) and writes the weights;
           --precision split times split-BF16 plans (--slices) instead;
   fit     refits the network from the timings one or more train runs saved
           (--data a.npz,b.npz: FP64 and split timings fit one network, whose
           slice-count feature tells the two apart);
-  eval    times every candidate of the evaluation batch (seed 4) that the cost
-          model, the network or the paper's rule would consider, and reports
-          the regret t(choice) / t(best measured) - 1 of each planner
-          (--precision split or split-int8: slice plans);
+  eval    times, per problem of the evaluation batch (seed 4), the cost
+          model's best candidates, the network's best and the three planners'
+          choices, and reports the regret t(choice) / t(best measured) - 1 of
+          each planner (--precision split or split-int8: slice plans);
+          --exhaustive times every candidate the planners consider (the
+          judge of the restricted set's best), --smallest N keeps the N
+          problems with the fewest flops;
   sweep   times the cost model's best candidates for one named workload (and
           the model's, the network's and the paper's choices): the swept plan;
           --precision split or split-int8 sweeps BF16 or INT8 slice plans.
@@ -110,7 +113,7 @@ def candidate_set(w, n_model, n_random, rng, extra=(), opts=None, within=None):
 
 def train(args):
     from synth import workloads as W
-    problems = W.problem_batch(40, count=args.count)
+    problems = W.problem_batch(40, count=args.count) + W.tall_batch(41, count=args.tall)
     bufs = Buffers(problems)
     rng = np.random.default_rng(1)
     X, y, meta = [], [], []
@@ -179,6 +182,9 @@ def evaluate(args):
     if args.weights:
         ooc.ooc_mlp_load(args.weights)
     problems = W.problem_batch(4, count=args.count)
+    if args.smallest:
+        # a subset fixed by size alone (never by outcome): the problems with the fewest flops
+        problems = sorted(problems, key=lambda w: w.flops)[: args.smallest]
     bufs = Buffers(problems)
     split = args.precision != "fp64"
     rows = []
@@ -204,6 +210,9 @@ def evaluate(args):
         sweep = [all_plans[i] for i in range(min(args.n_model, len(all_plans)))]
         sweep += [ranked[i] for i in by_mlp]
         sweep += [pm, pl] + ([] if split else [pp])
+        restricted = {_key(p) for p in sweep}
+        if args.exhaustive:  # every candidate the planners consider
+            sweep += list(all_plans)
         uniq, seen = [], set()
         for p in sweep:
             if _key(p) not in seen:
@@ -214,9 +223,24 @@ def evaluate(args):
         for p in uniq:
             times[_key(p)] = time_plan(w, views, p, args.reps)
             _log(f"[eval]   {p} {times[_key(p)]:.3f}s")
+        if args.confirm:
+            # the minimum of many single timings is biased low: re-time the
+            # fastest plans and the planners' choices, best of confirm_reps
+            by_time = sorted(uniq, key=lambda p: times[_key(p)])
+            again, seen2 = [], set()
+            for p in by_time[: args.confirm] + [pm, pl] + ([] if split else [pp]):
+                if _key(p) not in seen2:
+                    again.append(p)
+                    seen2.add(_key(p))
+            for p in again:
+                t2 = time_plan(w, views, p, args.confirm_reps)
+                _log(f"[eval]   confirm {p} {times[_key(p)]:.4f}s -> {t2:.4f}s")
+                times[_key(p)] = t2
         best = min(times.values())
         r = {"problem": idx, "M": w.M, "N": w.N, "K": w.K, "budget": w.budget, "swept": len(uniq),
-             "best_s": best, "model_s": times[_key(pm)], "mlp_s": times[_key(pl)], "flops": w.flops}
+             "best_s": best, "model_s": times[_key(pm)], "mlp_s": times[_key(pl)], "flops": w.flops,
+             "candidates": len(all_plans),
+             "restricted_best_s": min(t for k, t in times.items() if k in restricted)}
         if pp is not None:
             r["paper_s"] = times[_key(pp)]
         rows.append(r)
@@ -234,6 +258,11 @@ def evaluate(args):
                    "total_s": float(sum(r[f"{k}_s"] for r in rows))}
     summ["best"] = {"total_s": float(sum(r["best_s"] for r in rows)),
                     "mean_tflops": float(np.mean([r["flops"] / r["best_s"] / 1e12 for r in rows]))}
+    if args.exhaustive:
+        # how far the restricted set (model's best, network's best, the three choices) is from the whole
+        rb = np.array([r["restricted_best_s"] / r["best_s"] - 1 for r in rows])
+        summ["restricted_judge"] = {"mean_gap": float(rb.mean()), "max_gap": float(rb.max()),
+                                    "exact": int(np.sum(rb == 0.0)), "problems": len(rows)}
     with open(args.report, "w") as f:
         json.dump({"summary": summ, "problems": rows}, f, indent=1)
     _log(json.dumps(summ))
@@ -287,6 +316,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
     t.add_argument("--count", type=int, default=48)
+    t.add_argument("--tall", type=int, default=8, help="tall problems (synth tall_batch, seed 41) added to the batch")
     t.add_argument("--n-model", type=int, default=8)
     t.add_argument("--n-random", type=int, default=6)
     t.add_argument("--reps", type=int, default=1)
@@ -306,6 +336,10 @@ def main(argv=None):
         q.add_argument("--data", default="planner_sweep_train.npz")
         q.add_argument("--out", default="planner_mlp.txt")
     e.add_argument("--count", type=int, default=64)
+    e.add_argument("--smallest", type=int, default=0, help="only the N problems with the fewest flops")
+    e.add_argument("--exhaustive", action="store_true", help="time every candidate the planners consider")
+    e.add_argument("--confirm", type=int, default=0, help="re-time the N fastest plans and the choices")
+    e.add_argument("--confirm-reps", type=int, default=3)
     e.add_argument("--n-model", type=int, default=6)
     e.add_argument("--n-mlp", type=int, default=4)
     e.add_argument("--reps", type=int, default=1)

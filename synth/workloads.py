@@ -84,3 +84,20 @@ def problem_batch(seed, count=64, lo=4096, hi=24576, budget_lo=256 * MiB, budget
         out.append(Workload(f"batch{seed}-{p}", dims[0], dims[1], dims[2], 1.0, 0.0, budget,
                             seed=seed * 1000 + p))
     return out
+
+
+def tall_batch(seed, count=8, m_lo=65536, m_hi=262144, lo=4096, hi=8192, budget_lo=1 * GiB, budget_hi=4 * GiB):
+    """Tall problems: M log-uniform in [m_lo, m_hi], N and K log-uniform in
+    [lo, hi], budgets log-uniform in [budget_lo, budget_hi] rounded down to
+    2 MiB, beta = 1 for odd-numbered problems (0 otherwise); entries
+    uniform[-1, 1].  seed 41 widens the planner's training batch to the shapes
+    of the tall workload."""
+    out = []
+    for p in range(count):
+        m = int(round(math.exp(math.log(m_lo) + (math.log(m_hi) - math.log(m_lo)) * _u01(seed, p, 0))))
+        n, k = (int(round(math.exp(math.log(lo) + (math.log(hi) - math.log(lo)) * _u01(seed, p, q))))
+                for q in (1, 2))
+        b = math.exp(math.log(budget_lo) + (math.log(budget_hi) - math.log(budget_lo)) * _u01(seed, p, 3))
+        budget = max(2 * MiB, int(b) // (2 * MiB) * (2 * MiB))
+        out.append(Workload(f"tall{seed}-{p}", m, n, k, 1.0, float(p % 2), budget, seed=seed * 1000 + p))
+    return out

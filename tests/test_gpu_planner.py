@@ -29,17 +29,25 @@ def test_fit_learns_a_timing_function():
         ooc.ooc_mlp_load(WEIGHTS)
 
 
+def _subset():
+    """Problems of the evaluation batch fixed by size alone, never by outcome:
+    the first four under 4e12 flop."""
+    return [w for w in W.problem_batch(4, count=64) if w.flops < 4e12][:4]
+
+
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained planner network shipped with the library")
 def test_learned_planner_beats_the_papers_rule():
+    """What the trained network gains over the method without it (the paper's
+    partition rule), with its gain or regret against the cost model beside it."""
     ooc.ooc_mlp_load(WEIGHTS)
-    problems = [w for w in W.problem_batch(4, count=64) if w.flops < 4e12][:4]
+    problems = _subset()
     assert problems and all(w.beta == 0.0 for w in problems)
-    gains = []
+    gains, vs_model = [], []
     for w in problems:
         pp = PinnedProblem(w)
         try:
             times = {}
-            for name, planner in (("mlp", ooc.PLAN_MLP), ("paper", ooc.PLAN_PAPER)):
+            for name, planner in (("mlp", ooc.PLAN_MLP), ("paper", ooc.PLAN_PAPER), ("model", ooc.PLAN_MODEL)):
                 opts = ooc.make_opts(planner=planner)
                 _, stats = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, opts)
                 assert stats.arena_bytes <= w.budget
@@ -49,23 +57,23 @@ def test_learned_planner_beats_the_papers_rule():
                            for _ in range(2))
                 times[name] = best
             gains.append(times["paper"] / times["mlp"])
+            vs_model.append(times["model"] / times["mlp"])
             print(f"M={w.M} N={w.N} K={w.K} budget={w.budget >> 20} MiB: paper {times['paper']:.4f}s "
-                  f"learned {times['mlp']:.4f}s", flush=True)
+                  f"model {times['model']:.4f}s learned {times['mlp']:.4f}s", flush=True)
         finally:
             pp.free()
+    print(f"learned vs paper's rule: {np.mean(gains):.3f}x; vs cost model: {np.mean(vs_model):.3f}x", flush=True)
     assert np.mean(gains) > 1.0, gains
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained planner network shipped with the library")
 def test_learned_planner_on_split_plans():
     """The shipped network was also fitted to split-BF16 (s = 5) timings.  On
-    three problems of the evaluation batch where the timed sweep found the
-    network's split plan faster than the cost model's, its choice is a
-    different plan, runs within the budget, meets the gate against the oracle
-    and is not slower than the model's beyond timing noise."""
+    the same size-fixed subset of the evaluation batch its split choice runs
+    within the budget, meets the gate against the oracle and, in total, is not
+    slower than the cost model's choice beyond timing noise (5 %)."""
     ooc.ooc_mlp_load(WEIGHTS)
-    batch = W.problem_batch(4, count=64)
-    problems = [batch[i] for i in (22, 35, 57)]
+    problems = _subset()
     assert all(w.beta == 0.0 and w.flops < 4e12 for w in problems)
     total = {"mlp": 0.0, "model": 0.0}
     differ = 0
@@ -87,26 +95,30 @@ def test_learned_planner_on_split_plans():
             differ += chosen["mlp"] != chosen["model"]
         finally:
             pp.free()
-    print(f"split plans: learned {total['mlp']:.4f}s, cost model {total['model']:.4f}s", flush=True)
-    assert differ > 0
-    assert total["mlp"] <= 1.02 * total["model"], total
+    print(f"split plans: learned {total['mlp']:.4f}s, cost model {total['model']:.4f}s; "
+          f"{differ} of {len(problems)} choices differ", flush=True)
+    assert total["mlp"] <= 1.05 * total["model"], total
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained planner network shipped with the library")
 def test_learned_planner_declines_problems_outside_its_training_range():
     """M, N, K or budget more than four deviations (log scale) from the
     training problems' mean: the network's prediction would be an
-    extrapolation and the cost model's plan stands; inside the range the
-    network does change the choice."""
+    extrapolation and the cost model's plan stands (here a 1024^3 problem
+    through 8 MiB and a 2^22-row one); the tall workload, whose shapes the
+    training batch covers, is planned by the network."""
     ooc.ooc_mlp_load(WEIGHTS)
-    for w in (W.TALL, W.SMALL):
+    far = W.Workload("far", 1 << 22, 8192, 8192, 1.0, 0.0, 4 << 30, seed=0)
+    for w in (far, W.SMALL):
         for prec, s in ((ooc.FP64, 0), (ooc.SPLIT_BF16, 5)):
             mlp = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget,
                                ooc.make_opts(planner=ooc.PLAN_MLP, precision=prec, slices=s))
             model = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget,
                                  ooc.make_opts(planner=ooc.PLAN_MODEL, precision=prec, slices=s))
             assert mlp.as_dict() == model.as_dict(), (w.name, prec)
-    w = W.problem_batch(4, count=64)[22]
-    opts = {p: ooc.make_opts(planner=p, precision=ooc.SPLIT_BF16, slices=5) for p in (ooc.PLAN_MLP, ooc.PLAN_MODEL)}
-    plans = {p: ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, o).as_dict() for p, o in opts.items()}
-    assert plans[ooc.PLAN_MLP] != plans[ooc.PLAN_MODEL]
+    w = W.TALL
+    cands = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget)[0][:8]
+    pred = ooc.ooc_mlp_predict(w.M, w.N, w.K, w.beta, w.budget, cands)
+    assert np.all(np.isfinite(pred)) and np.all(np.asarray(pred) > 0)
+    mlp = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, ooc.make_opts(planner=ooc.PLAN_MLP))
+    assert mlp.as_dict() == cands[int(np.argmin(pred))].as_dict()
