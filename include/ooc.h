@@ -350,7 +350,8 @@ ooc_status ooc_syrk(int64_t N, int64_t K, double alpha, const double* A, int64_t
  * matrix A in place (row-major, lda >= N, page-locked): the lower triangle is
  * read and overwritten by L; the strict upper triangle is left unchanged.
  * Left-looking by block columns of b columns (the largest multiple of 64 up
- * to 8192 whose b x b block and two 256-row chunks fit the budget): the
+ * to 8192 whose b x b block takes at most a quarter of the budget, the rest
+ * holding two chunks of at least 256 rows): the
  * update of a block column by the columns to its left is one out-of-core
  * product (C = C - A B^T on the lower triangle, ooc_gemm_ex); its diagonal
  * block is factored on the device and the rows below are solved against it

@@ -539,12 +539,17 @@ void list_stats(const std::vector<ooc_op>& ops, ooc_stats* st) {
 }
 
 // Panel width of the out-of-core Cholesky factorisation: the largest multiple
-// of 64 up to 8192 (and N rounded up to 64) whose b x b diagonal block, two
-// chunk buffers of 256 rows and the status word fit the budget.
+// of 64 up to 8192 (and N rounded up to 64) whose b x b diagonal block takes
+// at most a quarter of the budget, leaving the rest to the two chunk buffers
+// of the solve (tall chunks keep the device solve's products wide), with at
+// least 256 rows per chunk.
 int64_t potrf_panel(int64_t N, uint64_t budget_elems) {
   int64_t b = std::min<int64_t>(8192, (N + 63) / 64 * 64);
-  while (b > 64 && (uint64_t)(b * b + 2 * 256 * b + 8) > budget_elems) b -= 64;
-  return (uint64_t)(b * b + 2 * 256 * b + 8) <= budget_elems ? b : 0;
+  auto fits = [&](int64_t x) {
+    return (uint64_t)(x * x) <= budget_elems / 4 && (uint64_t)(x * x + 2 * 256 * x + 8) <= budget_elems;
+  };
+  while (b > 64 && !fits(b)) b -= 64;
+  return fits(b) ? b : 0;
 }
 
 ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, const ooc_opts* opts, int64_t* info,
