@@ -76,6 +76,9 @@ def main():
     ap.add_argument("--split-leg", type=int, default=1, help="1: also time the split-BF16 form (FP64 runs only)")
     ap.add_argument("--split-slices", default="4,5,6",
                     help="slice counts tried for the split leg, smallest first; the first to meet the gate is timed")
+    ap.add_argument("--int8-leg", type=int, default=1, help="1: also time the split-INT8 form (FP64 runs only)")
+    ap.add_argument("--int8-slices", default="5,6,7",
+                    help="slice counts tried for the split-INT8 leg, smallest first; the first to meet the gate is timed")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
                     help="only run the library's device copy kernel once on BYTES (traffic-counter reference)")
     args = ap.parse_args()
@@ -146,9 +149,11 @@ def main():
     roof, link = leg.pop("roofline"), leg.pop("link")
     e2e = leg.pop("end_to_end_roofline")
 
-    split = None
+    split = split8 = None
     if args.split_leg and prec == ooc.FP64:
-        split = split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin)
+        split = split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin, ooc.SPLIT_BF16, args.split_slices)
+    if args.int8_leg and prec == ooc.FP64:
+        split8 = split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin, ooc.SPLIT_INT8, args.int8_slices)
 
     out = {
         "metric": METRIC, "value": leg["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -165,9 +170,12 @@ def main():
                    "planning_per_step_s": leg["plan_s"], "overlap": leg["overlap"]},
         "predicted_s": round(s1.t_predicted_s, 4),
         "split_bf16": split,
+        "split_int8": split8,
     }
     if split and split.get("value"):
         out["split_vs_fp64"] = round(split["value"] / leg["value"], 4)
+    if split8 and split8.get("value"):
+        out["split_int8_vs_fp64"] = round(split8["value"] / leg["value"], 4)
     print(json.dumps(out), flush=True)
     for m in (Am, Bm, Cm):
         m.free()
@@ -252,23 +260,24 @@ def run_leg(ooc, w, A, B, C, opts, popts, args, prec, slices):
             "plan": plan.as_dict(), "roofline": roof, "link": link, "end_to_end_roofline": e2e}
 
 
-def split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin):
-    """The split-BF16 form on the same workload and operands: the smallest slice
-    count (from --split-slices) whose result meets the gate on the oracle's
-    sampled rows (literal metric when beta == 0, generalised otherwise), timed
-    like the FP64 leg."""
+def split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin, prec, slice_list):
+    """A split form (BF16 or INT8 slices) on the same workload and operands: the
+    smallest slice count (from slice_list) whose result meets the gate on the
+    oracle's sampled rows (literal metric when beta == 0, generalised
+    otherwise), timed like the FP64 leg."""
     import oracle
+    tag = "bf16" if prec == ooc.SPLIT_BF16 else "int8"
     chosen, tried = None, []
-    for sl in (int(x) for x in args.split_slices.split(",")):
+    for sl in (int(x) for x in slice_list.split(",")):
         if w.beta != 0.0:
             synth.fill(C, w.spec_c())
-        o = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=sl)
+        o = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=prec, slices=sl)
         _, st = ooc.ooc_gemm(w.alpha, A, B, w.beta, C, w.budget, o)
         lit, gen = oracle.errors(C[rows], ref, w.alpha, D, w.beta, Cin) if ref is not None else (None, None)
         gated = lit if w.beta == 0.0 else gen
         tried.append({"slices": sl, "error_literal": lit, "error_generalised": gen,
                       "first_call_s": round(st.t_total_s, 4)})
-        log(f"[bench] split-BF16 s={sl}: plan {st.plan} {st.t_total_s:.3f}s error literal "
+        log(f"[bench] split-{tag.upper()} s={sl}: plan {st.plan} {st.t_total_s:.3f}s error literal "
             f"{lit if lit is None else f'{lit:.3e}'} generalised {gen if gen is None else f'{gen:.3e}'}")
         if gated is not None and gated <= oracle.GATE:
             chosen = (sl, lit, gen)
@@ -276,10 +285,10 @@ def split_leg(ooc, synth, w, A, B, C, args, ref, rows, D, Cin):
     if chosen is None:
         return {"value": None, "tried": tried, "note": "no slice count met the gate"}
     sl = chosen[0]
-    o = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=sl)
-    po = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=ooc.SPLIT_BF16, slices=sl, profile=bool(args.profile))
-    leg = run_leg(ooc, w, A, B, C, o, po, args, ooc.SPLIT_BF16, sl)
-    leg.update({"dtype": f"split-bf16x{sl}", "slices": sl, "error_literal": chosen[1],
+    o = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=prec, slices=sl)
+    po = ooc.make_opts(planner=ooc.PLAN_MODEL, precision=prec, slices=sl, profile=bool(args.profile))
+    leg = run_leg(ooc, w, A, B, C, o, po, args, prec, sl)
+    leg.update({"dtype": f"split-{tag}x{sl}", "slices": sl, "error_literal": chosen[1],
                 "error_generalised": chosen[2], "tried": tried})
     return leg
 

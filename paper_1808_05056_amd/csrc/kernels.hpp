@@ -31,6 +31,9 @@ enum SliceFormat { kSliceInt8 = 1, kSliceBF16 = 2 };
 inline SliceFormat slice_format(int precision) { return precision == OOC_SPLIT_INT8 ? kSliceInt8 : kSliceBF16; }
 constexpr int64_t kSplitMaxK = 8192;
 size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat f);
+// Whether the INT8 slice products of an m x n block run on 256 x 256 tiles
+// (else 256 x 128) on a device of `cus` compute units.
+bool split_i8_wide(int64_t m, int64_t n, int cus);
 // Optional timing of the slice-product kernels alone (slicing kernels
 // excluded): events[2x] and events[2x+1] are recorded around the x-th
 // slice-product launch, for x < count; `used` counts the launches made.

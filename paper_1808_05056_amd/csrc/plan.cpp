@@ -190,40 +190,22 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
     else if (rest > 0) t += tile_flops / r1;
   }
   if ((k & 1) || (n & 1)) t *= mc.kernel_scalar_factor;
-  if (precision == OOC_SPLIT_BF16) {
-    // the BF16 slice-product kernel computes whole 256 x 128 tiles, one per CU
-    // at a time, in waves of one tile per CU; every weight's pass over a tile
-    // pays a pipeline start of split_k0 k
-    const double mp = std::ceil(m / 256.0) * 256.0, np = std::ceil(n / 128.0) * 128.0;
-    const double products = slices * (slices + 1) / 2.0;
-    const double tiles16 = (double)ceil_div(m, 256) * (double)ceil_div(n, 128);
-    const double stile = 2.0 * 256.0 * 128.0 * (products * (double)k + slices * mc.split_k0);
-    const double ts = std::ceil(tiles16 / mc.cus) * stile / (mc.split_tflops_per_product * 1e12 / mc.cus);
-    const double slice_s = (mp + np) * k * (8.0 + 2.0 * slices) / 4e12;
-    // the FP64 slice-sum tile is read and written once per weight (s weights)
-    const double sum_s = (double)slices * 16.0 * mp * np / mc.hbm_bytes_per_s;
-    return mc.kernel_launch_s * 6 + slice_s + sum_s + ts;
-  }
   if (precision != OOC_FP64) {
-    // the INT8 slice-product kernel computes whole 128 x 128 tiles, two per
-    // CU at a time, in waves like the FP64 kernel; every weight's pass over a
-    // tile pays a pipeline start of split_k0 k at half the INT8 rate
-    const double mp = std::ceil(m / 128.0) * 128.0, np = std::ceil(n / 128.0) * 128.0;
+    // the slice-product kernels compute whole 256-row tiles of 128 columns
+    // (BF16, INT8) or 256 (INT8, when their waves end sooner), one per CU at
+    // a time, in waves of one tile per CU; every weight's pass over a tile
+    // pays a pipeline start of split_k0 k of BF16 work (twice as many k at
+    // the INT8 rate, which is about twice the BF16 one)
+    const bool i8 = precision == OOC_SPLIT_INT8;
+    const bool wide = i8 && split_i8_wide(m, n, mc.cus);
+    const double tbn = wide ? 256.0 : 128.0;
+    const double mp = std::ceil(m / 256.0) * 256.0, np = std::ceil(n / tbn) * tbn;
     const double products = slices * (slices + 1) / 2.0;
-    const double stile = 2.0 * 128.0 * 128.0 * (products * (double)k + 2.0 * slices * mc.split_k0);
-    const double s2 = mc.int8_tops_per_product * 1e12 / mc.cus;
-    const double s1 = mc.int8_tops_1wg_per_product * 1e12 / mc.cus;
-    double ts;
-    if (tiles <= mc.cus) {
-      ts = stile / s1;
-    } else {
-      const double per_wave = 2.0 * mc.cus;
-      const double full = std::floor(tiles / per_wave);
-      const double rest = tiles - full * per_wave;
-      ts = full * 2.0 * stile / s2;
-      if (rest > mc.cus) ts += 2.0 * stile / s2;
-      else if (rest > 0) ts += stile / s1;
-    }
+    const double stiles = (mp / 256.0) * (np / tbn);
+    const double stile = 2.0 * 256.0 * tbn * (products * (double)k + (i8 ? 2.0 : 1.0) * slices * mc.split_k0);
+    const double rate = !i8 ? mc.split_tflops_per_product
+                            : (wide ? mc.int8_wide_tops_per_product : mc.int8_tops_per_product);
+    const double ts = std::ceil(stiles / mc.cus) * stile / (rate * 1e12 / mc.cus);
     const double slice_s = (mp + np) * k * (8.0 + (double)slice_format(precision) * slices) / 4e12;
     // the FP64 slice-sum tile is read and written once per weight (s weights)
     const double sum_s = (double)slices * 16.0 * mp * np / mc.hbm_bytes_per_s;

@@ -37,6 +37,7 @@
 // so MFMA operands are contiguous in k; all padding is zero).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <type_traits>
 
@@ -224,8 +225,6 @@ __global__ __launch_bounds__(256) void split_cols(int64_t k, int64_t n, const do
   }
 }
 
-// Tiles of the INT8 slice-product kernel (128 x 128) and its LDS row padding (elements).
-constexpr int SBM = 128, SBN = 128, SKC = 64, SPAD = 8;
 
 // The exactness windows of the BF16 slice products (k per window), and the
 // bound on the sum over all pairs of weight t of one k's slice products.
@@ -312,36 +311,78 @@ __device__ inline void xcd_band_tile(int b, int tiles_m, int tiles_n, int gm_row
 }
 
 
-// BF16 slice products.  A workgroup of 8 waves (4 x 2) computes a 256 x 128
-// tile of C, each wave a 64 x 64 block as 2 x 2 tiles of
-// V_MFMA_F32_32X32X16_BF16 (one workgroup per CU, two waves per SIMD).  For each
-// weight t (from s+1 down to 2) the steps walk the exactness windows, inside a
-// window the pairs (p, t-p), inside a pair the window's 64-k chunks.  The A
-// and B plane rows of a step (256 + 128 rows of 128 bytes) are loaded straight
-// into one of three LDS stages, two steps ahead of the products; the direct
-// loads are written in asm so the compiler does not wait for all of them
-// before each LDS read, and the barrier between steps is a bare s_barrier
-// after an explicit wait for the next step's loads only (__syncthreads would
-// also wait for the loads of the step after).  At each window's end the FP32
-// accumulators are folded into the int32 sums U_t; at each weight's end the
-// sums go through LDS (the stages are idle by then) into
-// S = S + U_t 2^(e_i + f_j - 8t), accumulated in the workspace tile, and the
-// last weight writes C.  A row's 16-byte slots are permuted
-// (slot = chunk ^ ((row + row / 8) & 7)) so that 16-byte LDS reads of 8 or of
-// 16 consecutive rows fall in distinct banks.
-// Operand layout of V_MFMA_F32_32X32X16_BF16: lane l supplies A[l%32][8*(l/32) .. +8]
-// and B[8*(l/32) .. +8][l%32]; accumulator element v of lane l is
-// D[8*(v/4) + 4*(l/32) + v%4][l%32].
-constexpr int GBM = 256, GBN = 128, GKC = 64;  // tile rows, columns, k per step
-constexpr int GWM = 4, GWN = 2;                 // waves along M and N (64 x 64 each)
-constexpr int GNT = 64 * GWM * GWN;             // threads per workgroup
-constexpr int GROW = GKC * 2;                   // bytes per tile row and step
-constexpr int GA = GBM * GROW, GB = GBN * GROW, GSTAGE = GA + GB;
-constexpr int GNST = 3;                         // LDS stages
-constexpr int GALD = GBM / 8 / (GWM * GWN), GBLD = GBN / 8 / (GWM * GWN);  // 1-KB loads per wave and step
-constexpr int GLD = GALD + GBLD;
-static_assert(GALD * 8 * GWM * GWN == GBM && GBLD * 8 * GWM * GWN == GBN, "load split");
-static_assert(GBM * GBN * 4 <= GNST * GSTAGE, "sum buffer");
+// Slice products, BF16 or INT8 (EB bytes per digit), on 256-row tiles of C
+// of TBN = 128 or 256 columns.  A workgroup of 8 waves (one workgroup per
+// CU, two waves per SIMD) computes the tile, each wave a block of 2 x 2
+// (TBN = 128: 4 x 2 waves of 64 x 64) or 4 x 2 (TBN = 256: 2 x 4 waves of
+// 128 x 64) tiles of V_MFMA_F32_32X32X16_BF16 or V_MFMA_I32_32X32X32_I8.  For
+// each weight t (from s+1 down to 2) the steps walk the exactness windows,
+// inside a window the pairs (p, t-p), inside a pair the window's chunks of
+// 128 bytes per row (64 BF16 or 128 INT8 k).  The A and B plane rows of a
+// step (256 + TBN rows of 128 bytes) are loaded straight into one of NST LDS
+// stages, NST - 1 steps ahead of the products (three stages of 48 KiB for
+// TBN = 128, two of 64 KiB for TBN = 256); the direct loads are written in
+// asm so the compiler does not wait for all of them before each LDS read,
+// and the barrier between steps is a bare s_barrier after an explicit wait
+// for the next step's loads only (__syncthreads would also wait for the
+// loads of the step after).  At each window's end the FP32 accumulators are
+// folded into the int32 sums U_t; the INT8 products accumulate exactly in
+// INT32 over the whole K panel, so they have no windows and their
+// accumulators are the sums (which is what leaves the registers for TBN =
+// 256).  At each weight's end the sums go through LDS (the stages are idle
+// by then; for TBN = 256 one half of the tile at a time) into S = S + U_t
+// 2^(e_i + f_j - bits t), accumulated in the workspace tile, and the last
+// weight writes C.  A row's 16-byte slots are permuted (slot = chunk ^ ((row
+// + row / 8) & 7)) so that 16-byte LDS reads of 8 or of 16 consecutive rows
+// fall in distinct banks.
+// Operand layouts: lane l supplies A[l%32][8*(l/32) .. +8] and
+// B[8*(l/32) .. +8][l%32] (BF16, k16 per instruction) or A[l%32][16*(l/32) .. +16]
+// and B[16*(l/32) .. +16][l%32] (INT8, k32): 16 bytes per lane in both, slot
+// 2 kk + l/32 of the row for the kk-th instruction of a chunk.  Accumulator
+// element v of lane l is D[8*(v/4) + 4*(l/32) + v%4][l%32].
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+template <int EB>
+struct SliceMfma;
+template <>
+struct SliceMfma<2> {
+  typedef bf16x8 frag;
+  typedef f32x16 acc;
+  __device__ static acc mfma(frag a, frag b, acc c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+  static constexpr int kChunk = 64;  // k per 128-byte chunk
+  static constexpr bool kWindows = true;
+  __device__ static int window_chunks(int t, int) { return window_k(t) / kChunk; }
+};
+template <>
+struct SliceMfma<1> {
+  typedef i32x4 frag;
+  typedef i32x16 acc;
+  __device__ static acc mfma(frag a, frag b, acc c) { return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0); }
+  static constexpr int kChunk = 128;
+  // |U_t| < 8 * 8192 * 2^14 = 2^30 over a K panel of at most 8192: no windows
+  static constexpr bool kWindows = false;
+  __device__ static int window_chunks(int, int nchunks) { return nchunks; }
+};
+
+constexpr int GBM = 256;  // tile rows
+constexpr int GNT = 512;  // threads per workgroup (8 waves)
+constexpr int GROW = 128;  // bytes per tile row and step
+constexpr int GKK = 4;     // instructions per chunk along k (32 bytes of each row apiece)
+
+// Tile geometry for TBN columns.
+template <int TBN>
+struct SliceTile {
+  static constexpr int WM = TBN == 256 ? 2 : 4, WN = 8 / WM;                    // waves along M and N
+  static constexpr int FI = GBM / WM / 32, FJ = TBN / WN / 32;                  // 32 x 32 tiles per wave
+  static constexpr int A = GBM * GROW, STAGE = A + TBN * GROW;                  // bytes per LDS stage
+  static constexpr int NST = TBN == 256 ? 2 : 3;                                // LDS stages
+  static constexpr int ALD = GBM / 8 / 8, BLD = TBN / 8 / 8, LD = ALD + BLD;    // 1-KB loads per wave and step
+  static constexpr int HALVES = GBM * TBN * 4 > NST * STAGE ? 2 : 1;           // passes of the sums through LDS
+  static_assert(ALD * 64 == GBM && BLD * 64 == TBN, "load split");
+  static_assert(GBM / HALVES * TBN * 4 <= NST * STAGE && WM % HALVES == 0, "sum buffer");
+  static_assert(NST * STAGE + 4 * (GBM + TBN) <= 160 * 1024, "LDS");
+};
 
 __device__ __forceinline__ int gswz(int r) { return (r + (r >> 3)) & 7; }
 
@@ -360,62 +401,67 @@ __device__ __forceinline__ void wait_vm_barrier() {
   asm volatile("s_barrier" ::: "memory");
 }
 
-__global__ __launch_bounds__(GNT, 1) void split_gemm(int64_t m, int64_t n, int64_t kpad, int s,
-                                                     const uint16_t* __restrict__ Ap, const uint16_t* __restrict__ Bp,
-                                                     int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
-                                                     const int32_t* __restrict__ fb, double* __restrict__ Sws,
-                                                     double alpha, double beta, double* __restrict__ C, int64_t ldc,
-                                                     double gamma, const double* __restrict__ D, int64_t ldd) {
-  __shared__ __attribute__((aligned(1024))) unsigned char lds[GNST * GSTAGE];
-  __shared__ int32_t eas[GBM], fbs[GBN];
+template <int EB, int TBN>
+__device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kpad, int s,
+                                                const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
+                                                int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
+                                                const int32_t* __restrict__ fb, double* __restrict__ Sws,
+                                                double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                                double gamma, const double* __restrict__ D, int64_t ldd,
+                                                unsigned char* lds, int32_t* eas, int32_t* fbs) {
+  typedef SliceMfma<EB> M;
+  typedef SliceTile<TBN> T;
+  typedef typename M::frag frag;
+  constexpr int FI = T::FI, FJ = T::FJ, NST = T::NST;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w / GWN, wn = w % GWN;
+  const int wm = w / T::WN, wn = w % T::WN;
   int tm, tn;
-  xcd_band_tile((int)blockIdx.x, (int)(mpad / GBM), (int)(npad / GBN), kBandRows, &tm, &tn);
-  const int64_t m0 = (int64_t)tm * GBM, n0 = (int64_t)tn * GBN;
+  xcd_band_tile((int)blockIdx.x, (int)(mpad / GBM), (int)(npad / TBN), kBandRows, &tm, &tn);
+  const int64_t m0 = (int64_t)tm * GBM, n0 = (int64_t)tn * TBN;
   for (int r = tid; r < GBM; r += GNT) eas[r] = ea[m0 + r];
-  for (int c = tid; c < GBN; c += GNT) fbs[c] = fb[n0 + c];
-  const int nchunks = (int)(kpad / GKC);
+  for (int c = tid; c < TBN; c += GNT) fbs[c] = fb[n0 + c];
+  const int nchunks = (int)(kpad / M::kChunk);
+  const int64_t rowb = kpad * EB;  // bytes per plane row
 
-  // direct loads: wave w fills tile rows [8 GALD w, +8 GALD) of A and
-  // [8 GBLD w, +8 GBLD) of B, 8 rows per 1-KB load; lane l writes slot (l & 7)
-  // of row (l >> 3) of the load's 8, which holds the row's k-chunk slot ^ gswz(row)
+  // direct loads: wave w fills tile rows [8 ALD w, +8 ALD) of A and
+  // [8 BLD w, +8 BLD) of B, 8 rows per 1-KB load; lane l writes slot (l & 7)
+  // of row (l >> 3) of the load's 8, which holds the row's 16-byte slot ^ gswz(row)
   const int lrow = lane >> 3, lslot = lane & 7;
-  const uint16_t* a_src = Ap + (m0 + 8 * GALD * w + lrow) * kpad;
-  const uint16_t* b_src = Bp + (n0 + 8 * GBLD * w + lrow) * kpad;
+  const uint8_t* a_src = Ap + (m0 + 8 * T::ALD * w + lrow) * rowb;
+  const uint8_t* b_src = Bp + (n0 + 8 * T::BLD * w + lrow) * rowb;
   const uint32_t lds0 = (uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char*)lds;
-  const uint32_t la0 = __builtin_amdgcn_readfirstlane(lds0 + (8 * GALD * w) * GROW);
-  const uint32_t lb0 = __builtin_amdgcn_readfirstlane(lds0 + GA + (8 * GBLD * w) * GROW);
+  const uint32_t la0 = __builtin_amdgcn_readfirstlane(lds0 + (8 * T::ALD * w) * GROW);
+  const uint32_t lb0 = __builtin_amdgcn_readfirstlane(lds0 + T::A + (8 * T::BLD * w) * GROW);
   auto issue = [&](int p, int q, int cc, int stage) {
-    const uint16_t* pa = a_src + (int64_t)(p - 1) * mpad * kpad + (int64_t)cc * GKC;
-    const uint16_t* pb = b_src + (int64_t)(q - 1) * npad * kpad + (int64_t)cc * GKC;
-    const uint32_t so = (uint32_t)stage * GSTAGE;
+    const uint8_t* pa = a_src + (int64_t)(p - 1) * mpad * rowb + (int64_t)cc * GROW;
+    const uint8_t* pb = b_src + (int64_t)(q - 1) * npad * rowb + (int64_t)cc * GROW;
+    const uint32_t so = (uint32_t)stage * T::STAGE;
 #pragma unroll
-    for (int j = 0; j < GALD; ++j)
-      load_lds16(pa + (int64_t)8 * j * kpad + 8 * (lslot ^ gswz(8 * (GALD * w + j) + lrow)), la0 + so + 1024 * j);
+    for (int j = 0; j < T::ALD; ++j)
+      load_lds16(pa + 8 * j * rowb + 16 * (lslot ^ gswz(8 * (T::ALD * w + j) + lrow)), la0 + so + 1024 * j);
 #pragma unroll
-    for (int j = 0; j < GBLD; ++j)
-      load_lds16(pb + (int64_t)8 * j * kpad + 8 * (lslot ^ gswz(8 * (GBLD * w + j) + lrow)), lb0 + so + 1024 * j);
+    for (int j = 0; j < T::BLD; ++j)
+      load_lds16(pb + 8 * j * rowb + 16 * (lslot ^ gswz(8 * (T::BLD * w + j) + lrow)), lb0 + so + 1024 * j);
   };
   const int fr = lane & 31, fh = lane >> 5;
-  const int a_row0 = wm * 64 + fr, b_row0 = wn * 64 + fr;
-  auto frags = [&](const unsigned char* As, const unsigned char* Bs, int kk, bf16x8 (&a)[2], bf16x8 (&b)[2]) {
+  const int a_row0 = wm * (GBM / T::WM) + fr, b_row0 = wn * (TBN / T::WN) + fr;
+  auto frags = [&](const unsigned char* As, const unsigned char* Bs, int kk, frag (&a)[FI], frag (&b)[FJ]) {
     const int ch = 2 * kk + fh;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < FI; ++i) {
       const int r = a_row0 + 32 * i;
-      a[i] = *reinterpret_cast<const bf16x8*>(As + r * GROW + ((ch ^ gswz(r)) << 4));
+      a[i] = *reinterpret_cast<const frag*>(As + r * GROW + ((ch ^ gswz(r)) << 4));
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < FJ; ++j) {
       const int r = b_row0 + 32 * j;
-      b[j] = *reinterpret_cast<const bf16x8*>(Bs + r * GROW + ((ch ^ gswz(r)) << 4));
+      b[j] = *reinterpret_cast<const frag*>(Bs + r * GROW + ((ch ^ gswz(r)) << 4));
     }
   };
 
   for (int t = s + 1; t >= 2; --t) {
     const int plo = t - s > 1 ? t - s : 1, phi = t - 1 < s ? t - 1 : s;
-    const int np = phi - plo + 1, wc = window_k(t) / GKC;
+    const int np = phi - plo + 1, wc = M::window_chunks(t, nchunks);
     const int nsteps = np * nchunks;
     // prefetch cursor: window start, window length, pair, chunk in window
     int f_c0 = 0, f_wl = nchunks < wc ? nchunks : wc, f_pi = 0, f_ci = 0;
@@ -429,7 +475,7 @@ __global__ __launch_bounds__(GNT, 1) void split_gemm(int64_t m, int64_t n, int64
     };
     int issued = 0;
 #pragma unroll
-    for (int x = 0; x < GNST - 1; ++x) {
+    for (int x = 0; x < NST - 1; ++x) {
       if (issued < nsteps) {
         issue(plo + f_pi, t - plo - f_pi, f_c0 + f_ci, x);
         fadv();
@@ -437,216 +483,141 @@ __global__ __launch_bounds__(GNT, 1) void split_gemm(int64_t m, int64_t n, int64
       }
     }
     if (issued >= 2)
-      wait_vm_barrier<GLD>();  // step 0 has landed, step 1 may be in flight
+      wait_vm_barrier<T::LD>();  // step 0 has landed, step 1 may be in flight
     else
       wait_vm_barrier<0>();
-    int32_t U[2][2][16];  // exact: |U_t| < 8192 * 10 * 2^14 < 2^31 for K panels of at most 8192
+    // exact: |U_t| < 8192 * 10 * 2^14 < 2^31 for K panels of at most 8192
+    int32_t U[M::kWindows ? FI : 1][M::kWindows ? FJ : 1][16];
+    if constexpr (M::kWindows) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FJ; ++j)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) U[i][j][v] = 0;
+          for (int v = 0; v < 16; ++v) U[i][j][v] = 0;
+    }
+    typename M::acc acc[FI][FJ];
     int stage = 0, st = 0;
     for (int c0 = 0; c0 < nchunks; c0 += wc) {
       const int wl = (nchunks - c0) < wc ? (nchunks - c0) : wc;
       const int wsteps = np * wl;
-      f32x16 acc[2][2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FJ; ++j)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+          for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
       for (int x = 0; x < wsteps; ++x, ++st) {
         const bool more = issued < nsteps;
-        if (more) {  // two steps ahead, into the stage every wave left at the last barrier
-          issue(plo + f_pi, t - plo - f_pi, f_c0 + f_ci, stage == 0 ? GNST - 1 : stage - 1);
+        if (more) {  // NST - 1 steps ahead, into the stage every wave left at the last barrier
+          issue(plo + f_pi, t - plo - f_pi, f_c0 + f_ci, stage == 0 ? NST - 1 : stage - 1);
           fadv();
           ++issued;
         }
-        const unsigned char* As = lds + stage * GSTAGE;
-        const unsigned char* Bs = As + GA;
-        bf16x8 a0[2], b0[2], a1[2], b1[2];
+        const unsigned char* As = lds + stage * T::STAGE;
+        const unsigned char* Bs = As + T::A;
+        frag a0[FI], b0[FJ], a1[FI], b1[FJ];
         frags(As, Bs, 0, a0, b0);
 #pragma unroll
-        for (int kk = 0; kk < GKC / 16; ++kk) {
-          // fragments of the next k16 step are read while this one multiplies
+        for (int kk = 0; kk < GKK; ++kk) {
+          // fragments of the next instruction's k range are read while this one multiplies
           if (kk % 2 == 0) {
-            if (kk + 1 < GKC / 16) frags(As, Bs, kk + 1, a1, b1);
+            if (kk + 1 < GKK) frags(As, Bs, kk + 1, a1, b1);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < FI; ++i)
 #pragma unroll
-              for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0[i], b0[j], acc[i][j], 0, 0, 0);
+              for (int j = 0; j < FJ; ++j) acc[i][j] = M::mfma(a0[i], b0[j], acc[i][j]);
           } else {
-            if (kk + 1 < GKC / 16) frags(As, Bs, kk + 1, a0, b0);
+            if (kk + 1 < GKK) frags(As, Bs, kk + 1, a0, b0);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < FI; ++i)
 #pragma unroll
-              for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1[i], b1[j], acc[i][j], 0, 0, 0);
+              for (int j = 0; j < FJ; ++j) acc[i][j] = M::mfma(a1[i], b1[j], acc[i][j]);
           }
         }
-        // the next step has landed (the one after it may still be in flight),
-        // and every wave is done with this step's stage
+        // the next step has landed (with three stages the one after it may
+        // still be in flight), and every wave is done with this step's stage
         if (issued - (st + 2) >= 1)
-          wait_vm_barrier<GLD>();
+          wait_vm_barrier<T::LD>();
         else
           wait_vm_barrier<0>();
-        stage = stage == GNST - 1 ? 0 : stage + 1;
+        stage = stage == NST - 1 ? 0 : stage + 1;
       }
-      // fold the window's FP32 sums into the int32 weight sums (exact)
+      if constexpr (M::kWindows) {  // fold the window's FP32 sums into the int32 weight sums (exact)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < FJ; ++j)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) U[i][j][v] += (int32_t)acc[i][j][v];
+            for (int v = 0; v < 16; ++v) U[i][j][v] += (int32_t)acc[i][j][v];
+      }
     }
-    // the weight's sums through LDS (every stage is idle), then the FP64 slice-sum update
+    // the weight's sums through LDS (every stage is idle), a part of the tile
+    // at a time, then the FP64 slice-sum update of that part
     int32_t* Ul = reinterpret_cast<int32_t*>(lds);
+    constexpr int HR = GBM / T::HALVES;  // tile rows per pass
+#pragma unroll 1
+    for (int h = 0; h < T::HALVES; ++h) {
+      if (wm * (GBM / T::WM) / HR == h) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < FJ; ++j)
 #pragma unroll
-        for (int v = 0; v < 16; ++v)
-          Ul[(wm * 64 + 32 * i + 8 * (v >> 2) + 4 * fh + (v & 3)) * GBN + wn * 64 + 32 * j + fr] = U[i][j][v];
-    wait_vm_barrier<0>();
-    slice_sum_update<GBM, GBN, GNT>(Ul, eas, fbs, t, s, 8, tid, m0, n0, m, n, npad, Sws, alpha, beta, C, ldc, gamma,
-                                    D, ldd);
-    wait_vm_barrier<0>();  // LDS is staging space again
+            for (int v = 0; v < 16; ++v) {
+              const int r = wm * (GBM / T::WM) - h * HR + 32 * i + 8 * (v >> 2) + 4 * fh + (v & 3);
+              const int c = wn * (TBN / T::WN) + 32 * j + fr;
+              if constexpr (M::kWindows)
+                Ul[r * TBN + c] = U[i][j][v];
+              else
+                Ul[r * TBN + c] = acc[i][j][v];
+            }
+      }
+      wait_vm_barrier<0>();
+      slice_sum_update<HR, TBN, GNT>(Ul, eas + h * HR, fbs, t, s, SliceFmt<EB>::kBits, tid, m0 + h * HR, n0, m, n,
+                                     npad, Sws, alpha, beta, C, ldc, gamma, D, ldd);
+      wait_vm_barrier<0>();  // LDS is staging space again
+    }
   }
 }
 
-// INT8 slice products on V_MFMA_I32_32X32X32_I8 (lane l supplies A[l%32][16*(l/32) .. +16]
-// and B[16*(l/32) .. +16][l%32]; accumulator layout as for the BF16 form).
-// 128 x 128 tiles of 4 waves (64 x 64 each), two workgroups per CU, 128-k
-// chunks (128 bytes per row) staged in LDS through registers, double-buffered,
-// and tiles dealt to the XCDs in bands (xcd_band_tile).  A product of two INT8 slices is
-// below 2^14 and the INT32 accumulation is exact, so no windows: one weight's
-// sum over every pair and the whole K panel (at most 8192 k:
-// |U_t| < 8 * 8192 * 2^14 = 2^30) stays in the accumulators.
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-typedef int i32x16 __attribute__((ext_vector_type(16)));
-constexpr int SKC8 = 128;  // k per chunk (INT8)
+// BF16 slices, 256 x 128 tiles.
+__global__ __launch_bounds__(GNT, 1) void split_gemm(int64_t m, int64_t n, int64_t kpad, int s,
+                                                     const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
+                                                     int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
+                                                     const int32_t* __restrict__ fb, double* __restrict__ Sws,
+                                                     double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                                     double gamma, const double* __restrict__ D, int64_t ldd) {
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[SliceTile<128>::NST * SliceTile<128>::STAGE];
+  __shared__ int32_t eas[GBM], fbs[128];
+  split_gemm_body<2, 128>(m, n, kpad, s, Ap, Bp, mpad, npad, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd, lds,
+                          eas, fbs);
+}
 
-__global__ __launch_bounds__(256, 2) void split_gemm_i8(int64_t m, int64_t n, int64_t kpad, int s,
+// INT8 slices, 256 x 128 tiles.
+__global__ __launch_bounds__(GNT, 1) void split_gemm_i8(int64_t m, int64_t n, int64_t kpad, int s,
                                                         const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
                                                         int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
                                                         const int32_t* __restrict__ fb, double* __restrict__ Sws,
                                                         double alpha, double beta, double* __restrict__ C, int64_t ldc,
                                                         double gamma, const double* __restrict__ D, int64_t ldd) {
-  constexpr int LD = SKC8 + 2 * SPAD;  // bytes per LDS row: the BF16 kernel's 64 + 8 elements
-  __shared__ __attribute__((aligned(16))) union {
-    struct {
-      uint8_t A[2][SBM][LD];
-      uint8_t B[2][SBN][LD];
-    } st;
-    int32_t U[SBM * SBN];
-  } sm;
-  static_assert(sizeof(int32_t) * SBM * SBN <= 2 * (SBM + SBN) * LD, "fold buffer");
-  auto& As = sm.st.A;
-  auto& Bs = sm.st.B;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;
-  int tm, tn;
-  xcd_band_tile((int)blockIdx.x, (int)(mpad / SBM), (int)(npad / SBN), kBandRows, &tm, &tn);
-  const int64_t m0 = (int64_t)tm * SBM, n0 = (int64_t)tn * SBN;
-  // each thread moves 64 bytes of A and of B per chunk: a 32-byte quarter lq of rows lr and lr + 64
-  const int lr = tid >> 2, lq = (tid & 3) * 32;
-  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-  const int nchunks = (int)(kpad / SKC8);
-  auto gload = [&](int p, int q, int cc) {
-    const uint8_t* pa = Ap + ((int64_t)(p - 1) * mpad + m0) * kpad + (int64_t)cc * SKC8 + lq;
-    const uint8_t* pb = Bp + ((int64_t)(q - 1) * npad + n0) * kpad + (int64_t)cc * SKC8 + lq;
-    const uint4* a0 = reinterpret_cast<const uint4*>(pa + (int64_t)lr * kpad);
-    const uint4* a1 = reinterpret_cast<const uint4*>(pa + (int64_t)(lr + 64) * kpad);
-    const uint4* b0 = reinterpret_cast<const uint4*>(pb + (int64_t)lr * kpad);
-    const uint4* b1 = reinterpret_cast<const uint4*>(pb + (int64_t)(lr + 64) * kpad);
-    ra0 = a0[0]; ra1 = a0[1]; ra2 = a1[0]; ra3 = a1[1];
-    rb0 = b0[0]; rb1 = b0[1]; rb2 = b1[0]; rb3 = b1[1];
-  };
-  auto lstore = [&](int buf) {
-    *reinterpret_cast<uint4*>(&As[buf][lr][lq]) = ra0;
-    *reinterpret_cast<uint4*>(&As[buf][lr][lq + 16]) = ra1;
-    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq]) = ra2;
-    *reinterpret_cast<uint4*>(&As[buf][lr + 64][lq + 16]) = ra3;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq]) = rb0;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr][lq + 16]) = rb1;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq]) = rb2;
-    *reinterpret_cast<uint4*>(&Bs[buf][lr + 64][lq + 16]) = rb3;
-  };
-  const int fr = lane & 31, fk = 16 * (lane >> 5);
-  auto plo_of = [&](int t) { return t - s > 1 ? t - s : 1; };
-  {
-    const int t0 = s + 1;
-    gload(plo_of(t0), t0 - plo_of(t0), 0);
-    lstore(0);
-    __syncthreads();
-  }
-  for (int t = s + 1; t >= 2; --t) {
-    const int plo = plo_of(t), phi = t - 1 < s ? t - 1 : s;
-    const int np = phi - plo + 1;
-    i32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
-    // steps: the pairs (p, t-p) in turn, each over every chunk; the next step
-    // is prefetched into registers while this one multiplies
-    const int nsteps = np * nchunks;
-    int pi = 0, ci = 0;
-    for (int st = 0; st < nsteps; ++st) {
-      const int buf = st & 1;
-      int npi = pi, nci = ci + 1;
-      if (nci == nchunks) {
-        nci = 0;
-        ++npi;
-      }
-      const bool more = st + 1 < nsteps;
-      if (more) gload(plo + npi, t - (plo + npi), nci);
-#pragma unroll
-      for (int kk = 0; kk < SKC8; kk += 32) {
-        i32x4 a[2], b[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const i32x4*>(&As[buf][wm * 64 + i * 32 + fr][kk + fk]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const i32x4*>(&Bs[buf][wn * 64 + j * 32 + fr][kk + fk]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], b[j], acc[i][j], 0, 0, 0);
-      }
-      if (more) lstore(buf ^ 1);
-      __syncthreads();
-      pi = npi;
-      ci = nci;
-    }
-    // prefetch the next weight's first step while the slice sums are added
-    if (t > 2) gload(plo_of(t - 1), (t - 1) - plo_of(t - 1), 0);
-    int32_t* Ul = sm.U;  // [SBM][SBN]
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int v = 0; v < 16; ++v)
-          Ul[(wm * 64 + i * 32 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4)) * SBN + wn * 64 + j * 32 + (lane & 31)] =
-              acc[i][j][v];
-    __syncthreads();
-    slice_sum_update<SBM, SBN, 256>(Ul, ea + m0, fb + n0, t, s, 7, tid, m0, n0, m, n, npad, Sws, alpha, beta, C, ldc,
-                                    gamma, D, ldd);
-    __syncthreads();  // LDS is staging space again
-    if (t > 2) {
-      lstore(0);
-      __syncthreads();
-    }
-  }
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[SliceTile<128>::NST * SliceTile<128>::STAGE];
+  __shared__ int32_t eas[GBM], fbs[128];
+  split_gemm_body<1, 128>(m, n, kpad, s, Ap, Bp, mpad, npad, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd, lds,
+                          eas, fbs);
+}
+
+// INT8 slices, 256 x 256 tiles.
+__global__ __launch_bounds__(GNT, 1) void split_gemm_i8w(int64_t m, int64_t n, int64_t kpad, int s,
+                                                         const uint8_t* __restrict__ Ap, const uint8_t* __restrict__ Bp,
+                                                         int64_t mpad, int64_t npad, const int32_t* __restrict__ ea,
+                                                         const int32_t* __restrict__ fb, double* __restrict__ Sws,
+                                                         double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                                         double gamma, const double* __restrict__ D, int64_t ldd) {
+  __shared__ __attribute__((aligned(1024))) unsigned char lds[SliceTile<256>::NST * SliceTile<256>::STAGE];
+  __shared__ int32_t eas[GBM], fbs[256];
+  split_gemm_body<1, 256>(m, n, kpad, s, Ap, Bp, mpad, npad, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd, lds,
+                          eas, fbs);
 }
 
 inline int64_t pad64(int64_t x) { return (x + 63) / 64 * 64; }
@@ -657,14 +628,29 @@ inline int64_t pad256(int64_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace: A planes [s][mp][kp], B planes [s][np][kp] (BF16 or INT8),
 // row and column exponents (int32), column maxima (uint64), slice-sum tile
-// [mp][np] (FP64), with mp = m rounded up to the slice-product kernel's tile
-// rows (256 BF16, 128 INT8), np = n rounded up to 128 and kp = k rounded up
-// to a whole number of 128-byte chunks (64 BF16 or 128 INT8 elements).
+// [mp][np] (FP64), with mp = m rounded up to the slice-product kernel's 256
+// tile rows, np = n rounded up to its tile columns (128 BF16; 128 or 256
+// INT8, room for 256) and kp = k rounded up to a whole number of 128-byte
+// chunks (64 BF16 or 128 INT8 elements).
 static int64_t pad_k(int64_t k, SliceFormat f) { return f == kSliceInt8 ? pad128(k) : pad64(k); }
-static int64_t pad_m(int64_t m, SliceFormat f) { return f == kSliceInt8 ? pad128(m) : pad256(m); }
+static int64_t pad_m(int64_t m) { return pad256(m); }
+
+// A 256 x 256 INT8 tile moves half the plane bytes per product of a 256 x 128
+// one and runs at 1.17 times its rate (8192^3 launches: 1986 against 1702
+// TOP/s), so it takes about 1.71 times as long; the wide tiles are used when
+// their waves over the CUs (one tile per CU at a time) end sooner.
+constexpr double kWideTileTime = 1.71;
+
+bool split_i8_wide(int64_t m, int64_t n, int cus) {
+  const double rows = (double)(pad256(m) / 256);
+  const double narrow = std::ceil(rows * (double)(pad128(n) / 128) / cus);
+  const double wide = std::ceil(rows * (double)(pad256(n) / 256) / cus) * kWideTileTime;
+  return wide < narrow;
+}
 
 size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat f) {
-  const int64_t mp = pad_m(m, f), np = pad128(n), kp = pad_k(k < kSplitMaxK ? k : kSplitMaxK, f);
+  const int64_t mp = pad_m(m), np = f == kSliceInt8 ? pad256(n) : pad128(n);
+  const int64_t kp = pad_k(k < kSplitMaxK ? k : kSplitMaxK, f);
   return (size_t)((int64_t)f * s * (mp + np) * kp + 4 * (mp + np) + 8 * np + 8 * mp * np);
 }
 
@@ -701,7 +687,12 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
   if (m <= 0 || n <= 0) return hipSuccess;
   if (s < 1 || s > 8) return hipErrorInvalidValue;
   if (k <= 0) return launch_dgemm_f64(m, n, 0, alpha, nullptr, 1, nullptr, 1, beta, C, ldc, gamma, D, ldd, stream);
-  const int64_t mp = pad_m(m, f), np = pad128(n), kp = pad_k(k, f);
+  int dev = 0, cus = 0;
+  hipError_t qe = hipGetDevice(&dev);
+  if (qe == hipSuccess) qe = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (qe != hipSuccess) return qe;
+  const bool wide = f == kSliceInt8 && split_i8_wide(m, n, cus);
+  const int64_t mp = pad_m(m), np = wide ? pad256(n) : pad128(n), kp = pad_k(k, f);
   if (split_workspace_bytes(m, n, k, s, f) > ws_bytes) return hipErrorInvalidValue;
   const int eb = (int)f;
   uint8_t* Ap = static_cast<uint8_t*>(workspace);
@@ -760,18 +751,21 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
     with_s(slice_b);
   }
   // one-dimensional grids: the kernels map workgroups to tiles in XCD bands
-  const dim3 grid8((unsigned)((np / SBN) * (mp / SBM))), grid16((unsigned)((np / GBN) * (mp / GBM)));
+  const dim3 grid((unsigned)((np / (wide ? 256 : 128)) * (mp / GBM)));
   const bool timed = timer && timer->used < timer->count;
   if (timed) {
     const hipError_t e = hipEventRecord(timer->events[2 * timer->used], stream);
     if (e != hipSuccess) return e;
   }
-  if (f == kSliceInt8)
-    hipLaunchKernelGGL(split_gemm_i8, grid8, dim3(256), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
+  if (wide)
+    hipLaunchKernelGGL(split_gemm_i8w, grid, dim3(GNT), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
+                       beta, C, ldc, gamma, D, ldd);
+  else if (f == kSliceInt8)
+    hipLaunchKernelGGL(split_gemm_i8, grid, dim3(GNT), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha,
                        beta, C, ldc, gamma, D, ldd);
   else
-    hipLaunchKernelGGL(split_gemm, grid16, dim3(GNT), 0, stream, m, n, kp, s, reinterpret_cast<const uint16_t*>(Ap),
-                       reinterpret_cast<const uint16_t*>(Bp), mp, np, ea, fb, Sws, alpha, beta, C, ldc, gamma, D, ldd);
+    hipLaunchKernelGGL(split_gemm, grid, dim3(GNT), 0, stream, m, n, kp, s, Ap, Bp, mp, np, ea, fb, Sws, alpha, beta,
+                       C, ldc, gamma, D, ldd);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (timed) {

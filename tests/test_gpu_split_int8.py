@@ -63,6 +63,24 @@ def test_int8_kernel_bit_exact_vs_split_reference(case):
         gate_errors(got, ref, alpha, D, beta, C0)
 
 
+@pytest.mark.parametrize("shape", [(3900, 4000, 700, 6), (4096, 4096, 9000, 7)])
+def test_int8_wide_tiles_bit_exact_on_sampled_rows(shape):
+    # 3900 x 4000 and 4096^2 make 512 tiles of 256 x 128 (two waves on the
+    # 256 CUs of an MI355X) against 256 of 256 x 256 (one wave), so the
+    # kernel takes the wide tiles; ragged edges in M and N, and a second K
+    # panel in the second shape.  The split reference's row exponents are per
+    # row, so its result on the sampled rows is those rows of the whole one.
+    m, n, k, s = shape
+    _say(f"split-int8 wide tiles {shape}")
+    A = np.ascontiguousarray(synth.matrix(m, k, synth.spec(330, 0, synth.NORMAL, row_exp=(-10, 10))))
+    B = np.ascontiguousarray(synth.matrix(k, n, synth.spec(330, 1, synth.NORMAL, col_exp=(-10, 10))))
+    C0 = np.ascontiguousarray(synth.matrix(m, n, synth.spec(330, 2, synth.UNIFORM)))
+    got = _device_split_i8(A, B, C0, 1.25, 0.5, s)
+    rows = np.unique(np.concatenate([[0, 255, 256, m - 1], np.random.default_rng(7).integers(0, m, 60)]))
+    want = split_ref.split_gemm(1.25, A[rows], B, 0.5, C0[rows], s, kb=8192 if k > 8192 else None, fmt="i8")
+    assert np.array_equal(got[rows], want), np.max(np.abs(got[rows] - want))
+
+
 def test_int8_largest_digits_and_weight_sums():
     # x = 1 - 2^-53: the first seven digits are 127 (the INT8 maximum) and the
     # eighth 120; with s = 8 and 8192 k every weight's INT32 sum over all its
