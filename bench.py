@@ -9,7 +9,10 @@ The reported value is end-to-end TFLOP/s, 2*M*N*K / t with t including all
 transfers (the paper's measure, Section VI).
 
 Prints ONE JSON line.  Default workload: M = N = K = 32768 (8 GiB per matrix),
-alpha = 1.5, beta = 0.5, entries uniform[-1, 1], device budget 4 GiB.
+alpha = 1.5, beta = 0.5, entries uniform[-1, 1], device budget 4 GiB.  Beside
+the FP64 figures the line carries two split legs on the same operands, the
+split-BF16 form and the split-INT8 form, each with the smallest slice count
+whose result meets the 1e-12 gate on the oracle's sampled rows.
 """
 import argparse
 import json
