@@ -18,6 +18,14 @@ syrk_lower(alpha, A, beta, C) -> C'
                             the strict upper triangle of C is returned
                             unchanged; with beta == 0 C's lower triangle is not
                             read.
+trsm_rlt(L, X) -> Y         Y with Y L^T = X for lower-triangular L (n x n,
+                            nonzero diagonal) and X (m x n): column by column
+                            (forward substitution on every row at once),
+                              y_j = (x_j - sum_{k<j} y_k l_jk) / l_jj.
+                            Only the lower triangle of L is read.
+trsm_bound(L, Y)            the elementwise bound gamma_n |Y| |L|^T on
+                            |X - Y L^T| that forward substitution computed in
+                            floating point satisfies (Higham, Theorem 8.5).
 backward_bound(L)           the elementwise bound gamma_{n+1} (|L| |L|^T) on
                             |A - L L^T| that a Cholesky factorisation computed
                             in floating point with any summation order satisfies
@@ -62,6 +70,24 @@ def syrk_lower(alpha, A, beta, C):
     else:
         C[low] = alpha * S[low] + beta * C[low]
     return C
+
+
+def trsm_rlt(L, X):
+    L = np.asarray(L, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    n = L.shape[0]
+    assert L.shape == (n, n) and X.shape[1] == n
+    Y = np.zeros_like(X)
+    for j in range(n):
+        Y[:, j] = (X[:, j] - Y[:, :j] @ L[j, :j]) / L[j, j]
+    return Y
+
+
+def trsm_bound(L, Y):
+    """gamma_n |Y| |L|^T, gamma_n = n u / (1 - n u)."""
+    n = L.shape[0]
+    gamma = n * U_FP64 / (1.0 - n * U_FP64)
+    return gamma * (np.abs(Y) @ np.abs(np.tril(L)).T)
 
 
 def backward_bound(L):

@@ -115,3 +115,49 @@ def test_factor_of_syrk_result():
     A = chol_ref.syrk_lower(1.0, L, 0.0, np.zeros((17, 17)))
     A = np.tril(A) + np.tril(A, -1).T
     assert np.array_equal(chol_ref.potrf_lower(A), L)
+
+
+# ---- triangular solve Y L^T = X (trsm_rlt) ---------------------------------------------
+
+@pytest.mark.parametrize("m,n,seed", [(1, 1, 0), (5, 3, 1), (40, 17, 2), (7, 90, 3)])
+def test_trsm_integer_solution_recovered_exactly(m, n, seed):
+    # X = Y L^T with integer Y and an integer L whose diagonal divides every
+    # numerator exactly: every step of forward substitution is an exact integer
+    L = _int_factor(n, seed + 20, dmax=5)
+    Y = np.random.default_rng(seed).integers(-9, 10, (m, n)).astype(np.float64)
+    X = Y @ L.T
+    assert np.array_equal(chol_ref.trsm_rlt(L, X), Y)
+
+
+def test_trsm_identity_diagonal_and_upper_not_read():
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((6, 4))
+    assert np.array_equal(chol_ref.trsm_rlt(np.eye(4), X), X)
+    d = np.array([2.0, -0.5, 4.0, 8.0])
+    assert np.array_equal(chol_ref.trsm_rlt(np.diag(d), X), X / d)
+    L = np.tril(rng.standard_normal((4, 4))) + 4 * np.eye(4)
+    Lu = L + np.triu(np.full((4, 4), np.nan), 1)
+    assert np.array_equal(chol_ref.trsm_rlt(Lu, X), chol_ref.trsm_rlt(L, X))
+
+
+def test_trsm_two_by_two_by_hand():
+    # y1 = x1 / 2; y2 = (x2 - 3 y1) / 4
+    L = np.array([[2.0, 0.0], [3.0, 4.0]])
+    X = np.array([[4.0, 10.0], [-2.0, 1.0]])
+    assert np.array_equal(chol_ref.trsm_rlt(L, X), np.array([[2.0, 1.0], [-1.0, 1.0]]))
+
+
+def test_trsm_against_library_solve_and_backward_bound():
+    rng = np.random.default_rng(9)
+    n, m = 60, 25
+    L = np.tril(rng.standard_normal((n, n))) + n ** 0.5 * np.eye(n)
+    X = rng.standard_normal((m, n))
+    Y = chol_ref.trsm_rlt(L, X)
+    # Y L^T = X is L Y^T = X^T: a lower-triangular system per row of X
+    np.testing.assert_allclose(Y, np.linalg.solve(L, X.T).T, rtol=1e-12, atol=1e-13)
+    R = np.abs(X - Y @ L.T)
+    assert np.all(R <= 2.0 * chol_ref.trsm_bound(L, Y))
+    # and the bound is not vacuous: a perturbed solution fails it
+    Yb = Y.copy()
+    Yb[3, 7] += 1e-9
+    assert not np.all(np.abs(X - Yb @ L.T) <= 2.0 * chol_ref.trsm_bound(L, Yb))
