@@ -119,23 +119,32 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
         for (int e = 0; e < VB; ++e) rb[e] = pb[e];
       }
     } else {
+      // edge tiles: every load reads an address inside the operand (row and
+      // k clamped) and the value is then selected, so that no load waits for
+      // the one before it
+      const int64_t arc = arow < M ? arow : M - 1;
 #pragma unroll
       for (int e = 0; e < VA; ++e) {
         const int64_t kk = k0 + ak + e;
-        ra[e] = (arow < M && kk < K) ? A[arow * lda + kk] : 0.0;
+        const double v = A[arc * lda + (kk < K ? kk : K - 1)];
+        ra[e] = (arow < M && kk < K) ? v : 0.0;
       }
       if (TB) {
         const int64_t nn = n0 + btn;
+        const int64_t nnc = nn < N ? nn : N - 1;
 #pragma unroll
         for (int e = 0; e < VB; ++e) {
           const int64_t kk = k0 + btk + e;
-          rb[e] = (nn < N && kk < K) ? B[nn * ldb + kk] : 0.0;
+          const double v = B[nnc * ldb + (kk < K ? kk : K - 1)];
+          rb[e] = (nn < N && kk < K) ? v : 0.0;
         }
       } else {
+        const int64_t brc = brow < K ? brow : K - 1;
 #pragma unroll
         for (int e = 0; e < VB; ++e) {
           const int64_t nn = n0 + bn + e;
-          rb[e] = (brow < K && nn < N) ? B[brow * ldb + nn] : 0.0;
+          const double v = B[brc * ldb + (nn < N ? nn : N - 1)];
+          rb[e] = (brow < K && nn < N) ? v : 0.0;
         }
       }
     }
@@ -213,21 +222,46 @@ __global__ __launch_bounds__(64 * WM * WN, MINBLOCKS) void kernel(
   }
 
   // ---- epilogue: C = alpha*acc + beta*C + gamma*D (C, D not read when their weight is 0)
+  // One row of MFMA blocks at a time: its C (and D) values are loaded first,
+  // from addresses clamped into the matrices, so that the loads are in flight
+  // together; then the results are formed, then stored, limited to the
+  // tile's part of C (and, with a triangle mask, to row - col >= tri).  No
+  // load or result follows a store within a row of blocks, so the stores
+  // wait for nothing.
 #pragma unroll
   for (int i = 0; i < FM; ++i) {
+    double cv[FN][4], dv[FN][4];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int64_t col = n0 + bn0 + j * 16 + lrow;
+      const int64_t cc = col < N ? col : N - 1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + am0 + i * 16 + lk + 4 * v;
+        const int64_t rc = row < M ? row : M - 1;
+        if (beta != 0.0) cv[j][v] = C[rc * ldc + cc];
+        if (gamma != 0.0) dv[j][v] = D[rc * ldd + cc];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double val = alpha * acc[i][j][v];
+        if (beta != 0.0) val += beta * cv[j][v];
+        if (gamma != 0.0) val += gamma * dv[j][v];
+        // formed here, before any store (the compiler would otherwise sink
+        // it into the conditional store, behind a wait for the last store)
+        asm volatile("" : "+v"(val));
+        acc[i][j][v] = val;
+      }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       const int64_t col = n0 + bn0 + j * 16 + lrow;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + am0 + i * 16 + lk + 4 * v;
-        if (row < M && col < N && row - col >= tri) {
-          double* pc = C + row * ldc + col;
-          double val = alpha * acc[i][j][v];
-          if (beta != 0.0) val += beta * *pc;
-          if (gamma != 0.0) val += gamma * D[row * ldd + col];
-          *pc = val;
-        }
+        if (row < M && col < N && row - col >= tri) C[row * ldc + col] = acc[i][j][v];
       }
     }
   }

@@ -89,6 +89,8 @@ class HipRuntime:
         self.lib.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
         self.lib.hipMemGetInfo.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         self.lib.hipSetDevice.argtypes = [ctypes.c_int]
+        self.lib.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+        self.lib.hipFree.argtypes = [ctypes.c_void_p]
 
     def _check(self, rc, what):
         if rc != 0:
@@ -108,6 +110,27 @@ class HipRuntime:
 
     def stream_synchronize(self, s):
         self._check(self.lib.hipStreamSynchronize(s), "hipStreamSynchronize")
+
+    def device_synchronize(self):
+        self._check(self.lib.hipDeviceSynchronize(), "hipDeviceSynchronize")
+
+    def malloc(self, nbytes):
+        p = self._ct.c_void_p()
+        self._check(self.lib.hipMalloc(self._ct.byref(p), nbytes), "hipMalloc")
+        return p.value
+
+    def free(self, p):
+        self._check(self.lib.hipFree(p), "hipFree")
+
+    def free_shows_release(self, nbytes):
+        """Whether the runtime's free-memory reading rises again when a block of
+        nbytes from hipMalloc is freed (the runtime may keep freed blocks)."""
+        p = self.malloc(nbytes)
+        self.device_synchronize()
+        low = self.mem_free()
+        self.free(p)
+        self.device_synchronize()
+        return self.mem_free() - low >= nbytes // 2
 
     def mem_free(self):
         fr, tot = self._ct.c_size_t(), self._ct.c_size_t()

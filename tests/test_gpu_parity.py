@@ -271,8 +271,10 @@ def test_borrowed_streams_arena_release_and_stats():
         streams = [hip.stream_create() for _ in range(3)]
         plan = ooc.make_plan(512, 1024, 2048, ooc.ORDER_COLS, 2, 2, 2, 3)
         opts = ooc.make_opts(streams=streams, profile=True)
+        hip.device_synchronize()
         free0 = hip.mem_free()
         _, stats = ooc.ooc_gemm_planned(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, plan, opts)
+        hip.device_synchronize()
         free_cached = hip.mem_free()
         _say(f"borrowed streams: overlap {stats.overlap:.3f} t_plan {stats.t_plan_s * 1e3:.3f} ms "
              f"t_total {stats.t_total_s * 1e3:.2f} ms arena {stats.arena_bytes}")
@@ -283,9 +285,17 @@ def test_borrowed_streams_arena_release_and_stats():
         synth.fill(pp.C, w.spec_c())
         opts = ooc.make_opts(streams=streams, release_arena=True)
         _, stats = ooc.ooc_gemm_planned(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, plan, opts)
+        hip.device_synchronize()
         free_released = hip.mem_free()
+        _say(f"free device memory: before {free0}, arena cached {free_cached}, arena released {free_released}")
         check_rows(w, pp, np.arange(w.M))
-        assert free_released - free_cached >= 0.5 * stats.arena_bytes
+        # the arena went back to the runtime; its free-memory reading shows that
+        # only if the runtime hands freed blocks back at once, which a direct
+        # hipMalloc / hipFree of the same size tells
+        if hip.free_shows_release(stats.arena_bytes):
+            assert free_released - free_cached >= 0.5 * stats.arena_bytes
+        else:
+            _say("the runtime keeps freed blocks: its free-memory reading cannot show the release")
         assert stats.overlap == 0.0  # not profiled
         for s in streams:
             hip.stream_synchronize(s)
