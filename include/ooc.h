@@ -366,6 +366,22 @@ ooc_status ooc_syrk(int64_t N, int64_t K, double alpha, const double* A, int64_t
 ooc_status ooc_potrf(int64_t N, double* A, int64_t lda, size_t budget_bytes, const ooc_opts* opts, int64_t* info,
                      ooc_stats* stats);
 
+/* Triangular solve Y L^T = X out of core: X (M x N, row-major, ldx >= N,
+ * page-locked) is overwritten by Y = X L^{-T} for the lower-triangular N x N
+ * matrix L (row-major, ldl >= N, page-locked; only its lower triangle is
+ * read, its diagonal must be nonzero: a zero divides into Inf or NaN).  In
+ * column-major terms this is the forward substitution L Y' = X' for the
+ * columns of X' = X^T, the solve with the factor of ooc_potrf.  Left-looking
+ * by block columns of b columns (the panel rule of ooc_potrf): the update of
+ * a block column of X by the solved columns to its left is one out-of-core
+ * product (ooc_gemm_ex with a transposed B), then the block column is solved
+ * against L's diagonal block on the device, chunk by chunk (TRSM ops on the
+ * executor).  Every quotient is a true division: integer data with an
+ * integer solution gets it exactly.  FP64 whatever opts->precision says.
+ * stats: totals (flops = M N^2, bytes, times; blocks_done = block columns). */
+ooc_status ooc_trsm(int64_t M, int64_t N, const double* L, int64_t ldl, double* X, int64_t ldx, size_t budget_bytes,
+                    const ooc_opts* opts, ooc_stats* stats);
+
 /* ---- accumulation sessions: repeated invocation ----------------------------------
  * The paper's MMOOC can serve as the local step of an outer algorithm (SUMMA or
  * HSUMMA, Section V: the step/nsteps logic of Fig. 2): over steps s = 0..S-1

@@ -112,6 +112,7 @@ _sig("ooc_schedule", i32, [i64, i64, i64, dbl, dbl, P(ooc_plan_t), P(ooc_op), i6
 _sig("ooc_schedule_ex", i32, [i32, i32, i64, i64, i64, dbl, dbl, P(ooc_plan_t), P(ooc_op), i64, P(i64), P(u64)])
 _sig("ooc_syrk", i32, [i64, i64, dbl, vp, i64, dbl, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
 _sig("ooc_potrf", i32, [i64, vp, i64, sz, P(ooc_opts), P(i64), P(ooc_stats)])
+_sig("ooc_trsm", i32, [i64, i64, vp, i64, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
 _sig("ooc_run_ops", i32, [P(ooc_op), i64, P(ooc_host_matrix), i32, u64, P(ooc_opts), P(ooc_stats)])
 _sig("ooc_check_ops", i32, [P(ooc_op), i64, P(i64), P(i64)])
 _sig("ooc_gemm_ex", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, sz, P(ooc_opts),
@@ -148,7 +149,7 @@ _sig("ooc_mlp_predict", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P(dbl)
 _sig("ooc_last_error", ctypes.c_char_p, [])
 _sig("ooc_version", ctypes.c_char_p, [])
 
-EXPORTS = ["ooc_gemm", "ooc_gemm_ex", "ooc_schedule_ex", "ooc_syrk", "ooc_potrf", "ooc_run_ops", "ooc_check_ops", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
+EXPORTS = ["ooc_gemm", "ooc_gemm_ex", "ooc_schedule_ex", "ooc_syrk", "ooc_potrf", "ooc_trsm", "ooc_run_ops", "ooc_check_ops", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_device_copy", "ooc_dgemm_device",
            "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_split_gemm_device_noalloc", "ooc_mlp_features", "ooc_mlp_forward",
@@ -269,6 +270,23 @@ def ooc_potrf(A, budget_bytes, opts=None, raise_on_error=True):
     if raise_on_error:
         _check(s)
     return s, info.value, st
+
+
+def ooc_trsm(L, X, budget_bytes, opts=None, raise_on_error=True):
+    """X <- X L^{-T} (Y L^T = X) for lower-triangular L (N x N) and X (M x N), both page-locked;
+    only L's lower triangle is read.  Returns (status, ooc_stats)."""
+    N = L.shape[0]
+    M = X.shape[0]
+    if L.shape[1] != N or X.shape[1] != N:
+        raise ValueError("L must be N x N and X M x N")
+    pl, ldl = _mat_arg(L, "L")
+    px, ldx = _mat_arg(X, "X")
+    st = ooc_stats()
+    s = _lib.ooc_trsm(M, N, pl, ldl, px, ldx, budget_bytes, ctypes.byref(opts) if opts is not None else None,
+                      ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
 
 
 def make_op(kind, stream=0, waits=(), **fields):

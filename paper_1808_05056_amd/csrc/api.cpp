@@ -552,6 +552,42 @@ int64_t potrf_panel(int64_t N, uint64_t budget_elems) {
   return fits(b) ? b : 0;
 }
 
+// Append op `o` with the wait set `waits` (negative entries skipped); returns its index.
+int push_op(std::vector<ooc_op>& ops, ooc_op o, std::initializer_list<int> waits) {
+  o.nwait = 0;
+  for (int w : waits)
+    if (w >= 0) o.wait[o.nwait++] = w;
+  ops.push_back(o);
+  return (int)ops.size() - 1;
+}
+
+// Ops that solve rows [i0, i0 + rows) x columns [j0, j0 + jb) of host matrix
+// `mat` against the lower-triangular jb x jb block at arena offset 0 (X <- X
+// L^{-T}), in chunks of r rows through two arena buffers after `base`
+// elements: H2D on stream 0, TRSM on stream 1 (also after op `after` when it
+// is >= 0), D2H on stream 2; a buffer is refilled only after its last chunk
+// went home.
+void append_chunked_solve(std::vector<ooc_op>& ops, int mat, int64_t i0, int64_t rows, int64_t j0, int64_t jb,
+                          int64_t base, int64_t r, int after) {
+  int home[2] = {-1, -1};
+  for (int64_t q = 0; q * r < rows; ++q) {
+    const int64_t r0 = i0 + q * r, rr = std::min(r, rows - q * r);
+    const int buf = (int)(q & 1);
+    ooc_op o{};
+    o.kind = OOC_OP_H2D; o.stream = 0; o.mat = mat;
+    o.row0 = r0; o.col0 = j0; o.rows = rr; o.cols = jb; o.off_c = base + buf * r * jb; o.ld_c = jb;
+    const int h = push_op(ops, o, {home[buf]});
+    o = ooc_op{};
+    o.kind = OOC_OP_TRSM; o.stream = 1; o.rows = rr; o.cols = jb;
+    o.off_c = base + buf * r * jb; o.ld_c = jb; o.off_a = 0; o.ld_a = jb;
+    const int k = push_op(ops, o, {h, after});
+    o = ooc_op{};
+    o.kind = OOC_OP_D2H; o.stream = 2; o.mat = mat;
+    o.row0 = r0; o.col0 = j0; o.rows = rr; o.cols = jb; o.off_c = base + buf * r * jb; o.ld_c = jb;
+    home[buf] = push_op(ops, o, {k});
+  }
+}
+
 ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, const ooc_opts* opts, int64_t* info,
                       ooc_stats* stats) {
   const double t_enter = now_s();
@@ -592,48 +628,26 @@ ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, co
     const int64_t base = jb * jb + 8;  // chunk buffers after the block and the status word
     const int64_t r = below > 0 ? std::max<int64_t>(1, std::min<int64_t>(below, ((int64_t)(budget_bytes / 8) - base) / (2 * jb))) : 0;
     std::vector<ooc_op> ops;
-    auto push = [&](ooc_op o, std::initializer_list<int> waits) {
-      o.nwait = 0;
-      for (int w : waits)
-        if (w >= 0) o.wait[o.nwait++] = w;
-      ops.push_back(o);
-      return (int)ops.size() - 1;
-    };
     ooc_op o{};
     o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 0;
     o.row0 = j0; o.col0 = j0; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
-    const int h_diag = push(o, {});
+    const int h_diag = push_op(ops, o, {});
     o = ooc_op{};
     o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 1; o.rows = 1; o.cols = 1; o.off_c = jb * jb; o.ld_c = 1;
-    const int h_stat = push(o, {});
+    const int h_stat = push_op(ops, o, {});
     o = ooc_op{};
     o.kind = OOC_OP_POTRF; o.stream = 1; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
     o.off_w = jb * jb; o.len_w = 1; o.k0 = j0;
-    const int k_potrf = push(o, {h_diag, h_stat});
+    const int k_potrf = push_op(ops, o, {h_diag, h_stat});
     o = ooc_op{};
     o.kind = OOC_OP_D2H; o.stream = 2; o.mat = 0;
     o.row0 = j0; o.col0 = j0; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
-    push(o, {k_potrf});
+    push_op(ops, o, {k_potrf});
     o = ooc_op{};
     o.kind = OOC_OP_D2H; o.stream = 2; o.mat = 1; o.rows = 1; o.cols = 1; o.off_c = jb * jb; o.ld_c = 1;
-    push(o, {k_potrf});
-    std::vector<int> home(2, -1);  // last copy home out of each chunk buffer
-    for (int64_t q = 0; q * r < below; ++q) {
-      const int64_t i0 = j0 + jb + q * r, rr = std::min(r, N - i0);
-      const int buf = (int)(q & 1);
-      o = ooc_op{};
-      o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 0;
-      o.row0 = i0; o.col0 = j0; o.rows = rr; o.cols = jb; o.off_c = base + buf * r * jb; o.ld_c = jb;
-      const int h = push(o, {home[buf]});
-      o = ooc_op{};
-      o.kind = OOC_OP_TRSM; o.stream = 1; o.rows = rr; o.cols = jb;
-      o.off_c = base + buf * r * jb; o.ld_c = jb; o.off_a = 0; o.ld_a = jb;
-      const int k = push(o, {h});
-      o = ooc_op{};
-      o.kind = OOC_OP_D2H; o.stream = 2; o.mat = 0;
-      o.row0 = i0; o.col0 = j0; o.rows = rr; o.cols = jb; o.off_c = base + buf * r * jb; o.ld_c = jb;
-      home[buf] = push(o, {k});
-    }
+    push_op(ops, o, {k_potrf});
+    // the solves run on stream 1 after the factorisation
+    append_chunked_solve(ops, 0, j0 + jb, below, j0, jb, base, r, -1);
     *hstat = 0.0;
     ooc_stats ps{};
     HostMats hm{{A, lda}, {hstat, 1}};
@@ -653,6 +667,68 @@ ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, co
   (void)hipHostFree(hstat);
   const double n = (double)N;
   total.flops = n * n * n / 3.0 + n * n / 2.0 + n / 6.0;
+  total.t_total_s = now_s() - t_enter;
+  if (stats) *stats = total;
+  return st;
+}
+
+// Out-of-core triangular solve Y L^T = X (X <- X L^{-T}, the right-hand,
+// lower, transposed form; Y^T = L^{-1} X^T is forward substitution for the
+// columns of X^T), left-looking by block columns of b columns (the panel rule
+// of the factorisation): block column j of X is first updated by the columns
+// to its left, X_j = X_j - Y_left L_j,left^T (one out-of-core product with a
+// transposed B), then solved against the diagonal block L_jj on the device,
+// chunk by chunk.
+ooc_status trsm_impl(int64_t M, int64_t N, const double* L, int64_t ldl, double* X, int64_t ldx, size_t budget_bytes,
+                     const ooc_opts* opts, ooc_stats* stats) {
+  const double t_enter = now_s();
+  ooc_stats total{};
+  if (M < 0 || N < 0) return fail(OOC_ERR_ARG, "negative matrix size");
+  if (M == 0 || N == 0) {
+    if (stats) *stats = total;
+    return OOC_OK;
+  }
+  if (!L || ldl < N || !X || ldx < N) return fail(OOC_ERR_ARG, "bad L, X or leading dimension");
+  const int64_t b = potrf_panel(N, budget_bytes / 8);
+  if (b == 0) return fail(OOC_ERR_BUDGET, "the budget holds no 64-column panel of the solve");
+  const int dev = opts ? opts->device : 0;
+  ooc_status st = ensure_device(dev);
+  if (st != OOC_OK) return st;
+  if (!range_pinned(L, N, N, ldl)) return fail(OOC_ERR_NOT_PINNED, "L is not page-locked host memory");
+  if (!range_pinned(X, M, N, ldx)) return fail(OOC_ERR_NOT_PINNED, "X is not page-locked host memory");
+  ooc_opts gopts{};
+  if (opts) gopts = *opts;
+  gopts.precision = OOC_FP64;
+  gopts.timeline = nullptr;
+  gopts.timeline_cap = 0;
+  for (int64_t j0 = 0; j0 < N && st == OOC_OK; j0 += b) {
+    const int64_t jb = std::min(b, N - j0);
+    if (j0 > 0) {  // X_j = X_j - Y_left L_j,left^T
+      ooc_stats gs{};
+      st = gemm_impl(M, jb, j0, -1.0, X, ldx, L + j0 * ldl, ldl, 1.0, X + j0, ldx, budget_bytes, nullptr, &gopts, &gs,
+                     true, false);
+      add_stats(&total, gs);
+      if (st != OOC_OK) break;
+    }
+    // L_jj in, then the rows of X_j through two chunk buffers
+    const int64_t base = jb * jb;
+    const int64_t r = std::max<int64_t>(1, std::min<int64_t>(M, ((int64_t)(budget_bytes / 8) - base) / (2 * jb)));
+    std::vector<ooc_op> ops;
+    ooc_op o{};
+    o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 1;
+    o.row0 = j0; o.col0 = j0; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
+    const int h_diag = push_op(ops, o, {});
+    append_chunked_solve(ops, 0, 0, M, j0, jb, base, r, h_diag);
+    ooc_stats ps{};
+    HostMats hm{{X, ldx}, {const_cast<double*>(L), ldl}};
+    const uint64_t arena_bytes = (uint64_t)(base + 2 * r * jb) * 8;
+    st = exec_list(dev, ops, hm, arena_bytes, budget_bytes, RunCfg{3, OOC_FP64, 0}, &gopts, &ps);
+    list_stats(ops, &ps);
+    ps.arena_bytes = arena_bytes;
+    add_stats(&total, ps);
+    if (st == OOC_OK) ++total.blocks_done;
+  }
+  total.flops = (double)M * (double)N * (double)N;
   total.t_total_s = now_s() - t_enter;
   if (stats) *stats = total;
   return st;
@@ -818,6 +894,12 @@ ooc_status ooc_potrf(int64_t N, double* A, int64_t lda, size_t budget_bytes, con
                      ooc_stats* stats) {
   if (stats) std::memset(stats, 0, sizeof(*stats));
   return potrf_impl(N, A, lda, budget_bytes, opts, info, stats);
+}
+
+ooc_status ooc_trsm(int64_t M, int64_t N, const double* L, int64_t ldl, double* X, int64_t ldx, size_t budget_bytes,
+                    const ooc_opts* opts, ooc_stats* stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  return trsm_impl(M, N, L, ldl, X, ldx, budget_bytes, opts, stats);
 }
 
 ooc_status ooc_run_ops(const ooc_op* ops, int64_t nops, const ooc_host_matrix* mats, int32_t nmats,

@@ -194,6 +194,92 @@ def test_potrf_large_sampled_rows():
         ooc.ooc_release(-1)
 
 
+# ---- out-of-core triangular solve Y L^T = X -----------------------------------------
+
+@pytest.mark.parametrize("m,n,budget", [(37, 29, 1 * MiB), (700, 500, 2 * MiB), (3000, 200, 1 * MiB),
+                                        (1500, 1300, 3 * MiB)])
+def test_trsm_integer_solution_exact(m, n, budget):
+    # X = Y L^T with integer Y and L: every quotient of the solve is exact, and
+    # L's strict upper triangle (NaN) is never read
+    L = _int_factor(n, n + 1)
+    Y = np.random.default_rng(m).integers(-9, 10, (m, n)).astype(np.float64)
+    X = Y @ L.T
+    Lh = L.copy()
+    Lh[np.triu_indices(n, 1)] = np.nan
+    PL, PX = _pinned(Lh), _pinned(X)
+    try:
+        _, st = ooc.ooc_trsm(PL.array, PX.array, budget)
+        _say(f"trsm m={m} n={n}: panels {st.blocks_done} ops {st.ops} arena {st.arena_bytes} "
+             f"t {st.t_total_s * 1e3:.1f} ms")
+        assert np.array_equal(PX.array, Y)
+        assert st.arena_bytes <= budget
+        assert np.array_equal(np.isnan(PL.array), np.isnan(Lh))  # L left as it was
+    finally:
+        PL.free()
+        PX.free()
+        ooc.ooc_release(-1)
+
+
+def test_trsm_random_against_the_oracle():
+    m, n = 2000, 1500
+    rng = np.random.default_rng(17)
+    L = np.tril(rng.standard_normal((n, n))) + n ** 0.5 * np.eye(n)
+    X = rng.standard_normal((m, n))
+    PL, PX = _pinned(L), _pinned(X)
+    try:
+        _, st = ooc.ooc_trsm(PL.array, PX.array, 4 * MiB)
+        Y = PX.array.copy()
+        Yref = chol_ref.trsm_rlt(L, X)
+        fwd = np.max(np.abs(Y - Yref)) / np.max(np.abs(Yref))
+        back = np.abs(X - Y @ L.T)
+        bound = 2.0 * chol_ref.trsm_bound(L, Y)
+        _say(f"trsm m={m} n={n}: forward {fwd:.3e}, backward worst ratio {np.max(back / bound):.3e}, "
+             f"panels {st.blocks_done}")
+        assert fwd <= 1e-12
+        assert np.all(back <= bound)
+    finally:
+        PL.free()
+        PX.free()
+        ooc.ooc_release(-1)
+
+
+def test_trsm_large_sampled_rows_and_degenerate_calls():
+    # 16384 x 8192 right-hand sides (1 GiB) against an 8192^2 factor through a
+    # 256 MiB budget; the rows of the solve are independent, so the oracle
+    # solves the sampled rows alone
+    m, n = 16384, 8192
+    rng = np.random.default_rng(23)
+    PL, PX = ooc.PinnedMatrix(n, n), ooc.PinnedMatrix(m, n)
+    try:
+        L = PL.array
+        # off-diagonal entries in [-1/n, 1/n] under a diagonal in [1, 2]: diagonally
+        # dominant, so the solve is well conditioned
+        L[...] = np.tril(synth.matrix(n, n, synth.spec(4343, 0, synth.UNIFORM))) / n
+        L[np.arange(n), np.arange(n)] = 1.0 + n * np.abs(L.diagonal())
+        X = PX.array
+        X[...] = synth.matrix(m, n, synth.spec(4343, 1, synth.UNIFORM))
+        rows = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, 30)]))
+        Xrows = X[rows].copy()
+        _, st = ooc.ooc_trsm(L, X, 256 * MiB)
+        _say(f"trsm m={m} n={n}: {st.flops / st.t_total_s / 1e12:.2f} TFLOP/s, {st.t_total_s:.3f} s, panels "
+             f"{st.blocks_done}, H2D {st.bytes_h2d / 1e9:.2f} GB")
+        Yref = chol_ref.trsm_rlt(L, Xrows)
+        fwd = np.max(np.abs(X[rows] - Yref)) / np.max(np.abs(Yref))
+        assert fwd <= 1e-12, fwd
+        # degenerate calls: no rows, no columns, and a budget without a 64-column panel
+        empty = ooc.PinnedMatrix(1, n)
+        try:
+            assert ooc.ooc_trsm(L, empty.array[:0], 256 * MiB)[0] == ooc.OOC_OK
+        finally:
+            empty.free()
+        assert ooc.ooc_trsm(L[:0, :0], X[:, :0], 256 * MiB)[0] == ooc.OOC_OK
+        assert ooc.ooc_trsm(L, X, 64 * 1024, raise_on_error=False)[0] == ooc.OOC_ERR_BUDGET
+    finally:
+        PL.free()
+        PX.free()
+        ooc.ooc_release(-1)
+
+
 # ---- the general executor: hand-built operation lists -------------------------------
 
 def test_run_ops_product_list():
