@@ -25,37 +25,69 @@
 namespace ooc {
 namespace {
 
-constexpr int kLeaf = 64;   // potrf leaf: one wave, the block in LDS
-constexpr int kLeafT = 64;  // trsm leaf: one thread per row of X, rows and L in LDS
-constexpr int kLeafRows = 64;  // rows of X per trsm-leaf workgroup (one wave: more workgroups per leaf)
+constexpr int kLeaf = 64;   // potrf leaf: one wave, row l of the block in lane l's registers
+constexpr int kLeafT = 64;  // trsm leaf: one wave per 64 rows of X, a row in each lane's registers
+constexpr int kBatch = 16;  // L values read from LDS together by the leaves
 
-// One wave factors an n x n block (n <= 64) held in LDS, column by column:
-// pivot, scale the column below it, update the trailing lower triangle.  A
-// pivot that is not positive (or not finite) stops the factorisation; the
-// first failing column + 1 + col_base is written to *status if it is still 0.
+// v from lane `lane` (wave-uniform), read into scalar registers.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One wave factors an n x n block (n <= 64), right-looking: lane l holds row
+// l of the block in registers (rows and columns beyond n are the identity,
+// which factors to itself).  For each column j: the pivot comes from lane j,
+// every lane below divides its entry of the column by the pivot's square
+// root, and lane l updates its row, a_lc -= a_lj L_cj for j < c <= l, with
+// the column L_.j shared through LDS.  A pivot that is not positive (or not finite) stops
+// the factorisation; the first failing column + 1 + col_base is written to
+// *status if it is still 0.  The block moves through LDS on the way in and
+// out so that the global accesses are row-contiguous.
 __global__ __launch_bounds__(64) void potrf_leaf(int n, double* __restrict__ A, int64_t lda,
                                                  double* __restrict__ status, int64_t col_base) {
-  __shared__ double a[kLeaf][kLeaf + 1];
+  __shared__ double t[kLeaf][kLeaf + 1];
+  __shared__ double col[kLeaf];
   const int l = threadIdx.x;
-  for (int r = 0; r < n; ++r)
-    if (l <= r) a[r][l] = A[r * lda + l];
+  {
+    // every lane loads from an address inside the block (clamped) and then
+    // selects, so that the 64 loads are all in flight at once
+    const int lc = l < n ? l : n - 1;
+    double v[kLeaf];
+#pragma unroll
+    for (int r = 0; r < kLeaf; ++r) v[r] = A[(r < n ? r : n - 1) * lda + lc];
+#pragma unroll
+    for (int r = 0; r < kLeaf; ++r) t[r][l] = (r < n && l <= r) ? v[r] : (l == r ? 1.0 : 0.0);
+  }
   __syncthreads();
+  double a[kLeaf];
+#pragma unroll
+  for (int c = 0; c < kLeaf; ++c) a[c] = t[l][c];
+  // a failing pivot is recorded and the (then meaningless) arithmetic runs on,
+  // so that the loops stay straight-line code
   int bad = -1;
-  for (int j = 0; j < n && bad < 0; ++j) {
-    const double d = a[j][j];
-    if (!(d > 0.0) || !isfinite(d)) {
-      bad = j;
-      break;
-    }
+#pragma clang loop unroll(full)
+  for (int j = 0; j < kLeaf; ++j) {
+    const double d = lane_value(a[j], j);
+    if (bad < 0 && (!(d > 0.0) || !isfinite(d))) bad = j;
     const double piv = sqrt(d);
+    if (l == j) a[j] = piv;
+    if (l > j) a[j] = a[j] / piv;
+    // column j of L through LDS (one wave: its LDS operations run in order),
+    // read back in batches of 16 words whose reads are in flight together
+    col[l] = a[j];
     __syncthreads();
-    if (l == j) a[j][j] = piv;
-    if (l > j && l < n) a[l][j] = a[l][j] / piv;
-    __syncthreads();
-    // row l of the trailing triangle: a[l][c] -= a[l][j] a[c][j], j < c <= l
-    if (l > j && l < n) {
-      const double lj = a[l][j];
-      for (int c = j + 1; c <= l; ++c) a[l][c] = a[l][c] - lj * a[c][j];
+#pragma clang loop unroll(full)
+    for (int c0 = j + 1; c0 < kLeaf; c0 += kBatch) {
+      double lv[kBatch];
+#pragma unroll
+      for (int t = 0; t < kBatch; ++t)
+        if (c0 + t < kLeaf) lv[t] = col[c0 + t];
+#pragma unroll
+      for (int t = 0; t < kBatch; ++t)
+        if (c0 + t < kLeaf && l >= c0 + t) a[c0 + t] = a[c0 + t] - a[j] * lv[t];
     }
     __syncthreads();
   }
@@ -63,34 +95,67 @@ __global__ __launch_bounds__(64) void potrf_leaf(int n, double* __restrict__ A, 
     if (l == 0 && *status == 0.0) *status = (double)(col_base + bad + 1);
     return;
   }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kLeaf; ++c) t[l][c] = a[c];
+  __syncthreads();
   for (int r = 0; r < n; ++r)
-    if (l <= r) A[r * lda + l] = a[r][l];
+    if (l <= r) A[r * lda + l] = t[r][l];
 }
 
-// X <- X L^{-T} for X (m x n, n <= 64): each thread solves one row,
-// x_j = (x_j - sum_{k<j} x_k L_jk) / L_jj, with L and the rows in LDS (a
-// thread's row as a column of xs, so the threads read consecutive words).
-__global__ __launch_bounds__(kLeafRows) void trsm_leaf(int64_t m, int n, double* __restrict__ X, int64_t ldx,
-                                                       const double* __restrict__ L, int64_t ldl) {
-  __shared__ double lt[kLeafT][kLeafT + 1];
-  __shared__ double xs[kLeafT][kLeafRows];
-  for (int e = threadIdx.x; e < kLeafT * kLeafT; e += kLeafRows) {
-    const int r = e / kLeafT, c = e % kLeafT;
-    lt[r][c] = (r < n && c <= r) ? L[r * ldl + c] : (r == c ? 1.0 : 0.0);
+// X <- X L^{-T} for X (m x n, n <= 64), right-looking: lane l of a wave holds
+// row l of a 64-row block of X in registers; for each k, x_k = x_k / L_kk,
+// then x_j = x_j - x_k L_jk for j > k (independent updates, unlike the
+// chained sums of x_j = (x_j - sum_{k<j} x_k L_jk) / L_jj, whose operations
+// they repeat in the same order).  L^T sits in LDS (every lane reads the same
+// word: broadcasts), identity beyond n; the rows move through LDS so that the
+// global accesses are row-contiguous.
+__global__ __launch_bounds__(64) void trsm_leaf(int64_t m, int n, double* __restrict__ X, int64_t ldx,
+                                                const double* __restrict__ L, int64_t ldl) {
+  __shared__ double lt[kLeafT][kLeafT];      // lt[k][j] = L_jk
+  __shared__ double xs[kLeafT][kLeafT + 1];  // the block's rows
+  const int l = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * kLeafT;
+  {
+    // every lane loads from an address inside L and X (clamped) and then
+    // selects, so that the loads are all in flight at once
+    const int lc = l < n ? l : n - 1;
+    double v[kLeafT];
+#pragma unroll
+    for (int j = 0; j < kLeafT; ++j) v[j] = L[(j < n ? j : n - 1) * ldl + lc];
+#pragma unroll
+    for (int j = 0; j < kLeafT; ++j) lt[l][j] = (j < n && l <= j) ? v[j] : (j == l ? 1.0 : 0.0);
+#pragma unroll
+    for (int r = 0; r < kLeafT; ++r) v[r] = X[(row0 + r < m ? row0 + r : m - 1) * ldx + lc];
+#pragma unroll
+    for (int r = 0; r < kLeafT; ++r) xs[r][l] = (row0 + r < m && l < n) ? v[r] : 0.0;
   }
-  const int t = threadIdx.x;
-  const int64_t row = (int64_t)blockIdx.x * kLeafRows + t;
-  double* xr = X + row * ldx;
-  const bool live = row < m;
-  for (int j = 0; j < n; ++j) xs[j][t] = live ? xr[j] : 0.0;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    double s = xs[j][t];
-    for (int k = 0; k < j; ++k) s = s - xs[k][t] * lt[j][k];
-    xs[j][t] = s / lt[j][j];
+  double x[kLeafT];
+#pragma unroll
+  for (int j = 0; j < kLeafT; ++j) x[j] = xs[l][j];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < kLeafT; ++k) {
+    x[k] = x[k] / lt[k][k];
+    // L's column k in batches of 16 words: the batch's LDS reads are in
+    // flight together before its updates
+#pragma clang loop unroll(full)
+    for (int j0 = k + 1; j0 < kLeafT; j0 += kBatch) {
+      double lv[kBatch];
+#pragma unroll
+      for (int t = 0; t < kBatch; ++t)
+        if (j0 + t < kLeafT) lv[t] = lt[k][j0 + t];
+#pragma unroll
+      for (int t = 0; t < kBatch; ++t)
+        if (j0 + t < kLeafT) x[j0 + t] = x[j0 + t] - x[k] * lv[t];
+    }
   }
-  if (live)
-    for (int j = 0; j < n; ++j) xr[j] = xs[j][t];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kLeafT; ++j) xs[l][j] = x[j];
+  __syncthreads();
+  for (int r = 0; r < kLeafT; ++r)
+    if (row0 + r < m && l < n) X[(row0 + r) * ldx + l] = xs[r][l];
 }
 
 // split point of n columns: a multiple of `leaf` near the middle
@@ -105,8 +170,8 @@ hipError_t launch_trsm_rlt(int64_t m, int64_t n, double* X, int64_t ldx, const d
                            hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (n <= kLeafT) {
-    hipLaunchKernelGGL(trsm_leaf, dim3((unsigned)((m + kLeafRows - 1) / kLeafRows)), dim3(kLeafRows), 0, s, m,
-                       (int)n, X, ldx, L, ldl);
+    hipLaunchKernelGGL(trsm_leaf, dim3((unsigned)((m + kLeafT - 1) / kLeafT)), dim3(kLeafT), 0, s, m, (int)n, X,
+                       ldx, L, ldl);
     return hipGetLastError();
   }
   const int64_t n1 = half_of(n, kLeafT), n2 = n - n1;
