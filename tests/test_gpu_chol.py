@@ -353,3 +353,27 @@ def test_gemm_ex_transposed_b_split_bf16():
         for P in (Pa, Pb, Pc):
             P.free()
         ooc.ooc_release(-1)
+
+
+def test_gemm_ex_transposed_b_split_int8_wide_tiles():
+    # op(B) = B^T through the split-INT8 form at 4096^2 with room for large
+    # blocks (a 4096 x 4096 block makes 256 tiles of 256 x 256 against 512 of
+    # 256 x 128, so its slice products take the wide tiles); sampled rows
+    M, N, K = 4096, 4096, 2000
+    A = synth.matrix(M, K, synth.spec(322, 0, synth.NORMAL, row_exp=(-10, 10)))
+    Bs = synth.matrix(N, K, synth.spec(322, 1, synth.NORMAL, row_exp=(-10, 10)))
+    C0 = synth.matrix(M, N, synth.spec(322, 2, synth.UNIFORM))
+    Pa, Pb, Pc = _pinned(A), _pinned(Bs), _pinned(C0)
+    try:
+        _, st = ooc.ooc_gemm_ex(1.0, Pa.array, Pb.array, 0.5, Pc.array, 1 << 30, transb=True,
+                                opts=ooc.make_opts(precision=ooc.SPLIT_INT8, slices=7))
+        rows = np.unique(np.concatenate([[0, 255, 256, M - 1], np.random.default_rng(3).integers(0, M, 60)]))
+        ref, D = oracle.gemm_rows(1.0, A, np.ascontiguousarray(Bs.T), 0.5, C0[rows], rows=rows)
+        lit, gen = oracle.errors(Pc.array[rows], ref, 1.0, D, 0.5, C0[rows])
+        _say(f"split-int8 transb: error literal {lit:.3e} generalised {gen:.3e}; plan {st.plan}")
+        assert st.plan.precision == ooc.SPLIT_INT8
+        assert gen <= oracle.GATE
+    finally:
+        for P in (Pa, Pb, Pc):
+            P.free()
+        ooc.ooc_release(-1)
