@@ -68,15 +68,33 @@ typedef enum { OOC_FP64 = 0, OOC_SPLIT_BF16 = 1, OOC_SPLIT_INT8 = 2 } ooc_precis
  * a column, their A slices and the column's B slice fit), two streams used
  * round robin, A and C double-buffered, B single-buffered.  MODEL: the
  * candidate with the smallest simulated pipeline time under the analytic
- * cost model.  MLP: among the cost model's 8 best candidates, the one with the
- * smallest time predicted by the loaded network (the network shipped beside
- * the library is loaded on first use; falls back to MODEL when none is
- * loaded, for split-BF16 plans when the loaded network was trained on FP64
- * timings only, which it records as a constant slice-count feature, for
- * split-INT8 plans (the shipped network has not seen their timings), and for
- * problems whose M, N, K or budget lies more than four standard deviations
- * (log scale) from the training problems' mean).  AUTO = MODEL. */
-typedef enum { OOC_PLAN_AUTO = 0, OOC_PLAN_PAPER = 1, OOC_PLAN_MODEL = 2, OOC_PLAN_MLP = 3 } ooc_planner;
+ * cost model.  SWEEP: the measured sweep -- the cost model's n best
+ * candidates (n = 8, or OOC_SWEEP_TOP in the environment) are each timed by
+ * one product on the caller's A and B into a page-locked scratch C of C's
+ * shape (after one warm-up product; C itself is written once, by the chosen
+ * plan), and the fastest is used and remembered for the process, keyed by
+ * the problem (sizes, beta != 0, budget, precision, slices, stream count,
+ * transposed B, lower triangle).  It applies to ooc_gemm, ooc_gemm_ex and
+ * ooc_syrk; the planning-only calls, the accumulation sessions and the
+ * products inside ooc_potrf and ooc_trsm take the cost model's choice.  If
+ * the scratch C cannot be allocated the cost model's choice is used and not
+ * remembered.  MLP: among the cost model's 8 best candidates, the one with
+ * the smallest time predicted by the loaded network (the network shipped
+ * beside the library is loaded on first use).  The network declines when
+ * none is loaded, for split-BF16 plans when it was trained on FP64 timings
+ * only (which it records as a constant slice-count feature), for split-INT8
+ * plans (the shipped network has not seen their timings), and for problems
+ * whose M, N, K or budget lies more than four standard deviations (log
+ * scale) from the training problems' mean; then the product calls that
+ * SWEEP applies to plan by the measured sweep, and every other call takes
+ * the cost model's choice.  AUTO = MODEL. */
+typedef enum {
+  OOC_PLAN_AUTO = 0,
+  OOC_PLAN_PAPER = 1,
+  OOC_PLAN_MODEL = 2,
+  OOC_PLAN_MLP = 3,
+  OOC_PLAN_SWEEP = 4
+} ooc_planner;
 
 /* Task orders over the grid of C blocks (i: block row, j: block column) and
  * K panels p.  COLS is the paper's order (column by column, Fig. 2).

@@ -31,7 +31,7 @@ OOC_OK, OOC_ERR_ARG, OOC_ERR_BUDGET, OOC_ERR_DEVICE_MEM, OOC_ERR_NOT_PINNED, OOC
 STATUS_NAMES = {0: "OK", 1: "ERR_ARG", 2: "ERR_BUDGET", 3: "ERR_DEVICE_MEM", 4: "ERR_NOT_PINNED", 5: "ERR_HIP",
                 6: "ERR_NO_DEVICE", 7: "ERR_INJECTED", 8: "ERR_CAPACITY", 9: "ERR_NOT_SPD"}
 FP64, SPLIT_BF16, SPLIT_INT8 = 0, 1, 2
-PLAN_AUTO, PLAN_PAPER, PLAN_MODEL, PLAN_MLP = 0, 1, 2, 3
+PLAN_AUTO, PLAN_PAPER, PLAN_MODEL, PLAN_MLP, PLAN_SWEEP = 0, 1, 2, 3, 4
 ORDER_COLS, ORDER_ROWS, ORDER_COLS_P, ORDER_ROWS_P, ORDER_COLS_PS, ORDER_ROWS_PS = 0, 1, 2, 3, 4, 5
 OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM, OP_POTRF, OP_TRSM = range(6)
 OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_gemm", 4: "potrf", 5: "trsm"}

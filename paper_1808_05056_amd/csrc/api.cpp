@@ -15,8 +15,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -429,7 +431,89 @@ ooc_status check_args(int64_t M, int64_t N, int64_t K, double alpha, const doubl
 
 ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
                      int64_t ldb, double beta, double* C, int64_t ldc, size_t budget_bytes, const ooc_plan_t* given,
-                     const ooc_opts* opts, ooc_stats* stats, bool transb = false, bool lower = false) {
+                     const ooc_opts* opts, ooc_stats* stats, bool transb = false, bool lower = false,
+                     bool allow_sweep = true);
+
+namespace {
+// Plans chosen by the measured sweep, keyed by what the choice depends on.
+struct SweepKey {
+  int64_t M, N, K;
+  bool beta_nonzero;
+  uint64_t budget;
+  int precision, slices, nstreams;
+  bool transb, lower;
+  bool operator<(const SweepKey& o) const {
+    return std::tie(M, N, K, beta_nonzero, budget, precision, slices, nstreams, transb, lower) <
+           std::tie(o.M, o.N, o.K, o.beta_nonzero, o.budget, o.precision, o.slices, o.nstreams, o.transb, o.lower);
+  }
+};
+std::mutex g_sweep_mu;
+std::map<SweepKey, ooc_plan_t> g_sweep;
+}  // namespace
+
+// The measured sweep: the cost model's n best candidates, each timed by one
+// product on the caller's A and B into a page-locked scratch C of C's shape
+// (zeroed, so that beta * C stays finite), after one warm-up product that
+// also allocates the device arena; the fastest is returned and remembered.
+// Without a scratch C the model's choice is returned and not remembered.
+ooc_status sweep_plan(const Problem& pb, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      size_t budget_bytes, const ooc_opts* opts, ooc_plan_t* out) {
+  const SweepKey key{pb.M, pb.N, pb.keff(), pb.beta != 0.0, budget_bytes, opts ? opts->precision : 0,
+                     opts ? opts->slices : 0, opts ? opts->nstreams : 0, pb.transb, pb.lower};
+  {
+    std::lock_guard<std::mutex> lock(g_sweep_mu);
+    auto it = g_sweep.find(key);
+    if (it != g_sweep.end()) {
+      *out = it->second;
+      return OOC_OK;
+    }
+  }
+  ooc_opts mo{};
+  if (opts) mo = *opts;
+  mo.planner = OOC_PLAN_MODEL;
+  mo.profile = 0;
+  mo.timeline = nullptr;
+  mo.timeline_cap = 0;
+  std::vector<ooc_plan_t> plans;
+  std::vector<double> times;
+  ooc_status st = plan_candidates(pb, budget_bytes, &mo, &plans, &times);
+  if (st != OOC_OK) return st;
+  const size_t n = std::min<size_t>(plans.size(), (size_t)std::max(1, env_int("OOC_SWEEP_TOP", 8)));
+  *out = plans[0];
+  if (n == 1) return OOC_OK;
+  double* scratch = nullptr;
+  const size_t cbytes = (size_t)pb.M * (size_t)pb.N * sizeof(double);
+  if (hipHostMalloc(reinterpret_cast<void**>(&scratch), cbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return OOC_OK;
+  }
+  std::memset(scratch, 0, cbytes);
+  size_t best = 0;
+  double best_t = 0.0;
+  for (size_t c = 0; c <= n && st == OOC_OK; ++c) {
+    const size_t x = c == 0 ? 0 : c - 1;  // trial 0 warms up with the model's choice
+    ooc_stats ts{};
+    const double t0 = now_s();
+    st = gemm_impl(pb.M, pb.N, pb.K, pb.alpha, A, lda, B, ldb, pb.beta, scratch, pb.N, budget_bytes, &plans[x], &mo,
+                   &ts, pb.transb, pb.lower, false);
+    const double dt = now_s() - t0;
+    if (st == OOC_OK && c > 0 && (c == 1 || dt < best_t)) {
+      best = x;
+      best_t = dt;
+    }
+  }
+  (void)hipHostFree(scratch);
+  if (st != OOC_OK) return st;
+  *out = plans[best];
+  std::lock_guard<std::mutex> lock(g_sweep_mu);
+  if (g_sweep.size() > 4096) g_sweep.clear();
+  g_sweep[key] = plans[best];
+  return OOC_OK;
+}
+
+ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                     int64_t ldb, double beta, double* C, int64_t ldc, size_t budget_bytes, const ooc_plan_t* given,
+                     const ooc_opts* opts, ooc_stats* stats, bool transb, bool lower, bool allow_sweep) {
   const double t_enter = now_s();
   if (stats) std::memset(stats, 0, sizeof(*stats));
   ooc_status st = check_args(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, transb);
@@ -443,11 +527,26 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
   pb.lower = lower;
   ooc_plan_t plan;
   double predicted = 0.0;
+  bool measured = false;  // chosen by the measured sweep: its prediction is simulated below
   if (given) {
     plan = *given;
   } else {
-    st = choose_plan(pb, budget_bytes, opts, &plan, &predicted);
+    bool declined = false;
+    st = choose_plan(pb, budget_bytes, opts, &plan, &predicted, &declined);
     if (st != OOC_OK) return st;
+    const int planner = opts ? opts->planner : OOC_PLAN_AUTO;
+    if (allow_sweep && (planner == OOC_PLAN_SWEEP || (planner == OOC_PLAN_MLP && declined))) {
+      // the operands are page-locked (checked again below); the sweep's
+      // trial products need them to be
+      if (pb.keff() > 0 && (!range_pinned(A, M, K, lda) || !(transb ? range_pinned(B, N, K, ldb)
+                                                                      : range_pinned(B, K, N, ldb))))
+        return fail(OOC_ERR_NOT_PINNED, "A or B is not page-locked host memory (use ooc_host_alloc)");
+      st = ensure_device(opts ? opts->device : 0);
+      if (st != OOC_OK) return st;
+      st = sweep_plan(pb, A, lda, B, ldb, budget_bytes, opts, &plan);
+      if (st != OOC_OK) return st;
+      measured = true;
+    }
   }
   Layout lay;
   st = plan_layout(pb, plan, &lay);
@@ -458,7 +557,7 @@ ooc_status gemm_impl(int64_t M, int64_t N, int64_t K, double alpha, const double
   std::vector<ooc_op> ops;
   st = build_schedule(pb, plan, lay, &ops);
   if (st != OOC_OK) return st;
-  if (given) predicted = simulate(pb, plan, ops);
+  if (given || measured) predicted = simulate(pb, plan, ops);
   const double t_plan = now_s() - t_enter;
 
   const int dev = opts ? opts->device : 0;
@@ -619,7 +718,7 @@ ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, co
     if (j0 > 0) {
       ooc_stats gs{};
       st = gemm_impl(N - j0, jb, j0, -1.0, A + j0 * lda, lda, A + j0 * lda, lda, 1.0, panel, lda, budget_bytes,
-                     nullptr, &gopts, &gs, true, true);
+                     nullptr, &gopts, &gs, true, true, false);
       add_stats(&total, gs);
       if (st != OOC_OK) break;
     }
@@ -706,7 +805,7 @@ ooc_status trsm_impl(int64_t M, int64_t N, const double* L, int64_t ldl, double*
     if (j0 > 0) {  // X_j = X_j - Y_left L_j,left^T
       ooc_stats gs{};
       st = gemm_impl(M, jb, j0, -1.0, X, ldx, L + j0 * ldl, ldl, 1.0, X + j0, ldx, budget_bytes, nullptr, &gopts, &gs,
-                     true, false);
+                     true, false, false);
       add_stats(&total, gs);
       if (st != OOC_OK) break;
     }

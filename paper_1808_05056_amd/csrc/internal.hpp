@@ -96,9 +96,12 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
 ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
                            std::vector<ooc_plan_t>* plans, std::vector<double>* times);
 
-// Choose a plan according to opts->planner.
+// Choose a plan according to opts->planner (the measured sweep is not done
+// here: OOC_PLAN_SWEEP gets the cost model's choice).  With the learned
+// planner, *mlp_declined (if given) tells whether its network declined the
+// problem, so that the cost model's choice stands.
 ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
-                       ooc_plan_t* plan, double* predicted);
+                       ooc_plan_t* plan, double* predicted, bool* mlp_declined = nullptr);
 
 // Forget cached plan choices (after a new planner network is loaded).
 void clear_plan_cache();

@@ -558,8 +558,13 @@ struct PlanKey {
                     o.c_resident, o.c_ld, o.base, o.transb, o.lower);
   }
 };
+struct CachedPlan {
+  ooc_plan_t plan;
+  double predicted;
+  bool declined;  // the learned planner's network declined the problem
+};
 std::mutex g_plan_mu;
-std::map<PlanKey, std::pair<ooc_plan_t, double>> g_plan_cache;
+std::map<PlanKey, CachedPlan> g_plan_cache;
 }  // namespace
 
 void clear_plan_cache() {
@@ -568,10 +573,10 @@ void clear_plan_cache() {
 }
 
 static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
-                                       ooc_plan_t* plan, double* predicted);
+                                       ooc_plan_t* plan, double* predicted, bool* declined);
 
 ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts, ooc_plan_t* plan,
-                       double* predicted) {
+                       double* predicted, bool* mlp_declined) {
   PlanKey key{pb.M, pb.N, pb.keff(), pb.beta != 0.0, budget_bytes,
               opts ? opts->planner : 0, opts ? opts->precision : 0, opts ? opts->slices : 0,
               opts ? opts->nstreams : 0, pb.c_resident, pb.c_ld, pb.base, pb.transb, pb.lower};
@@ -579,23 +584,26 @@ ooc_status choose_plan(const Problem& pb, uint64_t budget_bytes, const ooc_opts*
     std::lock_guard<std::mutex> lock(g_plan_mu);
     auto it = g_plan_cache.find(key);
     if (it != g_plan_cache.end()) {
-      *plan = it->second.first;
-      if (predicted) *predicted = it->second.second;
+      *plan = it->second.plan;
+      if (predicted) *predicted = it->second.predicted;
+      if (mlp_declined) *mlp_declined = it->second.declined;
       return OOC_OK;
     }
   }
   double pred = 0.0;
-  ooc_status st = choose_plan_uncached(pb, budget_bytes, opts, plan, &pred);
+  bool declined = false;
+  ooc_status st = choose_plan_uncached(pb, budget_bytes, opts, plan, &pred, &declined);
   if (st != OOC_OK) return st;
   if (predicted) *predicted = pred;
+  if (mlp_declined) *mlp_declined = declined;
   std::lock_guard<std::mutex> lock(g_plan_mu);
   if (g_plan_cache.size() > 4096) g_plan_cache.clear();
-  g_plan_cache[key] = {*plan, pred};
+  g_plan_cache[key] = {*plan, pred, declined};
   return OOC_OK;
 }
 
 static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes, const ooc_opts* opts,
-                                       ooc_plan_t* plan, double* predicted) {
+                                       ooc_plan_t* plan, double* predicted, bool* declined) {
   const int planner = opts ? opts->planner : OOC_PLAN_AUTO;
   if (planner == OOC_PLAN_PAPER) {
     const int prec = opts ? opts->precision : OOC_FP64;
@@ -630,6 +638,8 @@ static ooc_status choose_plan_uncached(const Problem& pb, uint64_t budget_bytes,
     if (mlp_predict(pb, budget_bytes, top, &pred)) {
       for (size_t c = 1; c < pred.size(); ++c)
         if (pred[c] < pred[best]) best = c;
+    } else {
+      *declined = true;
     }
   }
   *plan = plans[best];

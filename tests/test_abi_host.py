@@ -463,3 +463,12 @@ def test_make_opts_borrowed_streams_and_release():
     assert o.release_arena == 1
     d = ooc.make_opts()
     assert not any(d.streams) and d.release_arena == 0
+
+
+def test_sweep_planner_in_planning_only_calls_is_the_cost_model():
+    # the measured sweep needs the caller's operands: planning-only calls
+    # return the cost model's choice for PLAN_SWEEP (the product calls time it)
+    for (M, N, K, beta, budget) in ((8192, 6000, 4000, 0.5, 256 << 20), (3000, 40000, 1000, 0.0, 1 << 30)):
+        sw = ooc.ooc_plan(M, N, K, beta, budget, ooc.make_opts(planner=ooc.PLAN_SWEEP))
+        mo = ooc.ooc_plan(M, N, K, beta, budget, ooc.make_opts(planner=ooc.PLAN_MODEL))
+        assert sw.as_dict() == mo.as_dict()

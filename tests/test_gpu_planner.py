@@ -7,6 +7,7 @@ import os
 import numpy as np
 import pytest
 
+import synth
 from synth import workloads as W
 import paper_1808_05056_amd as ooc
 from gpu_helpers import PinnedProblem, check_rows, sample_rows
@@ -122,3 +123,49 @@ def test_learned_planner_declines_problems_outside_its_training_range():
     assert np.all(np.isfinite(pred)) and np.all(np.asarray(pred) > 0)
     mlp = ooc.ooc_plan(w.M, w.N, w.K, w.beta, w.budget, ooc.make_opts(planner=ooc.PLAN_MLP))
     assert mlp.as_dict() == cands[int(np.argmin(pred))].as_dict()
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="no trained planner network shipped with the library")
+def test_measured_sweep_and_the_learned_planners_fallback():
+    """PLAN_SWEEP times the cost model's 8 best candidates on the caller's
+    operands and keeps the fastest: the result meets the gate, the plan is one
+    of those candidates, and a second call reuses it without timing again.  A
+    problem the network declines (K = 64, far below its training range) is
+    planned under PLAN_MLP by the same measured sweep."""
+    MiB = 1 << 20
+    sweep, mlp, model = (ooc.make_opts(planner=p) for p in (ooc.PLAN_SWEEP, ooc.PLAN_MLP, ooc.PLAN_MODEL))
+    w = W.Workload("sweep", 2048, 2048, 2048, 1.0, 0.5, 64 * MiB, seed=51)
+    pp = PinnedProblem(w)
+    try:
+        _, s1 = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, sweep)
+        check_rows(w, pp, sample_rows(w.M, s1.plan.mb, count=32, seed=1))
+        cands = ooc.ooc_plan_candidates(w.M, w.N, w.K, w.beta, w.budget, model)[0][:8]
+        assert s1.plan.as_dict() in [c.as_dict() for c in cands]
+        synth.fill(pp.C, w.spec_c())
+        _, s2 = ooc.ooc_gemm(w.alpha, pp.A, pp.B, w.beta, pp.C, w.budget, sweep)
+        check_rows(w, pp, sample_rows(w.M, s2.plan.mb, count=32, seed=2))
+        print(f"sweep: plan {s1.plan}; planning {s1.t_plan_s * 1e3:.1f} ms (timed), then {s2.t_plan_s * 1e3:.3f} ms; "
+              f"product {s2.t_total_s * 1e3:.1f} ms", flush=True)
+        assert s2.plan.as_dict() == s1.plan.as_dict()
+        assert s1.t_plan_s > 4 * s2.t_total_s  # the first call timed the candidates (9 products)
+        assert s2.t_plan_s < min(s2.t_total_s, s1.t_plan_s / 4)  # the second did not
+    finally:
+        pp.free()
+    ooc.ooc_mlp_load(WEIGHTS)
+    wd = W.Workload("declined", 4096, 4096, 64, 1.0, 0.0, 64 * MiB, seed=52)
+    # the network declines: the planning-only call returns the cost model's choice
+    assert (ooc.ooc_plan(wd.M, wd.N, wd.K, 0.0, wd.budget, mlp).as_dict()
+            == ooc.ooc_plan(wd.M, wd.N, wd.K, 0.0, wd.budget, model).as_dict())
+    pp = PinnedProblem(wd)
+    try:
+        _, s3 = ooc.ooc_gemm(wd.alpha, pp.A, pp.B, wd.beta, pp.C, wd.budget, mlp)
+        check_rows(wd, pp, sample_rows(wd.M, s3.plan.mb, count=32, seed=3))
+        _, s4 = ooc.ooc_gemm(wd.alpha, pp.A, pp.B, wd.beta, pp.C, wd.budget, sweep)
+        print(f"declined: MLP planning {s3.t_plan_s * 1e3:.1f} ms, plan {s3.plan}; the sweep's remembered plan "
+              f"{s4.plan}", flush=True)
+        assert s4.plan.as_dict() == s3.plan.as_dict()  # the sweep the MLP call ran is remembered
+        assert s3.t_plan_s > 4 * s4.t_total_s  # ... the MLP call timed the candidates
+        assert s4.t_plan_s < min(s4.t_total_s, s3.t_plan_s / 4)
+    finally:
+        pp.free()
+        ooc.ooc_release(-1)
