@@ -70,7 +70,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="square-32768-budget-4GiB")
-    ap.add_argument("--planner", default="model", choices=["model", "paper", "mlp"])
+    ap.add_argument("--planner", default="model", choices=["model", "paper", "mlp", "sweep"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "split", "split-int8"])
     ap.add_argument("--slices", type=int, default=6)
     ap.add_argument("--cpu-rows", type=int, default=128, help="rows of C the CPU reference computes")
@@ -104,7 +104,7 @@ def main():
     if not os.path.exists(ooc.LIB_PATH):
         raise SystemExit("libooc.so is not built")
     w = W.BY_NAME[args.workload]
-    planner = {"model": ooc.PLAN_MODEL, "paper": ooc.PLAN_PAPER, "mlp": ooc.PLAN_MLP}[args.planner]
+    planner = {"model": ooc.PLAN_MODEL, "paper": ooc.PLAN_PAPER, "mlp": ooc.PLAN_MLP, "sweep": ooc.PLAN_SWEEP}[args.planner]
     prec = {"fp64": ooc.FP64, "split": ooc.SPLIT_BF16, "split-int8": ooc.SPLIT_INT8}[args.precision]
     opts = ooc.make_opts(planner=planner, precision=prec, slices=args.slices if prec else 0)
     popts = ooc.make_opts(planner=planner, precision=prec, slices=args.slices if prec else 0,
