@@ -10,11 +10,11 @@
 //          written; the strict upper triangle is neither);
 //   trsm:  X <- X L^{-T} for an m x n block X and an n x n lower-triangular L
 //          (the column's rows below its diagonal block).
-// Both recurse on halves: potrf(A11); A21 <- A21 L11^{-T}; A22 <- A22 - A21 A21^T
-// (lower triangle); potrf(A22), and trsm on X1 = X[:, :n1]; X2 <- X2 - X1 L21^T;
-// trsm on X2, so nearly all their flops run in the FP64 matrix-core tile
-// kernel; blocks of at most 64 columns are finished by the leaf kernels
-// below.  Every quotient is a true division (no reciprocal), so integer
+// potrf walks blocks of 64 columns right-looking (factor the diagonal block,
+// solve the rows below, A22 <- A22 - A21 A21^T on the lower triangle); trsm
+// recurses on halves (trsm on X1 = X[:, :n1]; X2 <- X2 - X1 L21^T; trsm on
+// X2).  Nearly all their flops run in the FP64 matrix-core tile kernel;
+// blocks of at most 64 columns are finished by the leaf kernels below.  Every quotient is a true division (no reciprocal), so integer
 // inputs whose factor is integer give it exactly.
 #include <hip/hip_runtime.h>
 
@@ -183,20 +183,25 @@ hipError_t launch_trsm_rlt(int64_t m, int64_t n, double* X, int64_t ldx, const d
   return e;
 }
 
+// Right-looking over blocks of kLeaf columns: factor the diagonal block (one
+// wave), solve the rows below against it (one leaf launch over all of them),
+// and update the trailing lower triangle with one product.  Three launches of
+// wide grids per block instead of the many narrow ones of a recursion on
+// halves.
 hipError_t launch_potrf_lower(int64_t n, double* A, int64_t lda, double* status, int64_t col_base, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (n <= kLeaf) {
-    hipLaunchKernelGGL(potrf_leaf, dim3(1), dim3(64), 0, s, (int)n, A, lda, status, col_base);
-    return hipGetLastError();
+  hipError_t e = hipSuccess;
+  for (int64_t k0 = 0; k0 < n && e == hipSuccess; k0 += kLeaf) {
+    const int64_t kb = n - k0 < kLeaf ? n - k0 : kLeaf, m2 = n - k0 - kb;
+    double* Akk = A + k0 * lda + k0;
+    hipLaunchKernelGGL(potrf_leaf, dim3(1), dim3(64), 0, s, (int)kb, Akk, lda, status, col_base + k0);
+    e = hipGetLastError();
+    if (m2 == 0 || e != hipSuccess) break;
+    double* A21 = Akk + kb * lda;
+    e = launch_trsm_rlt(m2, kb, A21, lda, Akk, lda, s);
+    // A22 <- A22 - A21 A21^T on and below the diagonal
+    if (e == hipSuccess)
+      e = launch_dgemm_f64(m2, m2, kb, -1.0, A21, lda, A21, lda, 1.0, A21 + kb, lda, 0.0, nullptr, 0, s, true, 0);
   }
-  const int64_t n1 = half_of(n, kLeaf), n2 = n - n1;
-  hipError_t e = launch_potrf_lower(n1, A, lda, status, col_base, s);
-  if (e == hipSuccess) e = launch_trsm_rlt(n2, n1, A + n1 * lda, lda, A, lda, s);
-  // A22 <- A22 - A21 A21^T on and below the diagonal
-  if (e == hipSuccess)
-    e = launch_dgemm_f64(n2, n2, n1, -1.0, A + n1 * lda, lda, A + n1 * lda, lda, 1.0, A + n1 * lda + n1, lda, 0.0,
-                         nullptr, 0, s, true, 0);
-  if (e == hipSuccess) e = launch_potrf_lower(n2, A + n1 * lda + n1, lda, status, col_base + n1, s);
   return e;
 }
 
