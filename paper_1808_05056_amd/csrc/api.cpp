@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <future>
 #include <map>
 #include <mutex>
 #include <string>
@@ -651,6 +652,22 @@ int64_t potrf_panel(int64_t N, uint64_t budget_elems) {
   return fits(b) ? b : 0;
 }
 
+// Plan, on a host thread, the out-of-core product of a level-3 routine's
+// next block column while the device works on the current one: the plan lands
+// in the plan cache, where the product's own call finds it (planning a new
+// shape takes tens of milliseconds on the host).
+std::future<void> plan_ahead(int64_t M, int64_t N, int64_t K, bool lower, size_t budget_bytes, const ooc_opts& opts) {
+  Problem pb;
+  pb.M = M; pb.N = N; pb.K = K; pb.alpha = -1.0; pb.beta = 1.0;
+  pb.transb = true;
+  pb.lower = lower;
+  return std::async(std::launch::async, [pb, budget_bytes, opts]() {
+    (void)hipSetDevice(opts.device);  // the learned planner's inference runs on the caller's device
+    ooc_plan_t p;
+    (void)choose_plan(pb, budget_bytes, &opts, &p, nullptr);
+  });
+}
+
 // Append op `o` with the wait set `waits` (negative entries skipped); returns its index.
 int push_op(std::vector<ooc_op>& ops, ooc_op o, std::initializer_list<int> waits) {
   o.nwait = 0;
@@ -751,7 +768,10 @@ ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, co
     ooc_stats ps{};
     HostMats hm{{A, lda}, {hstat, 1}};
     const uint64_t arena_bytes = (uint64_t)(base + 2 * r * jb) * 8;
+    std::future<void> next;  // the next block column's update, planned meanwhile
+    if (j0 + jb < N) next = plan_ahead(N - j0 - jb, std::min(b, N - j0 - jb), j0 + jb, true, budget_bytes, gopts);
     st = exec_list(dev, ops, hm, arena_bytes, budget_bytes, RunCfg{3, OOC_FP64, 0}, &gopts, &ps);
+    if (next.valid()) next.wait();
     list_stats(ops, &ps);
     ps.arena_bytes = arena_bytes;
     add_stats(&total, ps);
@@ -821,7 +841,10 @@ ooc_status trsm_impl(int64_t M, int64_t N, const double* L, int64_t ldl, double*
     ooc_stats ps{};
     HostMats hm{{X, ldx}, {const_cast<double*>(L), ldl}};
     const uint64_t arena_bytes = (uint64_t)(base + 2 * r * jb) * 8;
+    std::future<void> next;  // the next block column's update, planned meanwhile
+    if (j0 + jb < N) next = plan_ahead(M, std::min(b, N - j0 - jb), j0 + jb, false, budget_bytes, gopts);
     st = exec_list(dev, ops, hm, arena_bytes, budget_bytes, RunCfg{3, OOC_FP64, 0}, &gopts, &ps);
+    if (next.valid()) next.wait();
     list_stats(ops, &ps);
     ps.arena_bytes = arena_bytes;
     add_stats(&total, ps);

@@ -178,7 +178,7 @@ def test_potrf_large_sampled_rows():
         Arows = A[rows].copy()
         _, info, st = ooc.ooc_potrf(A, 256 * MiB)
         _say(f"potrf n={n}: {st.flops / st.t_total_s / 1e12:.2f} TFLOP/s, {st.t_total_s:.3f} s, panels "
-             f"{st.blocks_done}, H2D {st.bytes_h2d / 1e9:.2f} GB")
+             f"{st.blocks_done}, H2D {st.bytes_h2d / 1e9:.2f} GB, planning {st.t_plan_s * 1e3:.1f} ms")
         assert info == 0
         Lf = np.tril(A)
         aL = np.abs(Lf)
@@ -262,7 +262,7 @@ def test_trsm_large_sampled_rows_and_degenerate_calls():
         Xrows = X[rows].copy()
         _, st = ooc.ooc_trsm(L, X, 256 * MiB)
         _say(f"trsm m={m} n={n}: {st.flops / st.t_total_s / 1e12:.2f} TFLOP/s, {st.t_total_s:.3f} s, panels "
-             f"{st.blocks_done}, H2D {st.bytes_h2d / 1e9:.2f} GB")
+             f"{st.blocks_done}, H2D {st.bytes_h2d / 1e9:.2f} GB, planning {st.t_plan_s * 1e3:.1f} ms")
         Yref = chol_ref.trsm_rlt(L, Xrows)
         fwd = np.max(np.abs(X[rows] - Yref)) / np.max(np.abs(Yref))
         assert fwd <= 1e-12, fwd
