@@ -23,6 +23,12 @@ trsm_rlt(L, X) -> Y         Y with Y L^T = X for lower-triangular L (n x n,
                             (forward substitution on every row at once),
                               y_j = (x_j - sum_{k<j} y_k l_jk) / l_jj.
                             Only the lower triangle of L is read.
+trsm_rln(L, X) -> Y         Y with Y L = X (back substitution on every row at
+                            once, from the last column):
+                              y_j = (x_j - sum_{k>j} y_k l_kj) / l_jj.
+potrs(L, B) -> X            X with X A = B for A = L L^T, i.e. each row of B
+                            as a right-hand side b of A x = b (A symmetric):
+                            Y L^T = B (forward), then X L = Y (backward).
 trsm_bound(L, Y)            the elementwise bound gamma_n |Y| |L|^T on
                             |X - Y L^T| that forward substitution computed in
                             floating point satisfies (Higham, Theorem 8.5).
@@ -81,6 +87,21 @@ def trsm_rlt(L, X):
     for j in range(n):
         Y[:, j] = (X[:, j] - Y[:, :j] @ L[j, :j]) / L[j, j]
     return Y
+
+
+def trsm_rln(L, X):
+    L = np.asarray(L, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    n = L.shape[0]
+    assert L.shape == (n, n) and X.shape[1] == n
+    Y = np.zeros_like(X)
+    for j in range(n - 1, -1, -1):
+        Y[:, j] = (X[:, j] - Y[:, j + 1:] @ L[j + 1:, j]) / L[j, j]
+    return Y
+
+
+def potrs(L, B):
+    return trsm_rln(L, trsm_rlt(L, B))
 
 
 def trsm_bound(L, Y):

@@ -161,3 +161,50 @@ def test_trsm_against_library_solve_and_backward_bound():
     Yb = Y.copy()
     Yb[3, 7] += 1e-9
     assert not np.all(np.abs(X - Yb @ L.T) <= 2.0 * chol_ref.trsm_bound(L, Yb))
+
+
+# ---- back substitution Y L = X (trsm_rln) and the Cholesky solve (potrs) ----------------
+
+@pytest.mark.parametrize("m,n,seed", [(1, 1, 0), (5, 3, 1), (40, 17, 2), (7, 90, 3)])
+def test_trsm_rln_integer_solution_recovered_exactly(m, n, seed):
+    L = _int_factor(n, seed + 40, dmax=5)
+    Y = np.random.default_rng(seed + 7).integers(-9, 10, (m, n)).astype(np.float64)
+    X = Y @ L
+    assert np.array_equal(chol_ref.trsm_rln(L, X), Y)
+
+
+def test_trsm_rln_two_by_two_by_hand_and_upper_not_read():
+    # Y L = X with L = [[2, 0], [3, 4]]: y2 = x2 / 4; y1 = (x1 - 3 y2) / 2
+    L = np.array([[2.0, np.nan], [3.0, 4.0]])
+    X = np.array([[7.0, 4.0], [1.0, -8.0]])
+    assert np.array_equal(chol_ref.trsm_rln(L, X), np.array([[2.0, 1.0], [3.5, -2.0]]))
+    d = np.array([2.0, -0.5, 4.0])
+    Xr = np.random.default_rng(1).standard_normal((4, 3))
+    assert np.array_equal(chol_ref.trsm_rln(np.diag(d), Xr), Xr / d)
+
+
+def test_trsm_rln_against_library_solve():
+    rng = np.random.default_rng(19)
+    n, m = 60, 25
+    L = np.tril(rng.standard_normal((n, n))) + n ** 0.5 * np.eye(n)
+    X = rng.standard_normal((m, n))
+    Y = chol_ref.trsm_rln(L, X)
+    # Y L = X is L^T Y^T = X^T
+    np.testing.assert_allclose(Y, np.linalg.solve(L.T, X.T).T, rtol=1e-12, atol=1e-13)
+    # back substitution's backward error (Higham, Theorem 8.5): |X - Y L| <= gamma_n |Y| |L|
+    gamma = n * chol_ref.U_FP64 / (1.0 - n * chol_ref.U_FP64)
+    assert np.all(np.abs(X - Y @ L) <= 2.0 * gamma * (np.abs(Y) @ np.abs(L)))
+
+
+def test_potrs_integer_and_against_library_solve():
+    # A = L L^T with integer L and integer X: B = X A is solved exactly
+    n, m = 30, 6
+    L = _int_factor(n, 44)
+    X = np.random.default_rng(2).integers(-5, 6, (m, n)).astype(np.float64)
+    assert np.array_equal(chol_ref.potrs(L, X @ (L @ L.T)), X)
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((n, n))
+    A = G @ G.T / n + np.eye(n)
+    B = rng.standard_normal((m, n))
+    Xs = chol_ref.potrs(chol_ref.potrf_lower(A), B)
+    np.testing.assert_allclose(Xs, np.linalg.solve(A, B.T).T, rtol=1e-10, atol=1e-12)
