@@ -73,13 +73,14 @@ def test_session_integer_data_bit_exact():
     assert np.array_equal(got, ref)
 
 
-def test_session_split_bf16_steps():
+@pytest.mark.parametrize("prec,slices", [(ooc.SPLIT_BF16, 6), (ooc.SPLIT_INT8, 7)])
+def test_session_split_steps(prec, slices):
     M, N, Ks, alphas, beta, budget = 1500, 1300, [1100, 900], [1.0, 1.0], 1.0, 24 * MiB
-    opts = ooc.make_opts(precision=ooc.SPLIT_BF16, slices=6)
+    opts = ooc.make_opts(precision=prec, slices=slices)
     got, ref, D, C0 = _run_session(M, N, Ks, alphas, beta, budget, synth.NORMAL, 90, opts)
     den = D + abs(beta) * np.abs(C0)
     err = oracle.normalized_error(got, ref, den)
-    _say(f"  split session normalised error {err:.3e}")
+    _say(f"  split session (precision {prec}, s = {slices}) normalised error {err:.3e}")
     assert err <= oracle.GATE
 
 
