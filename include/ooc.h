@@ -269,8 +269,8 @@ typedef enum {
                             its lower triangle becomes L with block = L L^T, the strict upper triangle
                             is untouched; a pivot that is not positive stores k0 + its column + 1 in
                             the double at off_w if that is still 0 (later columns unspecified) */
-  OOC_OP_TRSM = 5        /* X <- X L^{-T}: X is rows x cols at off_c (ld_c), L the cols x cols lower
-                            triangle at off_a (ld_a) */
+  OOC_OP_TRSM = 5        /* X <- X L^{-T}, or X <- X L^{-1} with flag OOC_OPF_BACK: X is rows x cols
+                            at off_c (ld_c), L the cols x cols lower triangle at off_a (ld_a) */
 } ooc_op_kind;
 
 #define OOC_MAX_WAITS 6
@@ -282,6 +282,8 @@ typedef enum {
  * written (FP64 products only). */
 #define OOC_OPF_TRANSB 1
 #define OOC_OPF_LOWER 2
+/* Flag of TRSM ops: back substitution X <- X L^{-1} instead of X <- X L^{-T}. */
+#define OOC_OPF_BACK 4
 
 typedef struct {
   int32_t kind;               /* ooc_op_kind */
@@ -291,7 +293,7 @@ typedef struct {
   int32_t wait[OOC_MAX_WAITS];/* earlier ops (other streams) that must complete first */
   int32_t mat;                /* copies: host matrix index (ooc_gemm: 0 = A, 1 = B, 2 = C) */
   int32_t slot;               /* device buffer index within its operand's pool */
-  int32_t flags;              /* GEMM / SPLIT_GEMM: OOC_OPF_* bits */
+  int32_t flags;              /* GEMM / SPLIT_GEMM: OOC_OPF_TRANSB, OOC_OPF_LOWER; TRSM: OOC_OPF_BACK */
   int32_t reserved;           /* 0 */
   int64_t row0, col0;         /* copies: host submatrix origin; GEMM: C block origin (i0, j0) */
   int64_t rows, cols;         /* copies: submatrix extent; GEMM: m, n */
@@ -399,6 +401,24 @@ ooc_status ooc_potrf(int64_t N, double* A, int64_t lda, size_t budget_bytes, con
  * stats: totals (flops = M N^2, bytes, times; blocks_done = block columns). */
 ooc_status ooc_trsm(int64_t M, int64_t N, const double* L, int64_t ldl, double* X, int64_t ldx, size_t budget_bytes,
                     const ooc_opts* opts, ooc_stats* stats);
+
+/* ooc_trsm with the transposition chosen: trans = 1 solves Y L^T = X (as
+ * ooc_trsm, forward substitution), trans = 0 solves Y L = X (X <- X L^{-1},
+ * back substitution: in column-major terms L^T Y' = X', the second solve with
+ * the factor of ooc_potrf), walking the block columns from the last one, each
+ * updated by the solved columns to its right (an out-of-core product without
+ * transposition).  Other arguments, errors and stats as for ooc_trsm. */
+ooc_status ooc_trsm_ex(int32_t trans, int64_t M, int64_t N, const double* L, int64_t ldl, double* X, int64_t ldx,
+                       size_t budget_bytes, const ooc_opts* opts, ooc_stats* stats);
+
+/* Solve with the Cholesky factor out of core: B (M x N, row-major, ldb >= N,
+ * page-locked) is overwritten by X with X A = B for A = L L^T (L from
+ * ooc_potrf, N x N lower-triangular, ldl >= N): each row of B is a
+ * right-hand side b of A x = b (A symmetric).  Two triangular solves: Y L^T =
+ * B, then X L = Y (ooc_trsm_ex with trans 1, then 0).  stats: totals (flops =
+ * 2 M N^2). */
+ooc_status ooc_potrs(int64_t M, int64_t N, const double* L, int64_t ldl, double* B, int64_t ldb, size_t budget_bytes,
+                     const ooc_opts* opts, ooc_stats* stats);
 
 /* ---- accumulation sessions: repeated invocation ----------------------------------
  * The paper's MMOOC can serve as the local step of an outer algorithm (SUMMA or

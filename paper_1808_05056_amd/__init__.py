@@ -37,7 +37,7 @@ OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM, OP_POTRF, OP_TRSM = range(6)
 OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_gemm", 4: "potrf", 5: "trsm"}
 OP_KINDS = {v: k for k, v in OP_NAMES.items()}
 MAX_WAITS = 6
-OPF_TRANSB, OPF_LOWER = 1, 2
+OPF_TRANSB, OPF_LOWER, OPF_BACK = 1, 2, 4
 
 i32, i64, u64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -113,6 +113,8 @@ _sig("ooc_schedule_ex", i32, [i32, i32, i64, i64, i64, dbl, dbl, P(ooc_plan_t), 
 _sig("ooc_syrk", i32, [i64, i64, dbl, vp, i64, dbl, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
 _sig("ooc_potrf", i32, [i64, vp, i64, sz, P(ooc_opts), P(i64), P(ooc_stats)])
 _sig("ooc_trsm", i32, [i64, i64, vp, i64, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
+_sig("ooc_trsm_ex", i32, [i32, i64, i64, vp, i64, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
+_sig("ooc_potrs", i32, [i64, i64, vp, i64, vp, i64, sz, P(ooc_opts), P(ooc_stats)])
 _sig("ooc_run_ops", i32, [P(ooc_op), i64, P(ooc_host_matrix), i32, u64, P(ooc_opts), P(ooc_stats)])
 _sig("ooc_check_ops", i32, [P(ooc_op), i64, P(i64), P(i64)])
 _sig("ooc_gemm_ex", i32, [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, sz, P(ooc_opts),
@@ -149,7 +151,7 @@ _sig("ooc_mlp_predict", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P(dbl)
 _sig("ooc_last_error", ctypes.c_char_p, [])
 _sig("ooc_version", ctypes.c_char_p, [])
 
-EXPORTS = ["ooc_gemm", "ooc_gemm_ex", "ooc_schedule_ex", "ooc_syrk", "ooc_potrf", "ooc_trsm", "ooc_run_ops", "ooc_check_ops", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
+EXPORTS = ["ooc_gemm", "ooc_gemm_ex", "ooc_schedule_ex", "ooc_syrk", "ooc_potrf", "ooc_trsm", "ooc_trsm_ex", "ooc_potrs", "ooc_run_ops", "ooc_check_ops", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_device_copy", "ooc_dgemm_device",
            "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_split_gemm_device_noalloc", "ooc_mlp_features", "ooc_mlp_forward",
@@ -284,6 +286,40 @@ def ooc_trsm(L, X, budget_bytes, opts=None, raise_on_error=True):
     st = ooc_stats()
     s = _lib.ooc_trsm(M, N, pl, ldl, px, ldx, budget_bytes, ctypes.byref(opts) if opts is not None else None,
                       ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
+
+
+def _solve_args(L, X):
+    N = L.shape[0]
+    M = X.shape[0]
+    if L.shape[1] != N or X.shape[1] != N:
+        raise ValueError("L must be N x N and X M x N")
+    pl, ldl = _mat_arg(L, "L")
+    px, ldx = _mat_arg(X, "X")
+    return M, N, pl, ldl, px, ldx
+
+
+def ooc_trsm_ex(L, X, budget_bytes, trans=1, opts=None, raise_on_error=True):
+    """trans=1: X <- X L^{-T} (as ooc_trsm); trans=0: X <- X L^{-1} (Y L = X, back substitution).
+    L (N x N, lower triangle read) and X (M x N) page-locked.  Returns (status, ooc_stats)."""
+    M, N, pl, ldl, px, ldx = _solve_args(L, X)
+    st = ooc_stats()
+    s = _lib.ooc_trsm_ex(trans, M, N, pl, ldl, px, ldx, budget_bytes,
+                         ctypes.byref(opts) if opts is not None else None, ctypes.byref(st))
+    if raise_on_error:
+        _check(s)
+    return s, st
+
+
+def ooc_potrs(L, B, budget_bytes, opts=None, raise_on_error=True):
+    """B <- B A^{-1} for A = L L^T (L from ooc_potrf): each row of B (M x N) is a right-hand side of A x = b.
+    Both page-locked.  Returns (status, ooc_stats)."""
+    M, N, pl, ldl, pb, ldb = _solve_args(L, B)
+    st = ooc_stats()
+    s = _lib.ooc_potrs(M, N, pl, ldl, pb, ldb, budget_bytes, ctypes.byref(opts) if opts is not None else None,
+                       ctypes.byref(st))
     if raise_on_error:
         _check(s)
     return s, st
@@ -434,6 +470,8 @@ def _ops_as_dicts(arr, count):
             if kind in ("potrf", "trsm"):
                 d.update(m=o.rows, n=o.cols, k0=o.k0, off_a=o.off_a, lda=o.ld_a, off_c=o.off_c, ldc=o.ld_c,
                          off_w=o.off_w)
+                if kind == "trsm":
+                    d["back"] = bool(o.flags & OPF_BACK)
                 ops.append(d)
                 continue
             d.update(m=o.rows, n=o.cols, k=o.k, i0=o.row0, j0=o.col0, k0=o.k0, off_a=o.off_a, lda=o.ld_a,

@@ -274,7 +274,9 @@ ooc_status run_ops(DevCtx& c, hipStream_t* streams, const RunCfg& plan, const st
           e = launch_potrf_lower(o.rows, arena + o.off_c, o.ld_c, arena + o.off_w, o.k0, s);
           break;
         case OOC_OP_TRSM:
-          e = launch_trsm_rlt(o.rows, o.cols, arena + o.off_c, o.ld_c, arena + o.off_a, o.ld_a, s);
+          e = (o.flags & OOC_OPF_BACK)
+                  ? launch_trsm_rln(o.rows, o.cols, arena + o.off_c, o.ld_c, arena + o.off_a, o.ld_a, s)
+                  : launch_trsm_rlt(o.rows, o.cols, arena + o.off_c, o.ld_c, arena + o.off_a, o.ld_a, s);
           break;
         default:
           status = OOC_ERR_ARG;
@@ -656,10 +658,11 @@ int64_t potrf_panel(int64_t N, uint64_t budget_elems) {
 // next block column while the device works on the current one: the plan lands
 // in the plan cache, where the product's own call finds it (planning a new
 // shape takes tens of milliseconds on the host).
-std::future<void> plan_ahead(int64_t M, int64_t N, int64_t K, bool lower, size_t budget_bytes, const ooc_opts& opts) {
+std::future<void> plan_ahead(int64_t M, int64_t N, int64_t K, bool transb, bool lower, size_t budget_bytes,
+                             const ooc_opts& opts) {
   Problem pb;
   pb.M = M; pb.N = N; pb.K = K; pb.alpha = -1.0; pb.beta = 1.0;
-  pb.transb = true;
+  pb.transb = transb;
   pb.lower = lower;
   return std::async(std::launch::async, [pb, budget_bytes, opts]() {
     (void)hipSetDevice(opts.device);  // the learned planner's inference runs on the caller's device
@@ -679,12 +682,12 @@ int push_op(std::vector<ooc_op>& ops, ooc_op o, std::initializer_list<int> waits
 
 // Ops that solve rows [i0, i0 + rows) x columns [j0, j0 + jb) of host matrix
 // `mat` against the lower-triangular jb x jb block at arena offset 0 (X <- X
-// L^{-T}), in chunks of r rows through two arena buffers after `base`
+// L^{-T}, or X <- X L^{-1} with `back`), in chunks of r rows through two arena buffers after `base`
 // elements: H2D on stream 0, TRSM on stream 1 (also after op `after` when it
 // is >= 0), D2H on stream 2; a buffer is refilled only after its last chunk
 // went home.
 void append_chunked_solve(std::vector<ooc_op>& ops, int mat, int64_t i0, int64_t rows, int64_t j0, int64_t jb,
-                          int64_t base, int64_t r, int after) {
+                          int64_t base, int64_t r, int after, bool back = false) {
   int home[2] = {-1, -1};
   for (int64_t q = 0; q * r < rows; ++q) {
     const int64_t r0 = i0 + q * r, rr = std::min(r, rows - q * r);
@@ -696,6 +699,7 @@ void append_chunked_solve(std::vector<ooc_op>& ops, int mat, int64_t i0, int64_t
     o = ooc_op{};
     o.kind = OOC_OP_TRSM; o.stream = 1; o.rows = rr; o.cols = jb;
     o.off_c = base + buf * r * jb; o.ld_c = jb; o.off_a = 0; o.ld_a = jb;
+    o.flags = back ? OOC_OPF_BACK : 0;
     const int k = push_op(ops, o, {h, after});
     o = ooc_op{};
     o.kind = OOC_OP_D2H; o.stream = 2; o.mat = mat;
@@ -769,7 +773,7 @@ ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, co
     HostMats hm{{A, lda}, {hstat, 1}};
     const uint64_t arena_bytes = (uint64_t)(base + 2 * r * jb) * 8;
     std::future<void> next;  // the next block column's update, planned meanwhile
-    if (j0 + jb < N) next = plan_ahead(N - j0 - jb, std::min(b, N - j0 - jb), j0 + jb, true, budget_bytes, gopts);
+    if (j0 + jb < N) next = plan_ahead(N - j0 - jb, std::min(b, N - j0 - jb), j0 + jb, true, true, budget_bytes, gopts);
     st = exec_list(dev, ops, hm, arena_bytes, budget_bytes, RunCfg{3, OOC_FP64, 0}, &gopts, &ps);
     if (next.valid()) next.wait();
     list_stats(ops, &ps);
@@ -797,9 +801,12 @@ ooc_status potrf_impl(int64_t N, double* A, int64_t lda, size_t budget_bytes, co
 // of the factorisation): block column j of X is first updated by the columns
 // to its left, X_j = X_j - Y_left L_j,left^T (one out-of-core product with a
 // transposed B), then solved against the diagonal block L_jj on the device,
-// chunk by chunk.
+// chunk by chunk.  With `back` it solves Y L = X (X <- X L^{-1}, back
+// substitution for the columns of X^T: L^T Y^T = X^T) instead, walking the
+// same block columns from the last: X_j = X_j - Y_right L_right,j (an
+// out-of-core product without transposition), then X_j <- X_j L_jj^{-1}.
 ooc_status trsm_impl(int64_t M, int64_t N, const double* L, int64_t ldl, double* X, int64_t ldx, size_t budget_bytes,
-                     const ooc_opts* opts, ooc_stats* stats) {
+                     const ooc_opts* opts, ooc_stats* stats, bool back = false) {
   const double t_enter = now_s();
   ooc_stats total{};
   if (M < 0 || N < 0) return fail(OOC_ERR_ARG, "negative matrix size");
@@ -820,12 +827,20 @@ ooc_status trsm_impl(int64_t M, int64_t N, const double* L, int64_t ldl, double*
   gopts.precision = OOC_FP64;
   gopts.timeline = nullptr;
   gopts.timeline_cap = 0;
-  for (int64_t j0 = 0; j0 < N && st == OOC_OK; j0 += b) {
+  const int64_t nblk = (N + b - 1) / b;
+  for (int64_t step = 0; step < nblk && st == OOC_OK; ++step) {
+    const int64_t j0 = (back ? nblk - 1 - step : step) * b;
     const int64_t jb = std::min(b, N - j0);
-    if (j0 > 0) {  // X_j = X_j - Y_left L_j,left^T
+    // the columns already solved that update this block column
+    const int64_t kdone = back ? N - j0 - jb : j0;
+    if (kdone > 0) {
       ooc_stats gs{};
-      st = gemm_impl(M, jb, j0, -1.0, X, ldx, L + j0 * ldl, ldl, 1.0, X + j0, ldx, budget_bytes, nullptr, &gopts, &gs,
-                     true, false, false);
+      if (back)  // X_j = X_j - Y_right L_right,j
+        st = gemm_impl(M, jb, kdone, -1.0, X + j0 + jb, ldx, L + (j0 + jb) * ldl + j0, ldl, 1.0, X + j0, ldx,
+                       budget_bytes, nullptr, &gopts, &gs, false, false, false);
+      else  // X_j = X_j - Y_left L_j,left^T
+        st = gemm_impl(M, jb, j0, -1.0, X, ldx, L + j0 * ldl, ldl, 1.0, X + j0, ldx, budget_bytes, nullptr, &gopts,
+                       &gs, true, false, false);
       add_stats(&total, gs);
       if (st != OOC_OK) break;
     }
@@ -837,12 +852,15 @@ ooc_status trsm_impl(int64_t M, int64_t N, const double* L, int64_t ldl, double*
     o.kind = OOC_OP_H2D; o.stream = 0; o.mat = 1;
     o.row0 = j0; o.col0 = j0; o.rows = jb; o.cols = jb; o.off_c = 0; o.ld_c = jb;
     const int h_diag = push_op(ops, o, {});
-    append_chunked_solve(ops, 0, 0, M, j0, jb, base, r, h_diag);
+    append_chunked_solve(ops, 0, 0, M, j0, jb, base, r, h_diag, back);
     ooc_stats ps{};
     HostMats hm{{X, ldx}, {const_cast<double*>(L), ldl}};
     const uint64_t arena_bytes = (uint64_t)(base + 2 * r * jb) * 8;
     std::future<void> next;  // the next block column's update, planned meanwhile
-    if (j0 + jb < N) next = plan_ahead(M, std::min(b, N - j0 - jb), j0 + jb, false, budget_bytes, gopts);
+    if (step + 1 < nblk) {  // forward: the next block may be the ragged last one; back: blocks are whole
+      const int64_t nb = back ? b : std::min(b, N - j0 - jb);
+      next = plan_ahead(M, nb, kdone + jb, !back, false, budget_bytes, gopts);
+    }
     st = exec_list(dev, ops, hm, arena_bytes, budget_bytes, RunCfg{3, OOC_FP64, 0}, &gopts, &ps);
     if (next.valid()) next.wait();
     list_stats(ops, &ps);
@@ -1022,6 +1040,29 @@ ooc_status ooc_trsm(int64_t M, int64_t N, const double* L, int64_t ldl, double* 
                     const ooc_opts* opts, ooc_stats* stats) {
   if (stats) std::memset(stats, 0, sizeof(*stats));
   return trsm_impl(M, N, L, ldl, X, ldx, budget_bytes, opts, stats);
+}
+
+ooc_status ooc_trsm_ex(int32_t trans, int64_t M, int64_t N, const double* L, int64_t ldl, double* X, int64_t ldx,
+                       size_t budget_bytes, const ooc_opts* opts, ooc_stats* stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (trans != 0 && trans != 1) return fail(OOC_ERR_ARG, "trans must be 0 or 1");
+  return trsm_impl(M, N, L, ldl, X, ldx, budget_bytes, opts, stats, trans == 0);
+}
+
+ooc_status ooc_potrs(int64_t M, int64_t N, const double* L, int64_t ldl, double* B, int64_t ldb, size_t budget_bytes,
+                     const ooc_opts* opts, ooc_stats* stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  ooc_stats fwd{}, bwd{};
+  ooc_status st = trsm_impl(M, N, L, ldl, B, ldb, budget_bytes, opts, &fwd, false);
+  if (st == OOC_OK) st = trsm_impl(M, N, L, ldl, B, ldb, budget_bytes, opts, &bwd, true);
+  if (stats) {
+    add_stats(stats, fwd);
+    add_stats(stats, bwd);
+    stats->flops = 2.0 * (double)M * (double)N * (double)N;
+    stats->t_total_s = fwd.t_total_s + bwd.t_total_s;
+    stats->blocks_done = fwd.blocks_done + bwd.blocks_done;
+  }
+  return st;
 }
 
 ooc_status ooc_run_ops(const ooc_op* ops, int64_t nops, const ooc_host_matrix* mats, int32_t nmats,

@@ -10,10 +10,11 @@
 //          written; the strict upper triangle is neither);
 //   trsm:  X <- X L^{-T} for an m x n block X and an n x n lower-triangular L
 //          (the column's rows below its diagonal block).
+//   trsm back: X <- X L^{-1} (the backward solve of ooc_trsm_ex and ooc_potrs).
 // potrf walks blocks of 64 columns right-looking (factor the diagonal block,
-// solve the rows below, A22 <- A22 - A21 A21^T on the lower triangle); trsm
-// recurses on halves (trsm on X1 = X[:, :n1]; X2 <- X2 - X1 L21^T; trsm on
-// X2).  Nearly all their flops run in the FP64 matrix-core tile kernel;
+// solve the rows below, A22 <- A22 - A21 A21^T on the lower triangle); the
+// solves recurse on halves (forward: trsm on X1 = X[:, :n1]; X2 <- X2 - X1
+// L21^T; trsm on X2; backward: trsm on X2, X1 <- X1 - X2 L21, trsm on X1).  Nearly all their flops run in the FP64 matrix-core tile kernel;
 // blocks of at most 64 columns are finished by the leaf kernels below.  Every quotient is a true division (no reciprocal), so integer
 // inputs whose factor is integer give it exactly.
 #include <hip/hip_runtime.h>
@@ -103,28 +104,39 @@ __global__ __launch_bounds__(64) void potrf_leaf(int n, double* __restrict__ A, 
     if (l <= r) A[r * lda + l] = t[r][l];
 }
 
-// X <- X L^{-T} for X (m x n, n <= 64), right-looking: lane l of a wave holds
-// row l of a 64-row block of X in registers; for each k, x_k = x_k / L_kk,
-// then x_j = x_j - x_k L_jk for j > k (independent updates, unlike the
-// chained sums of x_j = (x_j - sum_{k<j} x_k L_jk) / L_jj, whose operations
-// they repeat in the same order).  L^T sits in LDS (every lane reads the same
-// word: broadcasts), identity beyond n; the rows move through LDS so that the
-// global accesses are row-contiguous.
-__global__ __launch_bounds__(64) void trsm_leaf(int64_t m, int n, double* __restrict__ X, int64_t ldx,
-                                                const double* __restrict__ L, int64_t ldl) {
-  __shared__ double lt[kLeafT][kLeafT];      // lt[k][j] = L_jk
+// X <- X L^{-T} (forward, BACK false) or X <- X L^{-1} (BACK true) for X
+// (m x n, n <= 64): lane l of a wave holds row l of a 64-row block of X in
+// registers and substitutes right-looking.  Forward: for k = 0, 1, ...:
+// x_k = x_k / L_kk, then x_j = x_j - x_k L_jk for j > k.  Backward: for k =
+// n-1, n-2, ...: x_k = x_k / L_kk, then x_j = x_j - x_k L_kj for j < k.  The
+// updates of one k are independent (unlike the chained sums of the
+// left-looking form, whose operations they repeat in the same order).  The
+// L values of one k (column k of L forward, row k backward) sit in a row of
+// LDS, read by every lane at once (broadcasts), identity beyond n; the rows
+// of X move through LDS so that the global accesses are row-contiguous.
+template <bool BACK>
+__device__ __forceinline__ void trsm_leaf_body(int64_t m, int n, double* __restrict__ X, int64_t ldx,
+                                               const double* __restrict__ L, int64_t ldl) {
+  __shared__ double lt[kLeafT][kLeafT];      // forward lt[k][j] = L_jk, backward lt[k][j] = L_kj
   __shared__ double xs[kLeafT][kLeafT + 1];  // the block's rows
   const int l = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * kLeafT;
   {
     // every lane loads from an address inside L and X (clamped) and then
-    // selects, so that the loads are all in flight at once
+    // selects, so that the loads are all in flight at once; lane l reads
+    // column l of L, v[j] = L_jl
     const int lc = l < n ? l : n - 1;
     double v[kLeafT];
 #pragma unroll
     for (int j = 0; j < kLeafT; ++j) v[j] = L[(j < n ? j : n - 1) * ldl + lc];
 #pragma unroll
-    for (int j = 0; j < kLeafT; ++j) lt[l][j] = (j < n && l <= j) ? v[j] : (j == l ? 1.0 : 0.0);
+    for (int j = 0; j < kLeafT; ++j) {
+      const double e = (j < n && l <= j) ? v[j] : (j == l ? 1.0 : 0.0);
+      if (BACK)
+        lt[j][l] = e;
+      else
+        lt[l][j] = e;
+    }
 #pragma unroll
     for (int r = 0; r < kLeafT; ++r) v[r] = X[(row0 + r < m ? row0 + r : m - 1) * ldx + lc];
 #pragma unroll
@@ -135,19 +147,21 @@ __global__ __launch_bounds__(64) void trsm_leaf(int64_t m, int n, double* __rest
 #pragma unroll
   for (int j = 0; j < kLeafT; ++j) x[j] = xs[l][j];
 #pragma clang loop unroll(full)
-  for (int k = 0; k < kLeafT; ++k) {
+  for (int i = 0; i < kLeafT; ++i) {
+    const int k = BACK ? kLeafT - 1 - i : i;
     x[k] = x[k] / lt[k][k];
-    // L's column k in batches of 16 words: the batch's LDS reads are in
+    // the L values of k in batches of 16 words: the batch's LDS reads are in
     // flight together before its updates
+    const int jlo = BACK ? 0 : k + 1, jhi = BACK ? k : kLeafT;
 #pragma clang loop unroll(full)
-    for (int j0 = k + 1; j0 < kLeafT; j0 += kBatch) {
+    for (int j0 = jlo; j0 < jhi; j0 += kBatch) {
       double lv[kBatch];
 #pragma unroll
       for (int t = 0; t < kBatch; ++t)
-        if (j0 + t < kLeafT) lv[t] = lt[k][j0 + t];
+        if (j0 + t < jhi) lv[t] = lt[k][j0 + t];
 #pragma unroll
       for (int t = 0; t < kBatch; ++t)
-        if (j0 + t < kLeafT) x[j0 + t] = x[j0 + t] - x[k] * lv[t];
+        if (j0 + t < jhi) x[j0 + t] = x[j0 + t] - x[k] * lv[t];
     }
   }
   __syncthreads();
@@ -156,6 +170,16 @@ __global__ __launch_bounds__(64) void trsm_leaf(int64_t m, int n, double* __rest
   __syncthreads();
   for (int r = 0; r < kLeafT; ++r)
     if (row0 + r < m && l < n) X[(row0 + r) * ldx + l] = xs[r][l];
+}
+
+__global__ __launch_bounds__(64) void trsm_leaf(int64_t m, int n, double* __restrict__ X, int64_t ldx,
+                                                const double* __restrict__ L, int64_t ldl) {
+  trsm_leaf_body<false>(m, n, X, ldx, L, ldl);
+}
+
+__global__ __launch_bounds__(64) void trsm_leaf_back(int64_t m, int n, double* __restrict__ X, int64_t ldx,
+                                                     const double* __restrict__ L, int64_t ldl) {
+  trsm_leaf_body<true>(m, n, X, ldx, L, ldl);
 }
 
 // split point of n columns: a multiple of `leaf` near the middle
@@ -180,6 +204,24 @@ hipError_t launch_trsm_rlt(int64_t m, int64_t n, double* X, int64_t ldx, const d
   if (e == hipSuccess)
     e = launch_dgemm_f64(m, n2, n1, -1.0, X, ldx, L + n1 * ldl, ldl, 1.0, X + n1, ldx, 0.0, nullptr, 0, s, true);
   if (e == hipSuccess) e = launch_trsm_rlt(m, n2, X + n1, ldx, L + n1 * ldl + n1, ldl, s);
+  return e;
+}
+
+hipError_t launch_trsm_rln(int64_t m, int64_t n, double* X, int64_t ldx, const double* L, int64_t ldl,
+                           hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (n <= kLeafT) {
+    hipLaunchKernelGGL(trsm_leaf_back, dim3((unsigned)((m + kLeafT - 1) / kLeafT)), dim3(kLeafT), 0, s, m, (int)n,
+                       X, ldx, L, ldl);
+    return hipGetLastError();
+  }
+  // Y L = X with L = [L11 0; L21 L22]: Y2 = X2 L22^{-1}, then Y1 = (X1 - Y2 L21) L11^{-1}
+  const int64_t n1 = half_of(n, kLeafT), n2 = n - n1;
+  hipError_t e = launch_trsm_rln(m, n2, X + n1, ldx, L + n1 * ldl + n1, ldl, s);
+  // X1 <- X1 - X2 L21
+  if (e == hipSuccess)
+    e = launch_dgemm_f64(m, n1, n2, -1.0, X + n1, ldx, L + n1 * ldl, ldl, 1.0, X, ldx, 0.0, nullptr, 0, s);
+  if (e == hipSuccess) e = launch_trsm_rln(m, n1, X, ldx, L, ldl, s);
   return e;
 }
 

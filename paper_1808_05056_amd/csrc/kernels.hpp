@@ -64,10 +64,12 @@ hipError_t launch_adam(int64_t count, float* p, const float* g, float* m, float*
 // Cholesky pieces on device blocks (chol.hip), row-major FP64:
 // A = L L^T in place for the n x n block A (lower triangle; the strict upper
 // triangle untouched); a pivot that is not positive sets *status (if still 0)
-// to col_base + its column + 1.  X <- X L^{-T} for the m x n block X and the
-// n x n lower-triangular L.
+// to col_base + its column + 1.  X <- X L^{-T} (rlt) or X <- X L^{-1} (rln)
+// for the m x n block X and the n x n lower-triangular L.
 hipError_t launch_potrf_lower(int64_t n, double* A, int64_t lda, double* status, int64_t col_base, hipStream_t s);
 hipError_t launch_trsm_rlt(int64_t m, int64_t n, double* X, int64_t ldx, const double* L, int64_t ldl,
+                           hipStream_t s);
+hipError_t launch_trsm_rln(int64_t m, int64_t n, double* X, int64_t ldx, const double* L, int64_t ldl,
                            hipStream_t s);
 
 // Device-to-device copy kernel (bytes and pointers multiples of 16).

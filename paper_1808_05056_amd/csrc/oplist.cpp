@@ -134,6 +134,7 @@ ooc_status validate_ops(const ooc_op* ops, int64_t n, const ooc_host_matrix* mat
     if (o.kind == OOC_OP_POTRF && o.ld_c < o.rows) return bad_op(x, "leading dimension below the block size");
     if (o.kind == OOC_OP_TRSM && (o.ld_c < o.cols || o.ld_a < o.cols))
       return bad_op(x, "leading dimension below the block width");
+    if (o.kind == OOC_OP_TRSM && (o.flags & ~OOC_OPF_BACK)) return bad_op(x, "unknown flags");
     regions(o, &rd, &wr);
     for (const auto* v : {&rd, &wr})
       for (const Region& r : *v)

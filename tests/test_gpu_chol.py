@@ -280,6 +280,119 @@ def test_trsm_large_sampled_rows_and_degenerate_calls():
         ooc.ooc_release(-1)
 
 
+# ---- back substitution Y L = X and the Cholesky solve --------------------------------
+
+@pytest.mark.parametrize("m,n,budget", [(37, 29, 1 * MiB), (700, 500, 2 * MiB), (3000, 200, 1 * MiB),
+                                        (1500, 1300, 3 * MiB)])
+def test_trsm_back_integer_solution_exact(m, n, budget):
+    # X = Y L with integer Y and L: every quotient of the back substitution is
+    # exact; L's strict upper triangle (NaN) is never read
+    L = _int_factor(n, n + 2)
+    Y = np.random.default_rng(m + 1).integers(-9, 10, (m, n)).astype(np.float64)
+    X = Y @ L
+    Lh = L.copy()
+    Lh[np.triu_indices(n, 1)] = np.nan
+    PL, PX = _pinned(Lh), _pinned(X)
+    try:
+        _, st = ooc.ooc_trsm_ex(PL.array, PX.array, budget, trans=0)
+        _say(f"trsm back m={m} n={n}: panels {st.blocks_done} ops {st.ops} arena {st.arena_bytes} "
+             f"t {st.t_total_s * 1e3:.1f} ms")
+        assert np.array_equal(PX.array, Y)
+        assert st.arena_bytes <= budget
+        # trans=1 is ooc_trsm: the same L solves Y L^T = X exactly too
+        PX.array[...] = Y @ L.T
+        ooc.ooc_trsm_ex(PL.array, PX.array, budget, trans=1)
+        assert np.array_equal(PX.array, Y)
+    finally:
+        PL.free()
+        PX.free()
+        ooc.ooc_release(-1)
+
+
+def test_trsm_back_and_potrs_random_against_the_oracle():
+    m, n = 1800, 1400
+    rng = np.random.default_rng(29)
+    L = np.tril(rng.standard_normal((n, n))) + n ** 0.5 * np.eye(n)
+    X = rng.standard_normal((m, n))
+    PL, PX = _pinned(L), _pinned(X)
+    try:
+        _, st = ooc.ooc_trsm_ex(PL.array, PX.array, 4 * MiB, trans=0)
+        Y = PX.array.copy()
+        Yref = chol_ref.trsm_rln(L, X)
+        fwd = np.max(np.abs(Y - Yref)) / np.max(np.abs(Yref))
+        back = np.abs(X - Y @ L)
+        gamma = n * 2.0 ** -53 / (1 - n * 2.0 ** -53)
+        bound = 2.0 * gamma * (np.abs(Y) @ np.abs(L))
+        _say(f"trsm back m={m} n={n}: forward {fwd:.3e}, backward worst ratio {np.max(back / bound):.3e}, "
+             f"panels {st.blocks_done}")
+        assert fwd <= 1e-12
+        assert np.all(back <= bound)
+        # the Cholesky solve: B A^{-1} with A = L L^T
+        PX.array[...] = X
+        _, st = ooc.ooc_potrs(PL.array, PX.array, 4 * MiB)
+        Z = PX.array.copy()
+        Zref = chol_ref.potrs(L, X)
+        fwd = np.max(np.abs(Z - Zref)) / np.max(np.abs(Zref))
+        res = np.max(np.abs(Z @ L @ L.T - X)) / (np.max(np.abs(L)) ** 2 * n * np.max(np.abs(Z)))
+        _say(f"potrs m={m} n={n}: forward {fwd:.3e}, normalised residual {res:.3e}, panels {st.blocks_done}")
+        assert fwd <= 1e-12
+        assert res <= 1e-15
+        assert st.blocks_done >= 2
+    finally:
+        PL.free()
+        PX.free()
+        ooc.ooc_release(-1)
+
+
+def test_factor_then_solve_through_the_device():
+    # ooc_potrf then ooc_potrs on one SPD matrix: x solves A x = b for each row b
+    n, m = 1500, 700
+    A = _spd(n, 41)
+    B = np.random.default_rng(43).standard_normal((m, n))
+    Pa, Pb = _pinned(A), _pinned(B)
+    try:
+        _, info, _ = ooc.ooc_potrf(Pa.array, 4 * MiB)
+        assert info == 0
+        _, st = ooc.ooc_potrs(Pa.array, Pb.array, 4 * MiB)
+        Xs = Pb.array.copy()
+        Xref = np.linalg.solve(A, B.T).T
+        err = np.max(np.abs(Xs - Xref)) / np.max(np.abs(Xref))
+        cond = np.linalg.cond(A)
+        _say(f"potrf + potrs n={n} m={m}: forward {err:.3e} (cond {cond:.1f})")
+        assert err <= 50 * cond * n * 2.0 ** -53
+    finally:
+        Pa.free()
+        Pb.free()
+        ooc.ooc_release(-1)
+
+
+def test_potrs_large_sampled_rows():
+    # 16384 right-hand sides of an 8192^2 system through a 256 MiB budget; the
+    # rows of the solve are independent, so the oracle solves the sampled rows
+    m, n = 16384, 8192
+    rng = np.random.default_rng(47)
+    PL, PX = ooc.PinnedMatrix(n, n), ooc.PinnedMatrix(m, n)
+    try:
+        L = PL.array
+        L[...] = np.tril(synth.matrix(n, n, synth.spec(4747, 0, synth.UNIFORM))) / n
+        L[np.arange(n), np.arange(n)] = 1.0 + n * np.abs(L.diagonal())
+        X = PX.array
+        X[...] = synth.matrix(m, n, synth.spec(4747, 1, synth.UNIFORM))
+        rows = np.unique(np.concatenate([[0, m - 1], rng.integers(0, m, 30)]))
+        Xrows = X[rows].copy()
+        _, st = ooc.ooc_potrs(L, X, 256 * MiB)
+        _say(f"potrs m={m} n={n}: {st.flops / st.t_total_s / 1e12:.2f} TFLOP/s, {st.t_total_s:.3f} s, panels "
+             f"{st.blocks_done}, H2D {st.bytes_h2d / 1e9:.2f} GB, planning {st.t_plan_s * 1e3:.1f} ms")
+        Zref = chol_ref.potrs(L, Xrows)
+        fwd = np.max(np.abs(X[rows] - Zref)) / np.max(np.abs(Zref))
+        assert fwd <= 1e-12, fwd
+        assert ooc.ooc_potrs(L[:0, :0], X[:, :0], 256 * MiB)[0] == ooc.OOC_OK
+    finally:
+        PL.free()
+        PX.free()
+        ooc.ooc_release(-1)
+
+
 # ---- the general executor: hand-built operation lists -------------------------------
 
 def test_run_ops_product_list():

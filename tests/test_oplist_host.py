@@ -118,3 +118,34 @@ def test_potrf_and_syrk_argument_checks_on_the_host():
     # a budget that holds no 64-column panel
     st, info, _ = ooc.ooc_potrf(A, 1024, raise_on_error=False)
     assert st == ooc.OOC_ERR_BUDGET
+
+
+def test_solve_argument_checks_on_the_host():
+    L, X = np.zeros((8, 8)), np.zeros((5, 8))
+    assert ooc.ooc_trsm_ex(L, X, 1 << 20, trans=2, raise_on_error=False)[0] == ooc.OOC_ERR_ARG
+    for trans in (0, 1):
+        assert ooc.ooc_trsm_ex(L, X, 1024, trans=trans, raise_on_error=False)[0] == ooc.OOC_ERR_BUDGET
+    assert ooc.ooc_potrs(L, X, 1024, raise_on_error=False)[0] == ooc.OOC_ERR_BUDGET
+    with pytest.raises(ValueError):
+        ooc.ooc_potrs(L, np.zeros((5, 7)), 1 << 20)
+
+
+def _trsm_op(flags):
+    # a 4 x 3 block solved against the 3 x 3 triangle at arena offset 0
+    h_l = ooc.make_op("h2d", 0, mat=0, rows=3, cols=3, off_c=0, ld_c=3)
+    h_x = ooc.make_op("h2d", 0, mat=1, rows=4, cols=3, off_c=9, ld_c=3)
+    t = ooc.make_op("trsm", 1, waits=[0, 1], rows=4, cols=3, off_c=9, ld_c=3, off_a=0, ld_a=3, flags=flags)
+    d = ooc.make_op("d2h", 2, waits=[2], mat=1, rows=4, cols=3, off_c=9, ld_c=3)
+    return [h_l, h_x, t, d]
+
+
+@pytest.mark.parametrize("flags,ok", [(0, True), (ooc.OPF_BACK, True), (ooc.OPF_TRANSB, False),
+                                      (ooc.OPF_LOWER, False), (ooc.OPF_BACK | 8, False)])
+def test_trsm_op_flags(flags, ok):
+    ops = _trsm_op(flags)
+    st, _ = ooc.ooc_run_ops(ops, [np.zeros((3, 3)), np.zeros((4, 3))], 21 * 8, raise_on_error=False)
+    if ok:
+        assert st in (ooc.OOC_ERR_NO_DEVICE, ooc.OOC_ERR_NOT_PINNED)
+        assert ooc.ooc_check_ops(ops)[0] == ooc.OOC_OK
+    else:
+        assert st == ooc.OOC_ERR_ARG, ooc.ooc_last_error()
