@@ -230,8 +230,11 @@ def run_leg(ooc, w, A, B, C, opts, popts, args, prec, slices):
             peak, work, kname = PEAK_FP64_TFLOPS, w.flops, "dgemm_f64_mfma"
             traffic = measured_traffic(w.name, plan_tag)
         else:  # BF16 or INT8 matrix work of the slice products, slicing kernels excluded
-            peak, kname = ((PEAK_BF16_TFLOPS, "split_gemm") if prec == ooc.SPLIT_BF16
-                           else (PEAK_INT8_TOPS, "split_gemm_i8"))
+            if prec == ooc.SPLIT_BF16:
+                peak, kname = PEAK_BF16_TFLOPS, "split_gemm"
+            else:  # the tile width the library takes for a full block of the plan
+                wide = ooc.ooc_split_int8_wide_tiles(min(plan.mb, w.M), min(plan.nb, w.N), 256)
+                peak, kname = PEAK_INT8_TOPS, "split_gemm_i8w" if wide == 1 else "split_gemm_i8"
             work = w.flops * slices * (slices + 1) / 2
             traffic = None
         achieved = work * args.steps / mbusy / 1e12

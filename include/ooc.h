@@ -531,6 +531,13 @@ ooc_status ooc_split_int8_gemm_device(int32_t device, int64_t m, int64_t n, int6
                                       const double* A, int64_t lda, const double* B, int64_t ldb,
                                       double beta, double* C, int64_t ldc, int32_t reps, double* ms_out);
 
+/* Tile width of the INT8 slice products of an m x n block on a device with
+ * `cus` compute units: 1 if they run on 256 x 256 tiles (half the plane bytes
+ * per product of 256 x 128 ones, about 1.9 times the time per tile), when
+ * those tiles' waves over the CUs end sooner, else 0; -1 for m, n or cus
+ * below 1.  Host only (the library's own choice; for reports). */
+int32_t ooc_split_int8_wide_tiles(int64_t m, int64_t n, int32_t cus);
+
 /* ---- the learned planner ------------------------------------------------------ */
 /* A small regression network predicts the log run time of a candidate plan
  * from its features; OOC_PLAN_MLP takes the candidate with the smallest

@@ -147,6 +147,7 @@ _sig("ooc_mlp_fit", i32, [i32, P_flt, P_flt, i64, i32, i32, ctypes.c_float, ctyp
 _sig("ooc_mlp_save", i32, [ctypes.c_char_p])
 _sig("ooc_mlp_load", i32, [ctypes.c_char_p])
 _sig("ooc_mlp_loaded", i32, [])
+_sig("ooc_split_int8_wide_tiles", i32, [i64, i64, i32])
 _sig("ooc_mlp_predict", i32, [i64, i64, i64, dbl, sz, P(ooc_plan_t), i64, P(dbl)])
 _sig("ooc_last_error", ctypes.c_char_p, [])
 _sig("ooc_version", ctypes.c_char_p, [])
@@ -154,7 +155,7 @@ _sig("ooc_version", ctypes.c_char_p, [])
 EXPORTS = ["ooc_gemm", "ooc_gemm_ex", "ooc_schedule_ex", "ooc_syrk", "ooc_potrf", "ooc_trsm", "ooc_trsm_ex", "ooc_potrs", "ooc_run_ops", "ooc_check_ops", "ooc_gemm_planned", "ooc_plan", "ooc_plan_footprint", "ooc_partition", "ooc_plan_candidates",
            "ooc_plan_predict", "ooc_plan_simulate", "ooc_schedule", "ooc_host_alloc", "ooc_host_free", "ooc_device_alloc",
            "ooc_device_free", "ooc_copy_to_device", "ooc_copy_to_host", "ooc_release", "ooc_device_copy", "ooc_dgemm_device",
-           "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_split_gemm_device_noalloc", "ooc_mlp_features", "ooc_mlp_forward",
+           "ooc_split_gemm_device", "ooc_split_int8_gemm_device", "ooc_split_int8_wide_tiles", "ooc_split_gemm_device_noalloc", "ooc_mlp_features", "ooc_mlp_forward",
            "ooc_mlp_grad", "ooc_mlp_adam",
            "ooc_mlp_train", "ooc_mlp_fit", "ooc_mlp_save", "ooc_mlp_load", "ooc_mlp_loaded", "ooc_mlp_predict",
            "ooc_accum_begin", "ooc_accum_step", "ooc_accum_end", "ooc_accum_resident_rows", "ooc_accum_schedule",
@@ -562,6 +563,11 @@ def ooc_split_int8_gemm_device(m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ld
     _check(_lib.ooc_split_int8_gemm_device(device, m, n, k, s, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps,
                                            ctypes.byref(ms) if timed else None))
     return ms.value if timed else None
+
+
+def ooc_split_int8_wide_tiles(m, n, cus=256):
+    """1 if the INT8 slice products of an m x n block run on 256 x 256 tiles, 0 on 256 x 128, -1 for bad sizes."""
+    return _lib.ooc_split_int8_wide_tiles(m, n, cus)
 
 
 def ooc_dgemm_device(m, n, k, alpha, dA, lda, dB, ldb, beta, dC, ldc, reps=1, timed=False, device=0):

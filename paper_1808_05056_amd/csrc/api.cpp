@@ -1537,6 +1537,11 @@ ooc_status ooc_split_int8_gemm_device(int32_t device, int64_t m, int64_t n, int6
   return split_gemm_device(kSliceInt8, device, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, reps, ms_out);
 }
 
+int32_t ooc_split_int8_wide_tiles(int64_t m, int64_t n, int32_t cus) {
+  if (m < 1 || n < 1 || cus < 1) return -1;
+  return split_i8_wide(m, n, cus) ? 1 : 0;
+}
+
 ooc_status ooc_device_copy(int32_t device, void* dst, const void* src, size_t bytes) {
   if (!dst || !src || bytes % 16 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
     return fail(OOC_ERR_ARG, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");

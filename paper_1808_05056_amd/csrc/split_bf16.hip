@@ -432,16 +432,28 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
   const uint32_t lds0 = (uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char*)lds;
   const uint32_t la0 = __builtin_amdgcn_readfirstlane(lds0 + (8 * T::ALD * w) * GROW);
   const uint32_t lb0 = __builtin_amdgcn_readfirstlane(lds0 + T::A + (8 * T::BLD * w) * GROW);
-  auto issue = [&](int p, int q, int cc, int stage) {
-    const uint8_t* pa = a_src + (int64_t)(p - 1) * mpad * rowb + (int64_t)cc * GROW;
-    const uint8_t* pb = b_src + (int64_t)(q - 1) * npad * rowb + (int64_t)cc * GROW;
-    const uint32_t so = (uint32_t)stage * T::STAGE;
+  // with three stages the loads of a step are spread over its GKK
+  // instruction groups (part kk issues the A loads j with j % GKK == kk and
+  // the B loads j with j * GKK / BLD == kk), so that a wave's requests do not
+  // reach the L1 in one burst ahead of its products (8192^3: BF16 862 -> 913
+  // TFLOP/s, INT8 1624 -> 1785 TOP/s); with two stages, one step ahead, they
+  // go out together at the step's start (spread: 1880 -> 1756 TOP/s)
+  constexpr bool kSpread = NST > 2;
+  auto issue_part = [&](const uint8_t* pa, const uint8_t* pb, uint32_t so, int kk) {
 #pragma unroll
     for (int j = 0; j < T::ALD; ++j)
-      load_lds16(pa + 8 * j * rowb + 16 * (lslot ^ gswz(8 * (T::ALD * w + j) + lrow)), la0 + so + 1024 * j);
+      if (j % GKK == kk)
+        load_lds16(pa + 8 * j * rowb + 16 * (lslot ^ gswz(8 * (T::ALD * w + j) + lrow)), la0 + so + 1024 * j);
 #pragma unroll
     for (int j = 0; j < T::BLD; ++j)
-      load_lds16(pb + 8 * j * rowb + 16 * (lslot ^ gswz(8 * (T::BLD * w + j) + lrow)), lb0 + so + 1024 * j);
+      if (j * GKK / T::BLD == kk)
+        load_lds16(pb + 8 * j * rowb + 16 * (lslot ^ gswz(8 * (T::BLD * w + j) + lrow)), lb0 + so + 1024 * j);
+  };
+  auto src_a = [&](int p, int cc) { return a_src + (int64_t)(p - 1) * mpad * rowb + (int64_t)cc * GROW; };
+  auto src_b = [&](int q, int cc) { return b_src + (int64_t)(q - 1) * npad * rowb + (int64_t)cc * GROW; };
+  auto issue = [&](int p, int q, int cc, int stage) {
+#pragma unroll
+    for (int kk = 0; kk < GKK; ++kk) issue_part(src_a(p, cc), src_b(q, cc), (uint32_t)stage * T::STAGE, kk);
   };
   const int fr = lane & 31, fh = lane >> 5;
   const int a_row0 = wm * (GBM / T::WM) + fr, b_row0 = wn * (TBN / T::WN) + fr;
@@ -508,9 +520,14 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
 #pragma unroll
           for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
       for (int x = 0; x < wsteps; ++x, ++st) {
+        // NST - 1 steps ahead, into the stage every wave left at the last
+        // barrier (part by part between the products when spread)
         const bool more = issued < nsteps;
-        if (more) {  // NST - 1 steps ahead, into the stage every wave left at the last barrier
-          issue(plo + f_pi, t - plo - f_pi, f_c0 + f_ci, stage == 0 ? NST - 1 : stage - 1);
+        const uint8_t* ipa = src_a(plo + f_pi, f_c0 + f_ci);
+        const uint8_t* ipb = src_b(t - plo - f_pi, f_c0 + f_ci);
+        const uint32_t iso = (uint32_t)(stage == 0 ? NST - 1 : stage - 1) * T::STAGE;
+        if (more) {
+          if constexpr (!kSpread) issue(plo + f_pi, t - plo - f_pi, f_c0 + f_ci, stage == 0 ? NST - 1 : stage - 1);
           fadv();
           ++issued;
         }
@@ -520,6 +537,7 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
         frags(As, Bs, 0, a0, b0);
 #pragma unroll
         for (int kk = 0; kk < GKK; ++kk) {
+          if (kSpread && more) issue_part(ipa, ipb, iso, kk);
           // fragments of the next instruction's k range are read while this one multiplies
           if (kk % 2 == 0) {
             if (kk + 1 < GKK) frags(As, Bs, kk + 1, a1, b1);
@@ -636,10 +654,10 @@ static int64_t pad_k(int64_t k, SliceFormat f) { return f == kSliceInt8 ? pad128
 static int64_t pad_m(int64_t m) { return pad256(m); }
 
 // A 256 x 256 INT8 tile moves half the plane bytes per product of a 256 x 128
-// one and runs at 1.17 times its rate (8192^3 launches: 1986 against 1702
-// TOP/s), so it takes about 1.71 times as long; the wide tiles are used when
+// one and runs at 1.05 times its rate (8192^3 launches: 1880 against 1785
+// TOP/s), so it takes about 1.90 times as long; the wide tiles are used when
 // their waves over the CUs (one tile per CU at a time) end sooner.
-constexpr double kWideTileTime = 1.71;
+constexpr double kWideTileTime = 1.90;
 
 bool split_i8_wide(int64_t m, int64_t n, int cus) {
   const double rows = (double)(pad256(m) / 256);

@@ -472,3 +472,16 @@ def test_sweep_planner_in_planning_only_calls_is_the_cost_model():
         sw = ooc.ooc_plan(M, N, K, beta, budget, ooc.make_opts(planner=ooc.PLAN_SWEEP))
         mo = ooc.ooc_plan(M, N, K, beta, budget, ooc.make_opts(planner=ooc.PLAN_MODEL))
         assert sw.as_dict() == mo.as_dict()
+
+
+def test_int8_tile_width_rule():
+    # 8192^2 blocks on 256 CUs: 1024 wide tiles (4 waves) against 2048 narrow
+    # ones (8 waves): wide; a 4096 x 2048 block: 128 wide tiles (1 wave of half
+    # the CUs) against 256 narrow (1 wave): narrow; bad sizes are refused
+    assert ooc.ooc_split_int8_wide_tiles(8192, 8192, 256) == 1
+    assert ooc.ooc_split_int8_wide_tiles(4096, 2048, 256) == 0
+    assert ooc.ooc_split_int8_wide_tiles(0, 2048, 256) == -1
+    assert ooc.ooc_split_int8_wide_tiles(4096, 2048, 0) == -1
+    # any valid block gets a width
+    for m, n in [(256, 256), (1024, 4096), (65536, 8192), (300, 9000)]:
+        assert ooc.ooc_split_int8_wide_tiles(m, n, 256) in (0, 1)
