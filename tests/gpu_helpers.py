@@ -122,16 +122,6 @@ class HipRuntime:
     def free(self, p):
         self._check(self.lib.hipFree(p), "hipFree")
 
-    def free_shows_release(self, nbytes):
-        """Whether the runtime's free-memory reading rises again when a block of
-        nbytes from hipMalloc is freed (the runtime may keep freed blocks)."""
-        p = self.malloc(nbytes)
-        self.device_synchronize()
-        low = self.mem_free()
-        self.free(p)
-        self.device_synchronize()
-        return self.mem_free() - low >= nbytes // 2
-
     def mem_free(self):
         fr, tot = self._ct.c_size_t(), self._ct.c_size_t()
         self._check(self.lib.hipMemGetInfo(self._ct.byref(fr), self._ct.byref(tot)), "hipMemGetInfo")
