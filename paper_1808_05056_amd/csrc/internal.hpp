@@ -77,7 +77,7 @@ struct Machine {
   double kernel_k0 = 30.0;         // per-tile fixed cost in units of k
   double kernel_scalar_factor = 1.15;  // odd leading dimensions (8-byte loads)
   double kernel_launch_s = 6e-6;
-  double split_tflops_per_product = 1050.0;  // BF16 slice-product rate (TFLOP/s of BF16 work), 256 x 128 tiles,
+  double split_tflops_per_product = 1080.0;  // BF16 slice-product rate (TFLOP/s of BF16 work), 256 x 128 tiles,
                                              // one per CU, slice-sum traffic excluded (8192^3 launches at s = 5)
   double split_k0 = 160.0;                  // per weight and tile: pipeline start in units of k
   double int8_tops_per_product = 2090.0;    // INT8 slice-product rate (TOP/s), same tiles (1.99x the BF16 rate)

@@ -439,6 +439,11 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
   // TFLOP/s, INT8 1624 -> 1785 TOP/s); with two stages, one step ahead, they
   // go out together at the step's start (spread: 1880 -> 1756 TOP/s)
   constexpr bool kSpread = NST > 2;
+  // With three stages each step's last instruction group also runs after the
+  // step's barrier, under the next step's first LDS reads (8192^3 BF16: 937 ->
+  // 965 TFLOP/s; INT8 unchanged); the 256 x 256 INT8 tile has no registers
+  // for fragments held across the barrier (spilled, 1905 -> 1235 TOP/s).
+  constexpr bool kCarry = NST > 2;
   auto issue_part = [&](const uint8_t* pa, const uint8_t* pb, uint32_t so, int kk) {
 #pragma unroll
     for (int j = 0; j < T::ALD; ++j)
@@ -509,6 +514,13 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
           for (int v = 0; v < 16; ++v) U[i][j][v] = 0;
     }
     typename M::acc acc[FI][FJ];
+    static_assert(GKK % 2 == 0, "the last instruction group's fragments are in a1, b1");
+    auto mfma_group = [&](const frag (&a)[FI], const frag (&b)[FJ]) {
+#pragma unroll
+      for (int i = 0; i < FI; ++i)
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) acc[i][j] = M::mfma(a[i], b[j], acc[i][j]);
+    };
     int stage = 0, st = 0;
     for (int c0 = 0; c0 < nchunks; c0 += wc) {
       const int wl = (nchunks - c0) < wc ? (nchunks - c0) : wc;
@@ -519,6 +531,7 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
         for (int j = 0; j < FJ; ++j)
 #pragma unroll
           for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
+      frag a0[FI], b0[FJ], a1[FI], b1[FJ];
       for (int x = 0; x < wsteps; ++x, ++st) {
         // NST - 1 steps ahead, into the stage every wave left at the last
         // barrier (part by part between the products when spread)
@@ -533,24 +546,28 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
         }
         const unsigned char* As = lds + stage * T::STAGE;
         const unsigned char* Bs = As + T::A;
-        frag a0[FI], b0[FJ], a1[FI], b1[FJ];
         frags(As, Bs, 0, a0, b0);
+        // with kCarry the previous step's last instruction group multiplies
+        // (its fragments are in registers) while this step's first fragments
+        // are read
+        if constexpr (kCarry) {
+          if (x > 0) mfma_group(a1, b1);
+        }
 #pragma unroll
-        for (int kk = 0; kk < GKK; ++kk) {
-          if (kSpread && more) issue_part(ipa, ipb, iso, kk);
-          // fragments of the next instruction's k range are read while this one multiplies
+        for (int kk = 0; kk < (kCarry ? GKK - 1 : GKK); ++kk) {
+          if (kSpread && more) {
+            issue_part(ipa, ipb, iso, kk);
+            if (kCarry && kk + 2 == GKK) issue_part(ipa, ipb, iso, kk + 1);
+          }
+          // fragments of the next instruction's k range are read while this
+          // one multiplies; with kCarry the last group's stay in a1, b1 past
+          // the barrier
           if (kk % 2 == 0) {
             if (kk + 1 < GKK) frags(As, Bs, kk + 1, a1, b1);
-#pragma unroll
-            for (int i = 0; i < FI; ++i)
-#pragma unroll
-              for (int j = 0; j < FJ; ++j) acc[i][j] = M::mfma(a0[i], b0[j], acc[i][j]);
+            mfma_group(a0, b0);
           } else {
             if (kk + 1 < GKK) frags(As, Bs, kk + 1, a0, b0);
-#pragma unroll
-            for (int i = 0; i < FI; ++i)
-#pragma unroll
-              for (int j = 0; j < FJ; ++j) acc[i][j] = M::mfma(a1[i], b1[j], acc[i][j]);
+            mfma_group(a1, b1);
           }
         }
         // the next step has landed (with three stages the one after it may
@@ -561,6 +578,7 @@ __device__ __forceinline__ void split_gemm_body(int64_t m, int64_t n, int64_t kp
           wait_vm_barrier<0>();
         stage = stage == NST - 1 ? 0 : stage + 1;
       }
+      if constexpr (kCarry) mfma_group(a1, b1);  // the window's last group
       if constexpr (M::kWindows) {  // fold the window's FP32 sums into the int32 weight sums (exact)
 #pragma unroll
         for (int i = 0; i < FI; ++i)
