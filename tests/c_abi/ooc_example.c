@@ -1,8 +1,10 @@
 /* A plain C caller of the library: a tiled out-of-core product through a
  * small budget, checked exactly (integer-valued data, every sum exact) against
  * a naive triple loop; then the same product from the split-BF16 and the
- * split-INT8 forms, whose slices are exact for these small integers.  Prints
- * "ok" on success. */
+ * split-INT8 forms, whose slices are exact for these small integers; then an
+ * out-of-core Cholesky factorisation of A = L L^T with an integer L and the
+ * Cholesky solve of X A = B with an integer X, both exact.  Prints "ok" on
+ * success. */
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -14,6 +16,59 @@ static int check(const double* C, const double* R, int64_t n) {
       fprintf(stderr, "mismatch at %lld: %.17g vs %.17g\n", (long long)x, C[x], R[x]);
       return 1;
     }
+  return 0;
+}
+
+/* Factor A = L L^T (n = 300, panels of 128 columns through a 1 MiB budget)
+ * and solve X A = B for 50 right-hand sides; every pivot is a perfect square
+ * and every quotient exact, so L and X come back exactly. */
+static int cholesky(void) {
+  const int64_t n = 300, m = 50;
+  double *A = NULL, *Bm = NULL;
+  if (ooc_host_alloc((void**)&A, n * n * 8) || ooc_host_alloc((void**)&Bm, m * n * 8)) return 1;
+  double* L = calloc(n * n, 8);
+  double* X = malloc(m * n * 8);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j < i; ++j) L[i * n + j] = (double)((i * 5 + j * 3) % 7 - 3);
+    L[i * n + i] = (double)(1 + i % 4);
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = 0; k <= (i < j ? i : j); ++k) s += L[i * n + k] * L[j * n + k];
+      A[i * n + j] = s;
+    }
+  for (int64_t x = 0; x < m * n; ++x) X[x] = (double)(x % 11 - 5);
+  for (int64_t r = 0; r < m; ++r)
+    for (int64_t j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int64_t k = 0; k < n; ++k) s += X[r * n + k] * A[k * n + j];
+      Bm[r * n + j] = s;
+    }
+  int64_t info = -1;
+  ooc_stats st;
+  ooc_status s = ooc_potrf(n, A, n, (size_t)1 << 20, NULL, &info, &st);
+  if (s != OOC_OK || info != 0 || st.blocks_done < 3) {
+    fprintf(stderr, "ooc_potrf: %d info %lld panels %lld %s\n", (int)s, (long long)info, (long long)st.blocks_done,
+            ooc_last_error());
+    return 1;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j <= i; ++j)
+      if (A[i * n + j] != L[i * n + j]) {
+        fprintf(stderr, "factor mismatch at (%lld, %lld)\n", (long long)i, (long long)j);
+        return 1;
+      }
+  s = ooc_potrs(m, n, A, n, Bm, n, (size_t)1 << 20, NULL, &st);
+  if (s != OOC_OK) {
+    fprintf(stderr, "ooc_potrs: %d %s\n", (int)s, ooc_last_error());
+    return 1;
+  }
+  if (check(Bm, X, m * n)) return 1;
+  ooc_host_free(A);
+  ooc_host_free(Bm);
+  free(L);
+  free(X);
   return 0;
 }
 
@@ -63,6 +118,7 @@ int main(void) {
   ooc_host_free(C);
   free(C0);
   free(R);
+  if (cholesky()) return 6;
   ooc_release(-1);
   printf("ok\n");
   return 0;

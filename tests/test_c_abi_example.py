@@ -1,7 +1,8 @@
 """The C ABI from plain C: tests/c_abi/ooc_example.c is compiled with gcc
 against include/ooc.h and linked with the built library (no Python in the
 call path).  On the CPU only compiling and linking is checked; on the GPU the
-program runs a tiled product (FP64, then split-BF16 and split-INT8) and checks it exactly."""
+program runs a tiled product (FP64, then split-BF16 and split-INT8), a
+Cholesky factorisation and a Cholesky solve, and checks them exactly."""
 import os
 import subprocess
 
