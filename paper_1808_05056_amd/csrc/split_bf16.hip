@@ -100,34 +100,62 @@ __device__ __forceinline__ void slices_of(double r, int32_t e, uint32_t (&bits)[
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-// One wave per row of A: exponent, then the S slices of the row into the
-// planes, 8 consecutive k per lane and step (one 8 * EB-byte store per plane).
+// One workgroup per row of A, read from memory once: each thread holds up to
+// kRowChunks chunks of 8 consecutive k in registers (chunk c of thread t at k =
+// 8 (256 c + t)), the row's exponent comes from a workgroup reduction of the
+// maximum, and the S slices are written from the registers, one 8 * EB-byte
+// store per chunk and plane.  Every load reads an address inside the row
+// (clamped) and the value is then selected, so the loads are in flight
+// together.
+constexpr int kRowThreads = 256, kRowE = 8;
+constexpr int kRowChunks = (int)(kSplitMaxK / (kRowThreads * kRowE));
 template <int S, int EB>
-__global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const double* __restrict__ A, int64_t lda,
-                                                  int64_t mpad, int64_t kpad, uint8_t* __restrict__ planes,
-                                                  int32_t* __restrict__ ex_out) {
-  constexpr int E = 8, PER = 4 / EB, NW = E / PER;  // elements per lane and step, per 32-bit word; words
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= mpad) return;
+__global__ __launch_bounds__(kRowThreads) void split_rows(int64_t m, int64_t k, const double* __restrict__ A,
+                                                          int64_t lda, int64_t mpad, int64_t kpad,
+                                                          uint8_t* __restrict__ planes, int32_t* __restrict__ ex_out) {
+  constexpr int E = kRowE, PER = 4 / EB, NW = E / PER;  // elements per chunk, per 32-bit word; words
+  __shared__ double wmx[kRowThreads / 64];
+  __shared__ int wbad[kRowThreads / 64];
+  const int t = threadIdx.x, lane = t & 63;
+  const int64_t row = blockIdx.x;
   const bool live = row < m;
+  const double* src = A + (live ? row : m - 1) * lda;
+  double v[kRowChunks][E];
   double mx = 0.0;
   int bad = 0;
-  if (live) {
-    for (int64_t kk = lane; kk < k; kk += 64) {
-      const double v = A[row * lda + kk];
-      if (!isfinite(v)) bad = 1;
-      mx = fmax(mx, fabs(v));
+#pragma unroll
+  for (int c = 0; c < kRowChunks; ++c) {
+    const int64_t k0 = ((int64_t)c * kRowThreads + t) * E;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int64_t kk = k0 + q;
+      const double x = src[kk < k ? kk : k - 1];
+      v[c][q] = (live && kk < k) ? x : 0.0;
+      if (!isfinite(v[c][q])) bad = 1;
+      mx = fmax(mx, fabs(v[c][q]));
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
     mx = fmax(mx, __shfl_xor(mx, off));
     bad |= __shfl_xor(bad, off);
   }
+  if (lane == 0) {
+    wmx[t >> 6] = mx;
+    wbad[t >> 6] = bad;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < kRowThreads / 64; ++x) {
+    mx = fmax(mx, wmx[x]);
+    bad |= wbad[x];
+  }
   const int32_t ex = bad ? kBad : exponent_of(mx);
-  if (lane == 0) ex_out[row] = ex;
-  // kpad is a multiple of 64, so a lane's E values never cross it
-  for (int64_t k0 = (int64_t)lane * E; k0 < kpad; k0 += 64 * E) {
+  if (t == 0) ex_out[row] = ex;
+  // kpad is a multiple of 64, so a chunk never crosses it
+#pragma unroll
+  for (int c = 0; c < kRowChunks; ++c) {
+    const int64_t k0 = ((int64_t)c * kRowThreads + t) * E;
+    if (k0 >= kpad) break;
     uint32_t w[S][NW];
 #pragma unroll
     for (int p = 0; p < S; ++p)
@@ -135,12 +163,10 @@ __global__ __launch_bounds__(256) void split_rows(int64_t m, int64_t k, const do
       for (int x = 0; x < NW; ++x) w[p][x] = 0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-      const int64_t kk = k0 + q;
-      const double r = (live && !bad && kk < k) ? A[row * lda + kk] : 0.0;
-      uint32_t b[S];
-      slices_of<S, EB>(r, ex, b);
+      uint32_t bits[S];
+      slices_of<S, EB>(bad ? 0.0 : v[c][q], ex, bits);
 #pragma unroll
-      for (int p = 0; p < S; ++p) w[p][q / PER] |= b[p] << (8 * EB * (q % PER));
+      for (int p = 0; p < S; ++p) w[p][q / PER] |= bits[p] << (8 * EB * (q % PER));
     }
 #pragma unroll
     for (int p = 0; p < S; ++p) {
@@ -738,23 +764,24 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
   unsigned long long* bmax = reinterpret_cast<unsigned long long*>(fb + np);  // 8-byte aligned: mp, np even
   double* Sws = reinterpret_cast<double*>(bmax + np);
   if (gamma == 0.0) D = nullptr;
-  const dim3 rows_grid((unsigned)(mp / 4)), cols_grid((unsigned)(kp / 64), (unsigned)(np / 64));
+  if (kp > kSplitMaxK) return hipErrorInvalidValue;  // one K panel per call (split_rows holds a row)
+  const dim3 rows_grid((unsigned)mp), cols_grid((unsigned)(kp / 64), (unsigned)(np / 64));
   auto slice_a = [&](auto S) {
     constexpr int sv = decltype(S)::value;
     if (f == kSliceInt8)
-      hipLaunchKernelGGL((split_rows<sv, 1>), rows_grid, dim3(256), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
+      hipLaunchKernelGGL((split_rows<sv, 1>), rows_grid, dim3(kRowThreads), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
     else
-      hipLaunchKernelGGL((split_rows<sv, 2>), rows_grid, dim3(256), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
+      hipLaunchKernelGGL((split_rows<sv, 2>), rows_grid, dim3(kRowThreads), 0, stream, m, k, A, lda, mp, kp, Ap, ea);
   };
   // with transb the stored B^T (n x k) is sliced by rows, straight into the
   // transposed planes the slice-product kernels read
-  const dim3 brows_grid((unsigned)(np / 4));
+  const dim3 brows_grid((unsigned)np);
   auto slice_bt = [&](auto S) {
     constexpr int sv = decltype(S)::value;
     if (f == kSliceInt8)
-      hipLaunchKernelGGL((split_rows<sv, 1>), brows_grid, dim3(256), 0, stream, n, k, B, ldb, np, kp, Bp, fb);
+      hipLaunchKernelGGL((split_rows<sv, 1>), brows_grid, dim3(kRowThreads), 0, stream, n, k, B, ldb, np, kp, Bp, fb);
     else
-      hipLaunchKernelGGL((split_rows<sv, 2>), brows_grid, dim3(256), 0, stream, n, k, B, ldb, np, kp, Bp, fb);
+      hipLaunchKernelGGL((split_rows<sv, 2>), brows_grid, dim3(kRowThreads), 0, stream, n, k, B, ldb, np, kp, Bp, fb);
   };
   auto slice_b = [&](auto S) {
     constexpr int sv = decltype(S)::value;
