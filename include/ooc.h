@@ -284,6 +284,15 @@ typedef enum {
 #define OOC_OPF_LOWER 2
 /* Flag of TRSM ops: back substitution X <- X L^{-1} instead of X <- X L^{-T}. */
 #define OOC_OPF_BACK 4
+/* Flags of SPLIT_GEMM ops: the slices of the A (B) panel are still in the
+ * workspace, left there by the previous SPLIT_GEMM op of the list, so this op
+ * skips slicing that operand.  Allowed when that op had the same extents
+ * (rows, cols, k <= 8192), workspace, TRANSB flag and A (B) panel offset and
+ * leading dimension, and read the same data there: the caller vouches for the
+ * data, and orders the two ops (ooc_check_ops finds unordered uses of the
+ * workspace). */
+#define OOC_OPF_REUSE_A 8
+#define OOC_OPF_REUSE_B 16
 
 typedef struct {
   int32_t kind;               /* ooc_op_kind */
@@ -293,7 +302,8 @@ typedef struct {
   int32_t wait[OOC_MAX_WAITS];/* earlier ops (other streams) that must complete first */
   int32_t mat;                /* copies: host matrix index (ooc_gemm: 0 = A, 1 = B, 2 = C) */
   int32_t slot;               /* device buffer index within its operand's pool */
-  int32_t flags;              /* GEMM / SPLIT_GEMM: OOC_OPF_TRANSB, OOC_OPF_LOWER; TRSM: OOC_OPF_BACK */
+  int32_t flags;              /* GEMM: OOC_OPF_TRANSB, OOC_OPF_LOWER; SPLIT_GEMM: OOC_OPF_TRANSB,
+                                 OOC_OPF_REUSE_A, OOC_OPF_REUSE_B; TRSM: OOC_OPF_BACK */
   int32_t reserved;           /* 0 */
   int64_t row0, col0;         /* copies: host submatrix origin; GEMM: C block origin (i0, j0) */
   int64_t rows, cols;         /* copies: submatrix extent; GEMM: m, n */

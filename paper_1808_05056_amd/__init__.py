@@ -37,7 +37,7 @@ OP_H2D, OP_D2H, OP_GEMM, OP_SPLIT_GEMM, OP_POTRF, OP_TRSM = range(6)
 OP_NAMES = {0: "h2d", 1: "d2h", 2: "gemm", 3: "split_gemm", 4: "potrf", 5: "trsm"}
 OP_KINDS = {v: k for k, v in OP_NAMES.items()}
 MAX_WAITS = 6
-OPF_TRANSB, OPF_LOWER, OPF_BACK = 1, 2, 4
+OPF_TRANSB, OPF_LOWER, OPF_BACK, OPF_REUSE_A, OPF_REUSE_B = 1, 2, 4, 8, 16
 
 i32, i64, u64, dbl, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -478,7 +478,8 @@ def _ops_as_dicts(arr, count):
             d.update(m=o.rows, n=o.cols, k=o.k, i0=o.row0, j0=o.col0, k0=o.k0, off_a=o.off_a, lda=o.ld_a,
                      off_b=o.off_b, ldb=o.ld_b, off_c=o.off_c, ldc=o.ld_c, off_d=o.off_d, ldd=o.ld_d,
                      off_w=o.off_w, len_w=o.len_w, alpha=o.alpha, beta=o.beta, gamma=o.gamma,
-                     transb=bool(o.flags & OPF_TRANSB), lower=bool(o.flags & OPF_LOWER))
+                     transb=bool(o.flags & OPF_TRANSB), lower=bool(o.flags & OPF_LOWER),
+                     reuse_a=bool(o.flags & OPF_REUSE_A), reuse_b=bool(o.flags & OPF_REUSE_B))
         ops.append(d)
     return ops
 

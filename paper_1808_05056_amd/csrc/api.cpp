@@ -267,7 +267,8 @@ ooc_status run_ops(DevCtx& c, hipStream_t* streams, const RunCfg& plan, const st
           e = launch_split_gemm(slice_format(plan.precision), o.rows, o.cols, o.k, plan.slices, o.alpha,
                                 arena + o.off_a, o.ld_a, arena + o.off_b, o.ld_b, o.beta, arena + o.off_c, o.ld_c,
                                 o.gamma, arena + o.off_d, o.ld_d, arena + o.off_w, (size_t)o.len_w * 8, s,
-                                profile ? &kt : nullptr, (o.flags & OOC_OPF_TRANSB) != 0);
+                                profile ? &kt : nullptr, (o.flags & OOC_OPF_TRANSB) != 0,
+                                (o.flags & OOC_OPF_REUSE_A) != 0, (o.flags & OOC_OPF_REUSE_B) != 0);
           break;
         }
         case OOC_OP_POTRF:

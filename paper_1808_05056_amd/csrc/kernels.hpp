@@ -48,7 +48,8 @@ inline int64_t split_launches(int64_t k) { return k <= 0 ? 0 : (k + kSplitMaxK -
 hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                              double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                             hipStream_t stream, KernelTimer* timer = nullptr, bool transb = false);
+                             hipStream_t stream, KernelTimer* timer = nullptr, bool transb = false,
+                             bool reuse_a = false, bool reuse_b = false);
 
 // The planner network (see mlp.hip): parameter count, scratch size (floats)
 // for a batch of n, forward pass into y, loss and gradient, one Adam step.

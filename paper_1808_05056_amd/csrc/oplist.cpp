@@ -101,6 +101,7 @@ ooc_status validate_ops(const ooc_op* ops, int64_t n, const ooc_host_matrix* mat
       return fail(OOC_ERR_ARG, "host matrix " + std::to_string(m) + " malformed");
   int ns = 1;
   std::vector<Region> rd, wr;
+  int64_t prev_split = -1;  // the last SPLIT_GEMM op before x (slice reuse)
   for (int64_t x = 0; x < n; ++x) {
     const ooc_op& o = ops[x];
     if (o.kind < OOC_OP_H2D || o.kind > OOC_OP_TRSM) return bad_op(x, "unknown kind");
@@ -118,7 +119,9 @@ ooc_status validate_ops(const ooc_op* ops, int64_t n, const ooc_host_matrix* mat
       if (o.ld_c < o.cols) return bad_op(x, "device leading dimension below the copy width");
     }
     if (o.kind == OOC_OP_GEMM || o.kind == OOC_OP_SPLIT_GEMM) {
-      if (o.flags & ~(OOC_OPF_TRANSB | OOC_OPF_LOWER)) return bad_op(x, "unknown flags");
+      const int32_t known = o.kind == OOC_OP_GEMM ? (OOC_OPF_TRANSB | OOC_OPF_LOWER)
+                                                  : (OOC_OPF_TRANSB | OOC_OPF_LOWER | OOC_OPF_REUSE_A | OOC_OPF_REUSE_B);
+      if (o.flags & ~known) return bad_op(x, "unknown flags");
       if (o.ld_c < o.cols || (o.k > 0 && (o.ld_a < o.k || o.ld_b < ((o.flags & OOC_OPF_TRANSB) ? o.k : o.cols))) ||
           (o.gamma != 0.0 && o.ld_d < o.cols))
         return bad_op(x, "leading dimension below the block width");
@@ -129,6 +132,18 @@ ooc_status validate_ops(const ooc_op* ops, int64_t n, const ooc_host_matrix* mat
         if (slices < 1 || slices > 8) return bad_op(x, "split product needs 1..8 slices");
         if (o.k > 0 && (uint64_t)o.len_w * 8 < split_workspace_bytes(o.rows, o.cols, o.k, slices, slice_format(precision)))
           return bad_op(x, "split workspace too small");
+        if (o.flags & (OOC_OPF_REUSE_A | OOC_OPF_REUSE_B)) {
+          if (prev_split < 0) return bad_op(x, "slice reuse without an earlier split product");
+          const ooc_op& p = ops[prev_split];
+          if (p.rows != o.rows || p.cols != o.cols || p.k != o.k || o.k <= 0 || o.k > kSplitMaxK ||
+              p.off_w != o.off_w || p.len_w != o.len_w || ((p.flags ^ o.flags) & OOC_OPF_TRANSB))
+            return bad_op(x, "slice reuse needs the previous split product's extents, workspace and form");
+          if ((o.flags & OOC_OPF_REUSE_A) && (p.off_a != o.off_a || p.ld_a != o.ld_a))
+            return bad_op(x, "A slices reused from another panel");
+          if ((o.flags & OOC_OPF_REUSE_B) && (p.off_b != o.off_b || p.ld_b != o.ld_b))
+            return bad_op(x, "B slices reused from another panel");
+        }
+        prev_split = x;
       }
     }
     if (o.kind == OOC_OP_POTRF && o.ld_c < o.rows) return bad_op(x, "leading dimension below the block size");

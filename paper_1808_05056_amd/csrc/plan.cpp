@@ -168,7 +168,8 @@ bool paper_plan(const Problem& pb, uint64_t budget_bytes, ooc_plan_t* plan, int 
 
 // ---- cost model --------------------------------------------------------------------
 
-static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k, int precision, int slices) {
+static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k, int precision, int slices,
+                             int32_t flags = 0) {
   if (m <= 0 || n <= 0) return mc.kernel_launch_s;
   const double tiles = (double)ceil_div(m, 128) * (double)ceil_div(n, 128);
   if (k <= 0) return mc.kernel_launch_s + (double)m * n * 16.0 / 4e12;
@@ -206,7 +207,10 @@ static double kernel_seconds(const Machine& mc, int64_t m, int64_t n, int64_t k,
     const double rate = !i8 ? mc.split_tflops_per_product
                             : (wide ? mc.int8_wide_tops_per_product : mc.int8_tops_per_product);
     const double ts = std::ceil(stiles / mc.cus) * stile / (rate * 1e12 / mc.cus);
-    const double slice_s = (mp + np) * k * (8.0 + (double)slice_format(precision) * slices) / 4e12;
+    // slicing reads a panel and writes its planes; a panel whose slices the
+    // previous product left in the workspace is not sliced again
+    const double sliced = ((flags & OOC_OPF_REUSE_A) ? 0.0 : mp) + ((flags & OOC_OPF_REUSE_B) ? 0.0 : np);
+    const double slice_s = sliced * k * (8.0 + (double)slice_format(precision) * slices) / 4e12;
     // the FP64 slice-sum tile is read and written once per weight (s weights)
     const double sum_s = (double)slices * 16.0 * mp * np / mc.hbm_bytes_per_s;
     return mc.kernel_launch_s * 6 + slice_s + sum_s + ts;
@@ -231,7 +235,7 @@ double simulate(const Problem& pb, const ooc_plan_t& plan, const std::vector<ooc
     else {
       cls[x] = 2;
       work[x] = kernel_seconds(mc, o.rows, o.cols, o.k, o.kind == OOC_OP_SPLIT_GEMM ? plan.precision : OOC_FP64,
-                               plan.slices);
+                               plan.slices, o.flags);
     }
   }
   const int ns = plan.nstreams;

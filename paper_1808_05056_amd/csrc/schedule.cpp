@@ -20,6 +20,7 @@
 #include <string>
 
 #include "internal.hpp"
+#include "kernels.hpp"
 
 namespace ooc {
 
@@ -243,6 +244,7 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
   };
 
   int last_ws = -1;  // last split op, which used the (single) slice workspace
+  int64_t prev_split = -1;  // its task
   for (int64_t t = 0; t < T; ++t) {
     const Task& tk = tasks[t];
     const int64_t i0 = tk.i * mb, m = std::min(mb, M - i0);
@@ -361,6 +363,18 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
       g.off_b = lay.offB + sb * lay.slotB; g.ld_b = pb.transb ? k : n;
     }
     g.flags = (pb.transb ? OOC_OPF_TRANSB : 0) | (pb.lower ? OOC_OPF_LOWER : 0);
+    if (split && prev_split >= 0 && k <= kSplitMaxK) {
+      // the previous split product left the slices of its panels in the
+      // workspace: a panel it shares with this task (same extents) is not
+      // sliced again
+      const Task& pt = tasks[prev_split];
+      const int64_t pm = std::min(mb, M - pt.i * mb), pn = std::min(nb, N - pt.j * nb);
+      const int64_t pk = std::min(kb, K - pt.p * kb);
+      if (pm == m && pn == n && pk == k) {
+        if (ka[prev_split] == ka[t]) g.flags |= OOC_OPF_REUSE_A;
+        if (kbk[prev_split] == kbk[t]) g.flags |= OOC_OPF_REUSE_B;
+      }
+    }
     if (resident) {
       g.slot = -1;
       g.off_c = i0 * pb.c_ld + j0;
@@ -386,7 +400,10 @@ ooc_status build_schedule(const Problem& pb, const ooc_plan_t& plan, const Layou
     if (fold_here) gw.push_back(pd.load_op[sd]);
     if (split) gw.push_back(last_ws);
     int gx = push(g, gw);
-    if (split) last_ws = gx;
+    if (split) {
+      last_ws = gx;
+      prev_split = t;
+    }
     if (gx < 0) return fail(OOC_ERR_ARG, "schedule: too many waits");
     if (K > 0) {
       pa.readers[sa][ops[gx].stream] = gx;

@@ -719,24 +719,27 @@ size_t split_workspace_bytes(int64_t m, int64_t n, int64_t k, int s, SliceFormat
 static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                               double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                              hipStream_t stream, KernelTimer* timer, bool transb);
+                              hipStream_t stream, KernelTimer* timer, bool transb, bool reuse_a, bool reuse_b);
 
 hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                              int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                              double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                             hipStream_t stream, KernelTimer* timer, bool transb) {
-  // K panels of at most kSplitMaxK: C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C
+                             hipStream_t stream, KernelTimer* timer, bool transb, bool reuse_a, bool reuse_b) {
+  // K panels of at most kSplitMaxK: C = alpha*S_0 + beta*C + gamma*D, then C = alpha*S_p + C.
+  // reuse_a / reuse_b: the workspace still holds the slices of this A / B
+  // panel (one K panel only), from the previous product on it
   if (m <= 0 || n <= 0) return hipSuccess;
   if (f != kSliceBF16 && f != kSliceInt8) return hipErrorInvalidValue;
   if (k <= kSplitMaxK)
     return split_panel(f, m, n, k, s, alpha, A, lda, B, ldb, beta, C, ldc, gamma, D, ldd, workspace, ws_bytes, stream,
-                       timer, transb);
+                       timer, transb, reuse_a, reuse_b);
+  if (reuse_a || reuse_b) return hipErrorInvalidValue;
   for (int64_t k0 = 0; k0 < k; k0 += kSplitMaxK) {
     const int64_t kk = (k - k0) < kSplitMaxK ? (k - k0) : kSplitMaxK;
     const bool first = k0 == 0;
     hipError_t e = split_panel(f, m, n, kk, s, alpha, A + k0, lda, transb ? B + k0 : B + k0 * ldb, ldb,
                                first ? beta : 1.0, C, ldc, first ? gamma : 0.0, D, ldd, workspace, ws_bytes, stream,
-                               timer, transb);
+                               timer, transb, false, false);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -745,7 +748,7 @@ hipError_t launch_split_gemm(SliceFormat f, int64_t m, int64_t n, int64_t k, int
 static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, int s, double alpha, const double* A,
                               int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                               double gamma, const double* D, int64_t ldd, void* workspace, size_t ws_bytes,
-                              hipStream_t stream, KernelTimer* timer, bool transb) {
+                              hipStream_t stream, KernelTimer* timer, bool transb, bool reuse_a, bool reuse_b) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (s < 1 || s > 8) return hipErrorInvalidValue;
   if (k <= 0) return launch_dgemm_f64(m, n, 0, alpha, nullptr, 1, nullptr, 1, beta, C, ldc, gamma, D, ldd, stream);
@@ -802,8 +805,9 @@ static hipError_t split_panel(SliceFormat f, int64_t m, int64_t n, int64_t k, in
       default: fn(std::integral_constant<int, 8>{}); break;
     }
   };
-  with_s(slice_a);
-  if (transb) {
+  if (!reuse_a) with_s(slice_a);
+  if (reuse_b) {
+  } else if (transb) {
     with_s(slice_bt);
   } else {
     hipLaunchKernelGGL(zero_u64, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, stream,

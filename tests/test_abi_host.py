@@ -273,14 +273,26 @@ def test_split_schedule_race_free(case):
     A, B, C = _problem(M, N, K, 30 + case)
     want, _ = oracle.gemm_rows(1.0, A, B, 0.5, C)
 
+    # the workspace: the panels whose slices the last split product left there;
+    # a product flagged to reuse them takes them from here, not from the arena,
+    # so a wrong flag gives a wrong result
+    ws = {}
+
     def split_model(op, ar):
         def view(off, r, c, ld):
             return np.lib.stride_tricks.as_strided(ar[off:], shape=(r, c), strides=(ld * 8, 8))
-        a = view(op["off_a"], op["m"], op["k"], op["lda"])
-        b = view(op["off_b"], op["k"], op["n"], op["ldb"])
+        a = np.array(view(op["off_a"], op["m"], op["k"], op["lda"]))
+        b = np.array(view(op["off_b"], op["k"], op["n"], op["ldb"]))
         c = view(op["off_c"], op["m"], op["n"], op["ldc"])
+        if op["reuse_a"]:
+            assert ws["a"].shape == a.shape
+            a = ws["a"]
+        if op["reuse_b"]:
+            assert ws["b"].shape == b.shape
+            b = ws["b"]
+        ws["a"], ws["b"] = a, b
         fmt = "i8" if plan.precision == ooc.SPLIT_INT8 else "bf16"
-        res = op["alpha"] * split_ref.slice_sum(np.array(a), np.array(b), plan.slices, fmt)
+        res = op["alpha"] * split_ref.slice_sum(a, b, plan.slices, fmt)
         if op["beta"] != 0.0:
             res = res + op["beta"] * c
         if op["gamma"] != 0.0:
@@ -290,8 +302,31 @@ def test_split_schedule_race_free(case):
 
     for seed in range(4):
         Cw = C.copy()
+        ws.clear()
         sched_ref.execute(ops, A, B, Cw, arena, seed=seed, kernels={"split_gemm": split_model})
         assert np.array_equal(Cw, want)
+
+
+def test_split_schedules_reuse_the_slices_of_shared_panels():
+    # consecutive products on one A panel (rows in groups) or one B panel
+    # (a column without a K split) slice it once; edge blocks of other extents,
+    # and K panels walked inside a block, do not reuse
+    counts = []
+    for M, N, K, plan in SPLIT_PLANS:
+        ops, _ = ooc.ooc_schedule(M, N, K, 1.0, 0.5, plan)
+        sp = [op for op in ops if op["kind"] == "split_gemm"]
+        counts.append((sum(op["reuse_a"] for op in sp), sum(op["reuse_b"] for op in sp)))
+        prev = None
+        for op in sp:
+            if op["reuse_a"] or op["reuse_b"]:
+                assert prev is not None and (prev["m"], prev["n"], prev["k"]) == (op["m"], op["n"], op["k"])
+            if op["reuse_a"]:
+                assert (prev["off_a"], prev["lda"]) == (op["off_a"], op["lda"])
+            if op["reuse_b"]:
+                assert (prev["off_b"], prev["ldb"]) == (op["off_b"], op["ldb"])
+            prev = op
+    assert counts[0] == (0, 12) and counts[3][0] == 40 and counts[5] == (40, 0)
+    assert counts[2] == (0, 0) and counts[4] == (0, 0)
 
 
 def test_split_footprint_counts_workspace():

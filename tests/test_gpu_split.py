@@ -160,3 +160,36 @@ def test_split_pipeline_edge_cases(case):
         gate_errors(pp.C, ref, alpha, D, beta, Cin)
     finally:
         pp.free()
+
+
+@pytest.mark.parametrize("prec,slices,order", [(ooc.SPLIT_BF16, 6, ooc.ORDER_ROWS), (ooc.SPLIT_BF16, 6, ooc.ORDER_COLS),
+                                               (ooc.SPLIT_BF16, 6, ooc.ORDER_ROWS_P),
+                                               (ooc.SPLIT_INT8, 7, ooc.ORDER_ROWS_P)])
+def test_split_pipeline_reuses_slices_bit_exact(prec, slices, order):
+    """Consecutive products on one A panel (ROWS, ROWS_P in groups) or one B
+    panel (COLS) take its slices from the workspace instead of slicing it
+    again; the result is the split reference's bit for bit."""
+    w = W.Workload("split-reuse", 1000, 900, 1100, 1.5, 0.5, 0, seed=24, dist_a=synth.NORMAL,
+                   dist_b=synth.NORMAL, a_row_exp=(-20, 20), b_col_exp=(-20, 20))
+    if order == ooc.ORDER_ROWS_P:
+        plan = ooc.make_plan(256, 320, 320, order, 2, 4, 3, 3, precision=prec, slices=slices, group=2)
+    elif order == ooc.ORDER_ROWS:
+        plan = ooc.make_plan(256, 320, 1100, order, 1, 2, 2, 3, precision=prec, slices=slices)
+    else:
+        plan = ooc.make_plan(256, 320, 1100, order, 2, 1, 2, 3, precision=prec, slices=slices)
+    ops, _ = ooc.ooc_schedule(w.M, w.N, w.K, w.alpha, w.beta, plan)
+    reused = sum(op["reuse_a"] or op["reuse_b"] for op in ops if op["kind"] == "split_gemm")
+    assert reused >= 4
+    budget = ooc.ooc_plan_footprint(w.M, w.N, w.K, w.beta, plan)
+    pp = PinnedProblem(w)
+    try:
+        C0 = pp.C.copy()
+        _, stats = ooc.ooc_gemm_planned(w.alpha, pp.A, pp.B, w.beta, pp.C, budget, plan)
+        _say(f"split reuse {prec} order {order}: {reused} products reuse slices, t {stats.t_total_s * 1e3:.1f} ms")
+        fmt = "i8" if prec == ooc.SPLIT_INT8 else "bf16"
+        want = split_ref.split_gemm(w.alpha, pp.A, pp.B, w.beta, C0, slices, kb=plan.kb, fmt=fmt)
+        assert np.array_equal(pp.C, want)
+        ref, D = oracle.gemm_rows(w.alpha, pp.A, pp.B, w.beta, C0)
+        gate_errors(pp.C, ref, w.alpha, D, w.beta, C0)
+    finally:
+        pp.free()

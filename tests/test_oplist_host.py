@@ -149,3 +149,45 @@ def test_trsm_op_flags(flags, ok):
         assert ooc.ooc_check_ops(ops)[0] == ooc.OOC_OK
     else:
         assert st == ooc.OOC_ERR_ARG, ooc.ooc_last_error()
+
+
+def _split_pair(first_flags=0, second_flags=ooc.OPF_REUSE_A | ooc.OPF_REUSE_B, second=None):
+    # A (4 x 3) at 0, its copy at 12, B (3 x 5) at 24, C (4 x 5) at 39, the
+    # slice workspace after it; two split products on the same panels
+    W = 45376  # workspace elements for 4 x 5 x 3 at s = 2 (BF16 planes padded to 256 x 128 x 64)
+    ops = [ooc.make_op("h2d", 0, mat=0, rows=4, cols=3, off_c=0, ld_c=3),
+           ooc.make_op("h2d", 0, mat=0, rows=4, cols=3, off_c=12, ld_c=3),
+           ooc.make_op("h2d", 0, mat=1, rows=3, cols=5, off_c=24, ld_c=5)]
+    prod = dict(rows=4, cols=5, k=3, off_a=0, ld_a=3, off_b=24, ld_b=5, off_c=39, ld_c=5, alpha=1.0, beta=0.0,
+                off_w=59, len_w=W)
+    ops.append(ooc.make_op("split_gemm", 1, waits=[0, 1, 2], flags=first_flags, **prod))
+    prod2 = dict(prod, beta=1.0, flags=second_flags)
+    prod2.update(second or {})
+    ops.append(ooc.make_op("split_gemm", 1, **prod2))
+    ops.append(ooc.make_op("d2h", 2, waits=[4], mat=2, rows=4, cols=5, off_c=39, ld_c=5))
+    return ops, (59 + W) * 8
+
+
+@pytest.mark.parametrize("case,ok", [("reuse_both", True), ("reuse_a", True), ("first_op", False),
+                                     ("other_a_panel", False), ("other_k", False), ("fp64_flag", False)])
+def test_split_slice_reuse_flags(case, ok):
+    mats = [np.zeros((4, 3)), np.zeros((3, 5)), np.zeros((4, 5))]
+    if case == "reuse_both":
+        ops, arena = _split_pair()
+    elif case == "reuse_a":
+        ops, arena = _split_pair(second_flags=ooc.OPF_REUSE_A)
+    elif case == "first_op":
+        ops, arena = _split_pair(first_flags=ooc.OPF_REUSE_A)
+    elif case == "other_a_panel":  # the same values, but another panel of the arena
+        ops, arena = _split_pair(second_flags=ooc.OPF_REUSE_A, second=dict(off_a=12))
+    elif case == "other_k":
+        ops, arena = _split_pair(second=dict(k=2))
+    else:
+        ops, arena = _split_pair()
+        ops[4].kind = ooc.OP_GEMM
+    opts = ooc.make_opts(precision=ooc.SPLIT_BF16, slices=2)
+    st, _ = ooc.ooc_run_ops(ops, mats, arena, opts=opts, raise_on_error=False)
+    if ok:
+        assert st in (ooc.OOC_ERR_NO_DEVICE, ooc.OOC_ERR_NOT_PINNED), ooc.ooc_last_error()
+    else:
+        assert st == ooc.OOC_ERR_ARG, ooc.ooc_last_error()
