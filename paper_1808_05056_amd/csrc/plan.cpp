@@ -340,7 +340,9 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
   const int slices = (opts && opts->slices > 0) ? opts->slices : 6;
   const int want_streams = opts ? opts->nstreams : 0;
   const Machine& mc = machine();
-  struct Cand { ooc_plan_t p; double lb; };
+  // lb: the analytic lower bound; tie: link plus kernel time, which orders
+  // the many candidates of a link-bound problem that share one bound
+  struct Cand { ooc_plan_t p; double lb, tie; };
   std::vector<Cand> cands;
   std::vector<int> stream_opts = {1, 2, 3};
   if (want_streams >= 1 && want_streams <= 3) stream_opts = {want_streams};
@@ -387,7 +389,7 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
     // the bound does not depend on the stream count: one entry per count
     for (int ns : stream_opts) {
       p.nstreams = ns;
-      cands.push_back({p, std::max(t_link, t_comp)});
+      cands.push_back({p, std::max(t_link, t_comp), t_link + t_comp});
     }
   };
   const int max_parts = 64;
@@ -471,10 +473,11 @@ ooc_status plan_candidates(const Problem& pb, uint64_t budget_bytes, const ooc_o
   if (cands.empty()) {
     // the paper's partition covers every budget its footprint rule allows
     ooc_plan_t pp{};
-    if (paper_plan(pb, budget_bytes, &pp, prec, slices)) cands.push_back({pp, 0.0});
+    if (paper_plan(pb, budget_bytes, &pp, prec, slices)) cands.push_back({pp, 0.0, 0.0});
   }
   if (cands.empty()) return fail(OOC_ERR_BUDGET, "no plan fits in the device budget");
-  std::sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.lb < b.lb; });
+  std::stable_sort(cands.begin(), cands.end(),
+                   [](const Cand& a, const Cand& b) { return a.lb < b.lb || (a.lb == b.lb && a.tie < b.tie); });
   // simulate the most promising candidates, spread over host threads; fewer
   // for products that take milliseconds, where planning time would show, and
   // fewer when the schedules are long (about 3 million simulated operations
