@@ -27,7 +27,7 @@ namespace ooc {
 namespace {
 
 constexpr int kLeaf = 64;   // potrf leaf: one wave, row l of the block in lane l's registers
-constexpr int kLeafT = 64;  // trsm leaf: one wave per 64 rows of X, a row in each lane's registers
+constexpr int kLeafT = 64;  // trsm leaf: 64 columns, one wave of 64 lanes
 constexpr int kBatch = 16;  // L values read from LDS together by the leaves
 
 // v from lane `lane` (wave-uniform), read into scalar registers.
@@ -105,26 +105,43 @@ __global__ __launch_bounds__(64) void potrf_leaf(int n, double* __restrict__ A, 
 }
 
 // X <- X L^{-T} (forward, BACK false) or X <- X L^{-1} (BACK true) for X
-// (m x n, n <= 64): lane l of a wave holds row l of a 64-row block of X in
-// registers and substitutes right-looking.  Forward: for k = 0, 1, ...:
-// x_k = x_k / L_kk, then x_j = x_j - x_k L_jk for j > k.  Backward: for k =
-// n-1, n-2, ...: x_k = x_k / L_kk, then x_j = x_j - x_k L_kj for j < k.  The
-// updates of one k are independent (unlike the chained sums of the
-// left-looking form, whose operations they repeat in the same order).  The
-// L values of one k (column k of L forward, row k backward) sit in a row of
-// LDS, read by every lane at once (broadcasts), identity beyond n; the rows
-// of X move through LDS so that the global accesses are row-contiguous.
+// (m x n, n <= 64): a wave holds 16 rows of X, four lanes per row, lane q of
+// a row holding its columns 16q .. 16q+15 in registers, and substitutes
+// right-looking.  Forward: for k = 0, 1, ...: x_k = x_k / L_kk, then x_j =
+// x_j - x_k L_jk for j > k.  Backward: for k = n-1, n-2, ...: x_k = x_k /
+// L_kk, then x_j = x_j - x_k L_kj for j < k.  The lane holding column k
+// divides, the quotient goes to the row's other lanes by a DPP quad
+// broadcast, and every lane updates its columns (the updates of one k are
+// independent).  Four lanes per row give a launch four times the waves of
+// one lane per row (the chunks of a panel's rows run a few thousand rows per
+// launch).  The L values of one k (column k of L forward, row k backward) sit
+// in a row of LDS, identity beyond n, each 16-column segment padded by one
+// word so that the four lanes of a row read distinct banks; the rows of X
+// move through LDS so that the global accesses are row-contiguous.
+constexpr int kLeafRows = 16;  // rows of X per trsm leaf wave
+__device__ __forceinline__ int lseg(int j) { return j + (j >> 4); }
+
+// v from lane Q of each quad of lanes, to every lane of that quad.
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctrl = Q | (Q << 2) | (Q << 4) | (Q << 6);  // quad_perm [Q, Q, Q, Q]
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 template <bool BACK>
 __device__ __forceinline__ void trsm_leaf_body(int64_t m, int n, double* __restrict__ X, int64_t ldx,
                                                const double* __restrict__ L, int64_t ldl) {
-  __shared__ double lt[kLeafT][kLeafT];      // forward lt[k][j] = L_jk, backward lt[k][j] = L_kj
-  __shared__ double xs[kLeafT][kLeafT + 1];  // the block's rows
-  const int l = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * kLeafT;
+  __shared__ double lt[kLeafT][kLeafT + 4];        // forward lt[k][lseg(j)] = L_jk, backward L_kj
+  __shared__ double xs[kLeafRows][kLeafT + 1];     // the block's rows
+  const int l = threadIdx.x, r = l >> 2, q = l & 3;
+  const int64_t row0 = (int64_t)blockIdx.x * kLeafRows;
   {
     // every lane loads from an address inside L and X (clamped) and then
     // selects, so that the loads are all in flight at once; lane l reads
-    // column l of L, v[j] = L_jl
+    // column l of L, v[j] = L_jl, and column l of the block's rows
     const int lc = l < n ? l : n - 1;
     double v[kLeafT];
 #pragma unroll
@@ -133,43 +150,47 @@ __device__ __forceinline__ void trsm_leaf_body(int64_t m, int n, double* __restr
     for (int j = 0; j < kLeafT; ++j) {
       const double e = (j < n && l <= j) ? v[j] : (j == l ? 1.0 : 0.0);
       if (BACK)
-        lt[j][l] = e;
+        lt[j][lseg(l)] = e;
       else
-        lt[l][j] = e;
+        lt[l][lseg(j)] = e;
     }
+    double w[kLeafRows];
 #pragma unroll
-    for (int r = 0; r < kLeafT; ++r) v[r] = X[(row0 + r < m ? row0 + r : m - 1) * ldx + lc];
+    for (int rr = 0; rr < kLeafRows; ++rr) w[rr] = X[(row0 + rr < m ? row0 + rr : m - 1) * ldx + lc];
 #pragma unroll
-    for (int r = 0; r < kLeafT; ++r) xs[r][l] = (row0 + r < m && l < n) ? v[r] : 0.0;
+    for (int rr = 0; rr < kLeafRows; ++rr) xs[rr][l] = (row0 + rr < m && l < n) ? w[rr] : 0.0;
   }
   __syncthreads();
-  double x[kLeafT];
+  double x[16];
 #pragma unroll
-  for (int j = 0; j < kLeafT; ++j) x[j] = xs[l][j];
+  for (int t = 0; t < 16; ++t) x[t] = xs[r][16 * q + t];
 #pragma clang loop unroll(full)
   for (int i = 0; i < kLeafT; ++i) {
     const int k = BACK ? kLeafT - 1 - i : i;
-    x[k] = x[k] / lt[k][k];
-    // the L values of k in batches of 16 words: the batch's LDS reads are in
-    // flight together before its updates
-    const int jlo = BACK ? 0 : k + 1, jhi = BACK ? k : kLeafT;
-#pragma clang loop unroll(full)
-    for (int j0 = jlo; j0 < jhi; j0 += kBatch) {
-      double lv[kBatch];
+    const int qk = k >> 4, c = k & 15;
+    const double own = x[c] / lt[k][lseg(k)];  // the quotient, in the lanes that hold column k
+    double xk;
+    switch (qk) {
+      case 0: xk = quad_bcast<0>(own); break;
+      case 1: xk = quad_bcast<1>(own); break;
+      case 2: xk = quad_bcast<2>(own); break;
+      default: xk = quad_bcast<3>(own); break;
+    }
+    if (q == qk) x[c] = xk;
+    double lv[16];
 #pragma unroll
-      for (int t = 0; t < kBatch; ++t)
-        if (j0 + t < jhi) lv[t] = lt[k][j0 + t];
+    for (int t = 0; t < 16; ++t) lv[t] = lt[k][lseg(16 * q + t)];
 #pragma unroll
-      for (int t = 0; t < kBatch; ++t)
-        if (j0 + t < jhi) x[j0 + t] = x[j0 + t] - x[k] * lv[t];
+    for (int t = 0; t < 16; ++t) {
+      const int j = 16 * q + t;
+      if (BACK ? j < k : j > k) x[t] = x[t] - xk * lv[t];
     }
   }
-  __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kLeafT; ++j) xs[l][j] = x[j];
+  for (int t = 0; t < 16; ++t) xs[r][16 * q + t] = x[t];
   __syncthreads();
-  for (int r = 0; r < kLeafT; ++r)
-    if (row0 + r < m && l < n) X[(row0 + r) * ldx + l] = xs[r][l];
+  for (int rr = 0; rr < kLeafRows; ++rr)
+    if (row0 + rr < m && l < n) X[(row0 + rr) * ldx + l] = xs[rr][l];
 }
 
 __global__ __launch_bounds__(64) void trsm_leaf(int64_t m, int n, double* __restrict__ X, int64_t ldx,
@@ -194,7 +215,7 @@ hipError_t launch_trsm_rlt(int64_t m, int64_t n, double* X, int64_t ldx, const d
                            hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (n <= kLeafT) {
-    hipLaunchKernelGGL(trsm_leaf, dim3((unsigned)((m + kLeafT - 1) / kLeafT)), dim3(kLeafT), 0, s, m, (int)n, X,
+    hipLaunchKernelGGL(trsm_leaf, dim3((unsigned)((m + kLeafRows - 1) / kLeafRows)), dim3(kLeafT), 0, s, m, (int)n, X,
                        ldx, L, ldl);
     return hipGetLastError();
   }
@@ -211,7 +232,7 @@ hipError_t launch_trsm_rln(int64_t m, int64_t n, double* X, int64_t ldx, const d
                            hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (n <= kLeafT) {
-    hipLaunchKernelGGL(trsm_leaf_back, dim3((unsigned)((m + kLeafT - 1) / kLeafT)), dim3(kLeafT), 0, s, m, (int)n,
+    hipLaunchKernelGGL(trsm_leaf_back, dim3((unsigned)((m + kLeafRows - 1) / kLeafRows)), dim3(kLeafT), 0, s, m, (int)n,
                        X, ldx, L, ldl);
     return hipGetLastError();
   }
