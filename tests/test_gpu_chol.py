@@ -309,6 +309,31 @@ def test_trsm_back_integer_solution_exact(m, n, budget):
         ooc.ooc_release(-1)
 
 
+@pytest.mark.parametrize("m", [1, 15, 17])
+def test_solves_with_few_right_hand_sides_exact(m):
+    # fewer rows than one solve-leaf wave holds (16), and one more: both
+    # triangular forms and the Cholesky solve stay exact on integer data
+    n = 300
+    L = _int_factor(n, 77)
+    Y = np.random.default_rng(m + 5).integers(-9, 10, (m, n)).astype(np.float64)
+    PL = _pinned(L)
+    PX = _pinned(Y @ L.T)
+    try:
+        ooc.ooc_trsm_ex(PL.array, PX.array, 1 * MiB, trans=1)
+        assert np.array_equal(PX.array, Y)
+        PX.array[...] = Y @ L
+        ooc.ooc_trsm_ex(PL.array, PX.array, 1 * MiB, trans=0)
+        assert np.array_equal(PX.array, Y)
+        PX.array[...] = Y @ (L @ L.T)
+        _, st = ooc.ooc_potrs(PL.array, PX.array, 1 * MiB)
+        _say(f"solves with {m} right-hand sides of {n}: panels {st.blocks_done}")
+        assert np.array_equal(PX.array, Y)
+    finally:
+        PL.free()
+        PX.free()
+        ooc.ooc_release(-1)
+
+
 def test_trsm_back_and_potrs_random_against_the_oracle():
     m, n = 1800, 1400
     rng = np.random.default_rng(29)
