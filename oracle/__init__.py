@@ -11,7 +11,9 @@ Contents
                  executor/hazard checker for an operation list
   split_ref.py   the split-BF16 product (error-free slicing, Ozaki et al. 2012)
   mlp_ref.py     the MLP planner network: forward, backward, MSE, Adam in FP64
-  chol_ref.py    Cholesky factorisation and symmetric rank-k update (plain definitions)
+  chol_ref.py    Cholesky factorisation, symmetric rank-k update, forward and back
+                 substitution for the two right-hand triangular solves, the Cholesky
+                 solve, and their backward-error bounds (plain definitions)
 """
 import ctypes
 import os
